@@ -1,0 +1,102 @@
+"""Pins for the oracle's tensor-product collocation system and full-format solves."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import collocation as col
+from oracle import metrics
+from oracle import spectral as sp
+
+
+def _manufactured(N, d=2):
+    p = workloads.manufactured_2d(N)
+    beta = p.beta if d == 2 else np.linspace(1.0, 0.4, d)
+    ops = col.build_ops(d, N, p.eps, beta)
+    f = col.separable_full(col.manufactured_rhs_factors(ops, p.eps, beta))
+    grids = np.meshgrid(*[op["x"] for op in ops], indexing="ij")
+    exact = np.ones_like(grids[0])
+    for g in grids:
+        exact = exact * col.sin_exp(g)
+    return ops, f, exact
+
+
+def test_dense_and_schur_agree_and_are_backward_stable():
+    ops, f, _ = _manufactured(16)
+    u_dense = col.solve_dense(ops, f)
+    u_schur = col.embed_interior(col.solve_schur(ops, f))
+    assert metrics.rel_frobenius(u_schur, u_dense) < 1e-12
+    A = col.assemble_full(ops)
+    b = col.full_rhs(ops, f)
+    for u in (u_dense, u_schur):
+        berr = np.linalg.norm(A @ u.ravel() - b) / (np.linalg.norm(A, 2) * np.linalg.norm(u))
+        assert berr < 1e-14
+
+
+def test_schur_matches_dense_3d_gauss():
+    p = workloads.gauss_problem(3, 9, 2e-2, 3, seed=4, tol=1e-12, rank_cap=9)
+    ops = col.build_ops(3, 9, p.eps, p.beta)
+    f = col.separable_full(col.gauss_rhs_factors(ops, p.gauss.amp, p.gauss.centre, p.gauss.width))
+    u_dense = col.solve_dense(ops, f)
+    u_schur = col.embed_interior(col.solve_schur(ops, f))
+    assert metrics.rel_frobenius(u_schur, u_dense) < 1e-12
+
+
+def test_apply_interior_equals_assembled_rows():
+    ops, _, _ = _manufactured(7, d=3)
+    rng = np.random.default_rng(0)
+    u = rng.standard_normal((5, 5, 5))
+    A = col.assemble_full(ops)
+    full_u = np.pad(u, 1)
+    lhs = (A @ full_u.ravel()).reshape(7, 7, 7)[1:-1, 1:-1, 1:-1]
+    np.testing.assert_allclose(col.apply_interior(ops, u), lhs, atol=1e-11 * np.abs(lhs).max())
+
+
+def test_manufactured_exponential_convergence():
+    errs = {}
+    for N in (8, 12, 16, 20):
+        ops, f, exact = _manufactured(N)
+        errs[N] = metrics.rel_frobenius(col.solve_dense(ops, f), exact)
+    assert errs[8] > 1e-4 and errs[12] < 1e-5 and errs[16] < 1e-8 and errs[20] < 1e-12
+    assert errs[12] / errs[8] < 1e-2 and errs[16] / errs[12] < 1e-2
+
+
+def test_one_dimension_reduces_to_1d_solver():
+    ops = col.build_ops(1, 12, 1e-3, [1.0])
+    f = np.ones(10)
+    u = col.solve_dense(ops, f)
+    r = sp.solve_1d(12, 1e-3, 1.0, lambda t: np.ones_like(t))
+    np.testing.assert_allclose(u, r["u"], atol=1e-12)
+
+
+def _separable_boundary_layer(d, N, eps, beta, scheme):
+    """u = prod_l phi_l(x_l), phi_l the 1D closed form for (eps, beta_l):
+    -eps Lap u + beta.grad u = sum_l prod_{k != l} phi_k(x_k), u = 0 on the boundary."""
+    ops = col.build_ops(d, N, eps, beta, scheme)
+    terms = []
+    for l in range(d):
+        terms.append([np.ones_like(ops[k]["theta"]) if k == l else
+                      sp.closed_form_1d(ops[k]["theta"], eps, beta[k]) for k in range(d)])
+    f = col.separable_full(terms)
+    grids = np.meshgrid(*[op["x"] for op in ops], indexing="ij")
+    exact = np.ones_like(grids[0])
+    for k, g in enumerate(grids):
+        exact = exact * sp.closed_form_1d(g, eps, beta[k])
+    return ops, f, exact
+
+
+def test_separable_closed_form_is_reproduced_diffusive():
+    ops, f, exact = _separable_boundary_layer(3, 18, 0.5, [1.0, 0.5, 0.8], sp.SCHEME_SC)
+    assert metrics.rel_frobenius(col.embed_interior(col.solve_schur(ops, f)), exact) < 1e-11
+
+
+def test_superconsistent_has_no_oscillation_in_2d_transport_regime():
+    beta = [1.0, 0.6]
+    eps, N = 1e-4, 17
+    ops, f, exact = _separable_boundary_layer(2, N, eps, beta, sp.SCHEME_SC)
+    u_sc = col.embed_interior(col.solve_schur(ops, f))
+    fine = np.linspace(-1, 1, 2001)
+    expected = metrics.sign_changes(sp.closed_form_1d(fine, eps, beta[0]))
+    assert not metrics.is_oscillatory(u_sc, expected)
+    ops_p, f_p, _ = _separable_boundary_layer(2, N, eps, beta, sp.SCHEME_PLAIN)
+    u_plain = col.embed_interior(col.solve_schur(ops_p, f_p))
+    assert metrics.is_oscillatory(u_plain, expected)
