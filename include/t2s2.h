@@ -1,0 +1,200 @@
+/*
+ * t2s2.h -- C ABI of libt2s2, the MI355X (gfx950) tensor-train solver for the
+ * superconsistent spectral collocation system of steady advection-diffusion
+ * (T^2S^2).
+ *
+ * Problem (paper: Eq. advection-diffusion with Eq. pblm:time:B):
+ *     -eps Lap u + beta . grad u = f   in [-1, 1]^d,   u = 0 on the boundary,
+ * with constant eps > 0 and constant beta in R^d.
+ *
+ * Discretisation (paper: Overview (i)-(iii), Fig. 3):
+ *   - N_l nodes per dimension, polynomial degree n_l = N_l - 1; representation
+ *     grid = Gauss-Lobatto-Legendre (GLL) nodes (+-1 and the zeros of P_n');
+ *   - collocation grid per dimension = superconsistent nodes (scheme SC) or
+ *     the interior GLL nodes (scheme PLAIN).  The paper does not print the
+ *     superconsistent node formula; this library reads it as: theta_i is the
+ *     zero of eps P_n'(x) - beta_l P_n(x) inside the i-th gap (z_i, z_{i+1})
+ *     of the zeros z_1 < ... < z_n of P_n (i = 1 .. n-1).  beta_l = 0 gives
+ *     the interior GLL nodes;
+ *   - interior system  L u = f,  L = sum_l E_1 (x) .. (x) M_l (x) .. (x) E_d,
+ *     E_l[j,i] = Lagrange basis i of the GLL grid at theta_j, M_l =
+ *     -eps D2_l + beta_l D1_l (first/second derivatives of that basis), all
+ *     restricted to interior columns (zero Dirichlet data).  m_l = N_l - 2
+ *     unknowns per dimension.
+ *
+ * Tensor trains (paper: Methods, Eq. TT-format:elementwise and
+ * Eq. tt-matrix-format): core l of a TT vector is a C-contiguous FP64 array
+ * [r_{l-1}][n_l][r_l] in device memory, r_0 = r_d = 1; the full vector is in
+ * C order (index 1 slowest).  TT-matrix cores are [R_{l-1}][n_l (row)][n_l
+ * (column)][R_l].  The operator L is held as a rank-2 TT-matrix: first core
+ * [M_1 E_1], middle cores [[E 0],[M E]], last core [E_d; M_d].
+ *
+ * Conventions for every entry point:
+ *   - return value is a status code (T2S2_OK on success);
+ *   - a failing call leaves a message readable by t2s2_last_error()
+ *     (thread-local, valid until the next failing call on that thread);
+ *   - "stream" is a hipStream_t passed as void* (NULL = default stream);
+ *     device work is enqueued on it; calls that return host scalars
+ *     synchronise that stream;
+ *   - the caller allocates and owns every input and output buffer (device
+ *     buffers for TT cores, host buffers for arrays documented as host);
+ *     the library owns only the scratch memory behind a t2s2_problem,
+ *     allocated on demand and released by t2s2_problem_destroy;
+ *   - calls that share one t2s2_problem must not run concurrently.
+ */
+#ifndef T2S2_H
+#define T2S2_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define T2S2_OK 0
+#define T2S2_EINVAL 1      /* bad argument: sizes, ranks, non-finite data  */
+#define T2S2_ENOMEM 2      /* device allocation failed                     */
+#define T2S2_ENOTCONV 3    /* solve stopped at max_sweeps above target     */
+#define T2S2_EHIP 4        /* HIP runtime error (text in t2s2_last_error)  */
+
+#define T2S2_SCHEME_PLAIN 0
+#define T2S2_SCHEME_SC 1
+
+#define T2S2_MAX_DIM 16
+#define T2S2_MAX_HISTORY 128
+
+typedef struct t2s2_problem t2s2_problem;
+
+/* TT vector.  n, ranks, cores are host arrays of length d, d+1, d.
+ * cores[l] is a device pointer to at least ranks[l]*n[l]*ranks[l+1] doubles
+ * (outputs: to the capacity documented by the call).  Outputs overwrite
+ * ranks[] with the ranks actually produced. */
+typedef struct {
+  int d;
+  const int* n;
+  int* ranks;
+  double** cores;
+} t2s2_tt;
+
+/* TT-matrix (square modes).  ranks has d+1 entries; cores[l] is a device
+ * pointer to ranks[l]*n[l]*n[l]*ranks[l+1] doubles. */
+typedef struct {
+  int d;
+  const int* n;
+  const int* ranks;
+  double* const* cores;
+} t2s2_ttm;
+
+/* Solver options (alternating sweeps with residual enrichment; the paper's
+ * "swaps", Results: Superconsistent Stabilization, Fig. 6). */
+typedef struct {
+  double tol;          /* relative truncation threshold of the core splits   */
+  double target;       /* stop once ||f - L x||_2 / ||f||_2 <= target (FP64) */
+  int max_sweeps;      /* sweeps (one pass over all cores, alternating)      */
+  int kick;            /* enrichment rank per split                          */
+  int rank_cap;        /* max TT rank of x (<= the problem's rank_cap)       */
+  int init_rank;       /* rank of the seeded random start when x0 is NULL    */
+  unsigned long long seed;
+  int check_every;     /* evaluate the FP64 residual every this many sweeps  */
+  int verbose;         /* 1: print one line per sweep on stderr              */
+} t2s2_options;
+
+/* Per-solve report (host struct filled by t2s2_solve). */
+typedef struct {
+  int status;
+  int sweeps;
+  int max_rank;
+  int ranks[T2S2_MAX_DIM + 1];
+  double residual;                              /* final ||f - Lx||/||f||  */
+  double time_ms;                               /* wall time of the solve   */
+  int history_len;
+  double history_residual[T2S2_MAX_HISTORY];    /* per sweep, -1 if unchecked */
+  double history_local[T2S2_MAX_HISTORY];       /* max local rel. residual  */
+  int history_max_rank[T2S2_MAX_HISTORY];
+  double history_time_ms[T2S2_MAX_HISTORY];
+} t2s2_report;
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* t2s2_last_error(void);
+
+/* ---------------------------------------------------------------- host ---
+ * 1D ingredients (paper: Overview (i)-(ii)).  Host only, no GPU needed.
+ *   N      nodes (degree N-1), 3 <= N <= 257
+ *   eps    > 0; beta any finite value; scheme T2S2_SCHEME_SC or _PLAIN
+ *   gll_out     host, N doubles, ascending GLL nodes
+ *   colloc_out  host, N-2 doubles, ascending collocation nodes
+ * EINVAL on bad sizes or non-finite parameters. */
+int t2s2_nodes(int N, double eps, double beta, int scheme,
+               double* gll_out, double* colloc_out);
+
+/* Lagrange matrices of the GLL basis at the collocation nodes, row-major
+ * (N-2) x N host arrays: E[j,i] = l_i(theta_j), D1 = l_i', D2 = l_i''. */
+int t2s2_matrices_1d(int N, double eps, double beta, int scheme,
+                     double* E, double* D1, double* D2);
+
+/* ------------------------------------------------------------ problem ---
+ * Build the 1D ingredients and the rank-2 TT-matrix operator of the
+ * interior system on the current HIP device.
+ *   d        1 .. T2S2_MAX_DIM;  N  host array of d node counts (3..66)
+ *   eps > 0; beta host array of d finite values; scheme as above
+ *   rank_cap maximum TT rank any solve on this problem may reach (>= 1)
+ * On success *out owns device copies of the operator cores and 1D data.
+ * EINVAL, ENOMEM or EHIP otherwise (*out untouched). */
+int t2s2_problem_create(int d, const int* N, double eps, const double* beta,
+                        int scheme, int rank_cap, t2s2_problem** out);
+int t2s2_problem_destroy(t2s2_problem* p);
+
+/* Device pointers of the operator's TT-matrix cores (owned by p; valid until
+ * destroy).  out->n and out->ranks point into p. */
+int t2s2_problem_operator(const t2s2_problem* p, t2s2_ttm* out);
+
+/* Host copy of the m_l = N_l - 2 collocation nodes of dimension l. */
+int t2s2_problem_colloc(const t2s2_problem* p, int l, double* theta_out);
+
+/* ------------------------------------------------------ building blocks -- */
+
+/* y = A x (paper: Methods, structure-preserving operations): core l of y is
+ * Y[(a,p), i', (b,q)] = sum_i A_l[a, i', i, b] X_l[p, i, q], so y's ranks are
+ * R_l * r_l.  y->cores[l] must hold R_l r_l n_l R_{l+1} r_{l+1} doubles;
+ * y->ranks is written.  Asynchronous on stream. */
+int t2s2_tt_matvec(const t2s2_ttm* A, const t2s2_tt* x, t2s2_tt* y, void* stream);
+
+/* ||x||_2 (Frobenius) via left-to-right QR orthogonalisation of a copy;
+ * uses p's scratch.  Synchronises stream; result in *out (host). */
+int t2s2_tt_norm(t2s2_problem* p, const t2s2_tt* x, double* out, void* stream);
+
+/* ||f - L x||_2 / ||f||_2 with L the problem's operator, computed exactly in
+ * FP64: x and f are concatenated into the TT of f - L x (ranks s + 2 r), which
+ * is left-orthogonalised by QR; the norm is that of the last core.  Never
+ * uses the cancelling Gram expansion.  Synchronises stream. */
+int t2s2_tt_residual_norm(t2s2_problem* p, const t2s2_tt* x, const t2s2_tt* f,
+                          double* out, void* stream);
+
+/* In-place rounding rndg(x) (paper: Methods, rounding paragraph):
+ * right-to-left QR orthogonalisation, then left-to-right truncated SVDs with
+ * delta = tol ||x|| / sqrt(d-1) per split and rank <= rmax, so that
+ * ||x - rndg(x)|| <= tol ||x||.  x->cores must have room for the input
+ * ranks (output ranks never exceed them); x->ranks is updated.
+ * Synchronises stream. */
+int t2s2_tt_round(t2s2_problem* p, t2s2_tt* x, double tol, int rmax, void* stream);
+
+/* ---------------------------------------------------------------- solve ---
+ * Solve L x = f in TT format by alternating sweeps with exact local solves
+ * and residual enrichment (the paper cites AMEn for this step).
+ *   f      TT right-hand side on the collocation grid (device cores)
+ *   x0     optional TT start (NULL: seeded random TT of rank init_rank)
+ *   x_out  output TT; cores[l] must hold rank_cap*N_l*rank_cap doubles
+ *          (first/last: N_l*rank_cap); ranks written
+ *   rep    optional host report
+ * Returns T2S2_OK when the FP64 residual meets opts->target, T2S2_ENOTCONV
+ * (x_out still holds the last iterate) when max_sweeps is reached first. */
+int t2s2_solve(t2s2_problem* p, const t2s2_tt* f, const t2s2_tt* x0,
+               const t2s2_options* opts, t2s2_tt* x_out, t2s2_report* rep,
+               void* stream);
+
+/* Defaults: tol 1e-10, target 1e-8, max_sweeps 40, kick 8, rank_cap = the
+ * problem's, init_rank 2, seed 0, check_every 1, verbose 0. */
+void t2s2_default_options(t2s2_options* opts);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* T2S2_H */

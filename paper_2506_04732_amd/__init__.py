@@ -1,0 +1,230 @@
+"""MI355X-native tensor-train solver for superconsistent spectral collocation (T^2S^2).
+
+Thin Python binding of libt2s2 (C ABI in include/t2s2.h): argument
+marshalling only.  Every step of the solve runs in the library's HIP kernels;
+PyTorch provides device memory and the stream.  There is no CPU fallback:
+without the built library every entry point raises ``LibraryMissing``.
+
+Names follow the C ABI: ``nodes``, ``matrices_1d``, ``Problem`` (create /
+operator / colloc / tt_matvec / tt_norm / tt_residual_norm / tt_round /
+solve).
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+from . import _lib
+from ._lib import (SCHEME_PLAIN, SCHEME_SC, T2S2_ENOTCONV, LibraryMissing, T2S2Error, check, lib)
+
+__all__ = ["nodes", "matrices_1d", "TT", "Problem", "SolveResult", "SCHEME_PLAIN", "SCHEME_SC",
+           "LibraryMissing", "T2S2Error", "lib"]
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def nodes(N: int, eps: float, beta: float, scheme: int = SCHEME_SC):
+    """(GLL nodes (N,), collocation nodes (N-2,)) from the host builder."""
+    x = np.empty(N)
+    th = np.empty(N - 2)
+    check(lib().t2s2_nodes(int(N), float(eps), float(beta), int(scheme), _dptr(x), _dptr(th)))
+    return x, th
+
+
+def matrices_1d(N: int, eps: float, beta: float, scheme: int = SCHEME_SC):
+    """(E, D1, D2), each (N-2) x N: Lagrange basis of the GLL grid at the collocation nodes."""
+    E = np.empty((N - 2, N))
+    D1 = np.empty((N - 2, N))
+    D2 = np.empty((N - 2, N))
+    check(lib().t2s2_matrices_1d(int(N), float(eps), float(beta), int(scheme), _dptr(E), _dptr(D1), _dptr(D2)))
+    return E, D1, D2
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class TT:
+    """TT vector with device cores in caller-owned torch buffers.
+
+    ``bufs[l]`` is a flat float64 CUDA tensor of at least ranks[l]*n[l]*ranks[l+1]
+    elements (its capacity may be larger); ``core(l)`` views the live part.
+    """
+
+    def __init__(self, n: Sequence[int], ranks: Sequence[int], bufs):
+        self.n = [int(v) for v in n]
+        self.ranks = [int(v) for v in ranks]
+        self.bufs = list(bufs)
+        self.d = len(self.n)
+
+    @staticmethod
+    def empty(n: Sequence[int], cap: int, device="cuda"):
+        torch = _torch()
+        d = len(n)
+        caps = [1] + [cap] * (d - 1) + [1]
+        bufs = [torch.zeros(caps[l] * n[l] * caps[l + 1], dtype=torch.float64, device=device) for l in range(d)]
+        return TT(n, [1] * (d + 1), bufs)
+
+    @staticmethod
+    def empty_like_ranks(n: Sequence[int], ranks: Sequence[int], device="cuda"):
+        torch = _torch()
+        bufs = [torch.zeros(ranks[l] * n[l] * ranks[l + 1], dtype=torch.float64, device=device)
+                for l in range(len(n))]
+        return TT(n, ranks, bufs)
+
+    @staticmethod
+    def from_numpy(cores: Sequence[np.ndarray], device="cuda", cap: Optional[int] = None):
+        torch = _torch()
+        n = [c.shape[1] for c in cores]
+        ranks = [cores[0].shape[0]] + [c.shape[2] for c in cores]
+        bufs = []
+        for l, c in enumerate(cores):
+            size = c.size
+            if cap is not None:
+                r0 = 1 if l == 0 else cap
+                r1 = 1 if l == len(cores) - 1 else cap
+                size = max(size, r0 * c.shape[1] * r1)
+            b = torch.zeros(size, dtype=torch.float64, device=device)
+            b[:c.size] = torch.from_numpy(np.ascontiguousarray(c, dtype=np.float64).ravel()).to(device)
+            bufs.append(b)
+        return TT(n, ranks, bufs)
+
+    def core(self, l: int):
+        r0, n, r1 = self.ranks[l], self.n[l], self.ranks[l + 1]
+        return self.bufs[l][: r0 * n * r1].view(r0, n, r1)
+
+    def to_numpy(self) -> List[np.ndarray]:
+        return [self.core(l).detach().cpu().numpy().copy() for l in range(self.d)]
+
+    def _struct(self):
+        self._n_arr = (C.c_int * self.d)(*self.n)
+        self._r_arr = (C.c_int * (self.d + 1))(*self.ranks)
+        self._c_arr = (C.c_void_p * self.d)(*[b.data_ptr() for b in self.bufs])
+        return _lib.TTStruct(self.d, self._n_arr, self._r_arr, self._c_arr)
+
+    def _read_ranks(self):
+        self.ranks = [int(self._r_arr[i]) for i in range(self.d + 1)]
+
+
+def _stream():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+@dataclass
+class SolveResult:
+    x: TT
+    status: int
+    sweeps: int
+    residual: float
+    ranks: List[int]
+    time_ms: float
+    history_residual: List[float] = field(default_factory=list)
+    history_local: List[float] = field(default_factory=list)
+    history_max_rank: List[int] = field(default_factory=list)
+    history_time_ms: List[float] = field(default_factory=list)
+
+    @property
+    def converged(self) -> bool:
+        return self.status == 0
+
+
+class Problem:
+    """-eps Lap u + beta . grad u = f on [-1,1]^d, u = 0 on the boundary (t2s2_problem_create)."""
+
+    def __init__(self, d: int, N, eps: float, beta, scheme: int = SCHEME_SC, rank_cap: int = 64):
+        Ns = [int(N)] * d if np.isscalar(N) else [int(v) for v in N]
+        self.d, self.N, self.eps, self.scheme, self.rank_cap = d, Ns, float(eps), int(scheme), int(rank_cap)
+        self.beta = np.asarray(beta, dtype=np.float64).copy()
+        self.m = [v - 2 for v in Ns]
+        h = C.c_void_p()
+        n_arr = (C.c_int * d)(*Ns)
+        b_arr = self.beta.ctypes.data_as(C.POINTER(C.c_double))
+        check(lib().t2s2_problem_create(d, n_arr, self.eps, b_arr, self.scheme, self.rank_cap, C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().t2s2_problem_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- queries
+    def colloc(self, l: int) -> np.ndarray:
+        th = np.empty(self.m[l])
+        check(lib().t2s2_problem_colloc(self._h, int(l), _dptr(th)))
+        return th
+
+    def operator(self) -> _lib.TTMStruct:
+        s = _lib.TTMStruct()
+        check(lib().t2s2_problem_operator(self._h, C.byref(s)))
+        return s
+
+    def operator_ranks(self) -> List[int]:
+        s = self.operator()
+        return [int(s.ranks[i]) for i in range(self.d + 1)]
+
+    # ---------------------------------------------------------- building blocks
+    def tt_matvec(self, x: TT) -> TT:
+        op = self.operator()
+        R = [int(op.ranks[i]) for i in range(self.d + 1)]
+        y = TT.empty_like_ranks(x.n, [R[i] * x.ranks[i] for i in range(self.d + 1)])
+        xs, ys = x._struct(), y._struct()
+        check(lib().t2s2_tt_matvec(C.byref(op), C.byref(xs), C.byref(ys), _stream()))
+        y._read_ranks()
+        return y
+
+    def tt_norm(self, x: TT) -> float:
+        out = C.c_double()
+        xs = x._struct()
+        check(lib().t2s2_tt_norm(self._h, C.byref(xs), C.byref(out), _stream()))
+        return out.value
+
+    def tt_residual_norm(self, x: TT, f: TT) -> float:
+        out = C.c_double()
+        xs, fs = x._struct(), f._struct()
+        check(lib().t2s2_tt_residual_norm(self._h, C.byref(xs), C.byref(fs), C.byref(out), _stream()))
+        return out.value
+
+    def tt_round(self, x: TT, tol: float, rmax: int = 10 ** 6) -> TT:
+        xs = x._struct()
+        check(lib().t2s2_tt_round(self._h, C.byref(xs), float(tol), int(rmax), _stream()))
+        x._read_ranks()
+        return x
+
+    # ------------------------------------------------------------------ solve
+    def solve(self, f: TT, x0: Optional[TT] = None, *, tol: float = 1e-10, target: float = 1e-8,
+              max_sweeps: int = 40, kick: int = 8, rank_cap: Optional[int] = None, init_rank: int = 2,
+              seed: int = 0, check_every: int = 1, verbose: bool = False, out: Optional[TT] = None) -> SolveResult:
+        cap = int(rank_cap or self.rank_cap)
+        x = out if out is not None else TT.empty(self.m, cap)
+        o = _lib.Options()
+        lib().t2s2_default_options(C.byref(o))
+        o.tol, o.target, o.max_sweeps, o.kick = float(tol), float(target), int(max_sweeps), int(kick)
+        o.rank_cap, o.init_rank, o.seed = cap, int(init_rank), int(seed)
+        o.check_every, o.verbose = int(check_every), int(bool(verbose))
+        rep = _lib.Report()
+        fs, xs = f._struct(), x._struct()
+        x0s = x0._struct() if x0 is not None else None
+        code = lib().t2s2_solve(self._h, C.byref(fs), C.byref(x0s) if x0s is not None else None, C.byref(o),
+                                C.byref(xs), C.byref(rep), _stream())
+        check(code, allow=(T2S2_ENOTCONV,))
+        x._read_ranks()
+        h = rep.history_len
+        return SolveResult(x=x, status=code, sweeps=rep.sweeps, residual=rep.residual,
+                           ranks=list(rep.ranks[: self.d + 1]), time_ms=rep.time_ms,
+                           history_residual=list(rep.history_residual[:h]),
+                           history_local=list(rep.history_local[:h]),
+                           history_max_rank=list(rep.history_max_rank[:h]),
+                           history_time_ms=list(rep.history_time_ms[:h]))

@@ -1,0 +1,96 @@
+"""ctypes declarations of libt2s2 (include/t2s2.h).  Marshalling only."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libt2s2.so")
+
+T2S2_OK, T2S2_EINVAL, T2S2_ENOMEM, T2S2_ENOTCONV, T2S2_EHIP = 0, 1, 2, 3, 4
+SCHEME_PLAIN, SCHEME_SC = 0, 1
+MAX_DIM, MAX_HISTORY = 16, 128
+
+EXPORTED = [
+    "t2s2_last_error", "t2s2_nodes", "t2s2_matrices_1d", "t2s2_problem_create", "t2s2_problem_destroy",
+    "t2s2_problem_operator", "t2s2_problem_colloc", "t2s2_tt_matvec", "t2s2_tt_norm",
+    "t2s2_tt_residual_norm", "t2s2_tt_round", "t2s2_solve", "t2s2_default_options",
+]
+
+
+class TTStruct(C.Structure):
+    _fields_ = [("d", C.c_int), ("n", C.POINTER(C.c_int)), ("ranks", C.POINTER(C.c_int)),
+                ("cores", C.POINTER(C.c_void_p))]
+
+
+class TTMStruct(C.Structure):
+    _fields_ = [("d", C.c_int), ("n", C.POINTER(C.c_int)), ("ranks", C.POINTER(C.c_int)),
+                ("cores", C.POINTER(C.c_void_p))]
+
+
+class Options(C.Structure):
+    _fields_ = [("tol", C.c_double), ("target", C.c_double), ("max_sweeps", C.c_int), ("kick", C.c_int),
+                ("rank_cap", C.c_int), ("init_rank", C.c_int), ("seed", C.c_ulonglong),
+                ("check_every", C.c_int), ("verbose", C.c_int)]
+
+
+class Report(C.Structure):
+    _fields_ = [("status", C.c_int), ("sweeps", C.c_int), ("max_rank", C.c_int),
+                ("ranks", C.c_int * (MAX_DIM + 1)), ("residual", C.c_double), ("time_ms", C.c_double),
+                ("history_len", C.c_int), ("history_residual", C.c_double * MAX_HISTORY),
+                ("history_local", C.c_double * MAX_HISTORY), ("history_max_rank", C.c_int * MAX_HISTORY),
+                ("history_time_ms", C.c_double * MAX_HISTORY)]
+
+
+class LibraryMissing(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libt2s2.so from the package directory; fail loudly if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise LibraryMissing(f"{LIB_PATH} is missing: run paper_2506_04732_amd.build.build() first")
+    # torch's HIP runtime must be the one in the process: libt2s2 resolves
+    # libamdhip64.so.7 by soname, so loading torch first makes both share it
+    import torch  # noqa: F401
+    L = C.CDLL(LIB_PATH)
+    dp, ip, vp = C.POINTER(C.c_double), C.POINTER(C.c_int), C.c_void_p
+    L.t2s2_last_error.restype = C.c_char_p
+    L.t2s2_last_error.argtypes = []
+    L.t2s2_nodes.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int, dp, dp]
+    L.t2s2_matrices_1d.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int, dp, dp, dp]
+    L.t2s2_problem_create.argtypes = [C.c_int, ip, C.c_double, dp, C.c_int, C.c_int, C.POINTER(vp)]
+    L.t2s2_problem_destroy.argtypes = [vp]
+    L.t2s2_problem_operator.argtypes = [vp, C.POINTER(TTMStruct)]
+    L.t2s2_problem_colloc.argtypes = [vp, C.c_int, dp]
+    L.t2s2_tt_matvec.argtypes = [C.POINTER(TTMStruct), C.POINTER(TTStruct), C.POINTER(TTStruct), vp]
+    L.t2s2_tt_norm.argtypes = [vp, C.POINTER(TTStruct), dp, vp]
+    L.t2s2_tt_residual_norm.argtypes = [vp, C.POINTER(TTStruct), C.POINTER(TTStruct), dp, vp]
+    L.t2s2_tt_round.argtypes = [vp, C.POINTER(TTStruct), C.c_double, C.c_int, vp]
+    L.t2s2_solve.argtypes = [vp, C.POINTER(TTStruct), C.POINTER(TTStruct), C.POINTER(Options),
+                             C.POINTER(TTStruct), C.POINTER(Report), vp]
+    L.t2s2_default_options.argtypes = [C.POINTER(Options)]
+    L.t2s2_default_options.restype = None
+    for name in EXPORTED:
+        if name not in ("t2s2_last_error", "t2s2_default_options"):
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+class T2S2Error(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libt2s2 error {code}: {msg}")
+        self.code = code
+
+
+def check(code: int, allow=()) -> int:
+    if code != T2S2_OK and code not in allow:
+        raise T2S2Error(code, lib().t2s2_last_error().decode())
+    return code

@@ -1,0 +1,275 @@
+// C ABI of libt2s2 (declared in include/t2s2.h).  Argument checks, error
+// translation and marshalling only; the work happens in solver.hip.
+#include "../../include/t2s2.h"
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "solver.h"
+#include "spectral_host.h"
+
+struct t2s2_problem {
+  t2s2::Problem* P = nullptr;
+  std::vector<int> n, R;
+  std::vector<double*> cores;
+};
+
+namespace t2s2 {
+static thread_local std::string g_last_error;
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+}  // namespace t2s2
+
+namespace {
+
+template <class F>
+int guarded(F&& f) {
+  try {
+    t2s2::set_last_error("");
+    return f();
+  } catch (const t2s2::Error& e) {
+    t2s2::set_last_error(e.what());
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    t2s2::set_last_error("host allocation failed");
+    return T2S2_ENOMEM;
+  } catch (const std::exception& e) {
+    t2s2::set_last_error(e.what());
+    return T2S2_EINVAL;
+  }
+}
+
+t2s2::DTT to_dtt(const t2s2_tt* t) {
+  T2S2_CHECK(t && t->d >= 1 && t->d <= T2S2_MAX_DIM && t->n && t->ranks && t->cores, "invalid TT descriptor");
+  t2s2::DTT x;
+  x.d = t->d;
+  x.n.assign(t->n, t->n + t->d);
+  x.r.assign(t->ranks, t->ranks + t->d + 1);
+  x.c.assign(t->cores, t->cores + t->d);
+  T2S2_CHECK(x.r[0] == 1 && x.r[x.d] == 1, "TT boundary ranks must be 1");
+  for (int l = 0; l < x.d; ++l) {
+    T2S2_CHECK(x.n[l] >= 1 && x.r[l + 1] >= 1, "TT sizes and ranks must be positive");
+    T2S2_CHECK(x.c[l] != nullptr, "TT core pointer is NULL");
+  }
+  return x;
+}
+
+t2s2::Ctx ctx_for(t2s2_problem* p, void* stream) {
+  t2s2::Ctx c;
+  c.s = static_cast<hipStream_t>(stream);
+  c.sc = &p->P->sc;
+  return c;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* t2s2_last_error(void) { return t2s2::g_last_error.c_str(); }
+
+int t2s2_nodes(int N, double eps, double beta, int scheme, double* gll_out, double* colloc_out) {
+  return guarded([&] {
+    T2S2_CHECK(N >= 3 && N <= 257, "N must be in [3, 257]");
+    T2S2_CHECK(std::isfinite(eps) && eps > 0.0 && std::isfinite(beta), "eps must be > 0, beta finite");
+    T2S2_CHECK(scheme == 0 || scheme == 1, "scheme must be 0 or 1");
+    T2S2_CHECK(gll_out && colloc_out, "output pointers must not be NULL");
+    const std::vector<double> x = t2s2::gll_nodes(N - 1);
+    const std::vector<double> th = t2s2::colloc_nodes(N - 1, eps, beta, scheme);
+    std::memcpy(gll_out, x.data(), N * sizeof(double));
+    std::memcpy(colloc_out, th.data(), (N - 2) * sizeof(double));
+    return T2S2_OK;
+  });
+}
+
+int t2s2_matrices_1d(int N, double eps, double beta, int scheme, double* E, double* D1, double* D2) {
+  return guarded([&] {
+    T2S2_CHECK(N >= 3 && N <= 257, "N must be in [3, 257]");
+    T2S2_CHECK(std::isfinite(eps) && eps > 0.0 && std::isfinite(beta), "eps must be > 0, beta finite");
+    T2S2_CHECK(scheme == 0 || scheme == 1, "scheme must be 0 or 1");
+    T2S2_CHECK(E && D1 && D2, "output pointers must not be NULL");
+    const std::vector<double> x = t2s2::gll_nodes(N - 1);
+    const std::vector<double> th = t2s2::colloc_nodes(N - 1, eps, beta, scheme);
+    t2s2::lagrange_eval(x.data(), N, th.data(), N - 2, E, D1, D2);
+    return T2S2_OK;
+  });
+}
+
+int t2s2_problem_create(int d, const int* N, double eps, const double* beta, int scheme, int rank_cap,
+                        t2s2_problem** out) {
+  return guarded([&] {
+    T2S2_CHECK(out && N && beta, "NULL argument");
+    T2S2_CHECK(d >= 1 && d <= T2S2_MAX_DIM, "d must be in [1, 16]");
+    t2s2::Problem* P = t2s2::problem_create(d, N, eps, beta, scheme, rank_cap);
+    t2s2_problem* h = new t2s2_problem();
+    h->P = P;
+    h->n = P->m;
+    h->R = P->opL.R;
+    h->cores = P->opL.c;
+    *out = h;
+    return T2S2_OK;
+  });
+}
+
+int t2s2_problem_destroy(t2s2_problem* p) {
+  return guarded([&] {
+    if (!p) return T2S2_OK;
+    delete p->P;
+    delete p;
+    return T2S2_OK;
+  });
+}
+
+int t2s2_problem_operator(const t2s2_problem* p, t2s2_ttm* out) {
+  return guarded([&] {
+    T2S2_CHECK(p && out, "NULL argument");
+    out->d = p->P->d;
+    out->n = p->n.data();
+    out->ranks = p->R.data();
+    out->cores = p->cores.data();
+    return T2S2_OK;
+  });
+}
+
+int t2s2_problem_colloc(const t2s2_problem* p, int l, double* theta_out) {
+  return guarded([&] {
+    T2S2_CHECK(p && theta_out, "NULL argument");
+    T2S2_CHECK(l >= 0 && l < p->P->d, "dimension index out of range");
+    const auto& th = p->P->theta[l];
+    std::memcpy(theta_out, th.data(), th.size() * sizeof(double));
+    return T2S2_OK;
+  });
+}
+
+int t2s2_tt_matvec(const t2s2_ttm* A, const t2s2_tt* x, t2s2_tt* y, void* stream) {
+  return guarded([&] {
+    T2S2_CHECK(A && A->cores && A->ranks && A->n, "invalid TT-matrix descriptor");
+    t2s2::DTT xd = to_dtt(x);
+    T2S2_CHECK(y && y->cores && y->ranks && y->d == xd.d, "invalid output TT descriptor");
+    T2S2_CHECK(A->d == xd.d, "operator and vector dimensions differ");
+    t2s2::DTTM Ad;
+    Ad.d = A->d;
+    Ad.n.assign(A->n, A->n + A->d);
+    Ad.R.assign(A->ranks, A->ranks + A->d + 1);
+    Ad.c.assign(A->cores, A->cores + A->d);
+    T2S2_CHECK(Ad.R[0] == 1 && Ad.R[Ad.d] == 1, "operator boundary ranks must be 1");
+    for (int l = 0; l < xd.d; ++l) T2S2_CHECK(Ad.n[l] == xd.n[l] && Ad.n[l] <= 64, "mode sizes must match, <= 64");
+    t2s2::DTT yd;
+    yd.c.assign(y->cores, y->cores + y->d);
+    t2s2::Ctx c;
+    c.s = static_cast<hipStream_t>(stream);
+    t2s2::tt_matvec(c, Ad, xd, yd);
+    for (int l = 0; l <= xd.d; ++l) y->ranks[l] = yd.r[l];
+    return T2S2_OK;
+  });
+}
+
+int t2s2_tt_norm(t2s2_problem* p, const t2s2_tt* x, double* out, void* stream) {
+  return guarded([&] {
+    T2S2_CHECK(p && out, "NULL argument");
+    t2s2::DTT xd = to_dtt(x);
+    t2s2::Ctx c = ctx_for(p, stream);
+    *out = t2s2::tt_norm(c, xd);
+    return T2S2_OK;
+  });
+}
+
+int t2s2_tt_residual_norm(t2s2_problem* p, const t2s2_tt* x, const t2s2_tt* f, double* out, void* stream) {
+  return guarded([&] {
+    T2S2_CHECK(p && out, "NULL argument");
+    t2s2::DTT xd = to_dtt(x), fd = to_dtt(f);
+    T2S2_CHECK(xd.d == p->P->d && fd.d == p->P->d, "dimension mismatch with the problem");
+    for (int l = 0; l < xd.d; ++l)
+      T2S2_CHECK(xd.n[l] == p->P->m[l] && fd.n[l] == p->P->m[l], "mode sizes must be N_l - 2");
+    t2s2::Ctx c = ctx_for(p, stream);
+    *out = t2s2::tt_residual_norm(*p->P, c, xd, fd);
+    return T2S2_OK;
+  });
+}
+
+int t2s2_tt_round(t2s2_problem* p, t2s2_tt* x, double tol, int rmax, void* stream) {
+  return guarded([&] {
+    T2S2_CHECK(p, "NULL argument");
+    T2S2_CHECK(std::isfinite(tol) && tol >= 0.0 && rmax >= 1, "tol must be >= 0 and rmax >= 1");
+    t2s2::DTT xd = to_dtt(x);
+    t2s2::Ctx c = ctx_for(p, stream);
+    t2s2::tt_round(c, xd, tol, rmax);
+    c.sync();
+    for (int l = 0; l <= xd.d; ++l) x->ranks[l] = xd.r[l];
+    return T2S2_OK;
+  });
+}
+
+void t2s2_default_options(t2s2_options* o) {
+  if (!o) return;
+  o->tol = 1e-10;
+  o->target = 1e-8;
+  o->max_sweeps = 40;
+  o->kick = 8;
+  o->rank_cap = 0;
+  o->init_rank = 2;
+  o->seed = 0;
+  o->check_every = 1;
+  o->verbose = 0;
+}
+
+int t2s2_solve(t2s2_problem* p, const t2s2_tt* f, const t2s2_tt* x0, const t2s2_options* opts, t2s2_tt* x_out,
+               t2s2_report* rep, void* stream) {
+  return guarded([&] {
+    T2S2_CHECK(p && f && x_out, "NULL argument");
+    t2s2::DTT fd = to_dtt(f);
+    T2S2_CHECK(fd.d == p->P->d, "f has the wrong dimension");
+    for (int l = 0; l < fd.d; ++l) T2S2_CHECK(fd.n[l] == p->P->m[l], "f mode sizes must be N_l - 2");
+    T2S2_CHECK(x_out->d == fd.d && x_out->cores && x_out->ranks, "invalid x_out descriptor");
+    t2s2::SolveOptions o;
+    if (opts) {
+      T2S2_CHECK(std::isfinite(opts->tol) && opts->tol > 0.0 && std::isfinite(opts->target), "bad tolerances");
+      T2S2_CHECK(opts->max_sweeps >= 1 && opts->kick >= 0 && opts->init_rank >= 1, "bad sweep/kick/rank options");
+      o.tol = opts->tol;
+      o.target = opts->target;
+      o.max_sweeps = opts->max_sweeps;
+      o.kick = opts->kick;
+      o.rank_cap = opts->rank_cap;
+      o.init_rank = opts->init_rank;
+      o.seed = opts->seed;
+      o.check_every = opts->check_every;
+      o.verbose = opts->verbose;
+    }
+    t2s2::DTT xd;
+    xd.d = fd.d;
+    xd.n = fd.n;
+    xd.r.assign(fd.d + 1, 1);
+    xd.c.assign(x_out->cores, x_out->cores + fd.d);
+    t2s2::DTT x0d;
+    const t2s2::DTT* x0p = nullptr;
+    if (x0) {
+      x0d = to_dtt(x0);
+      x0p = &x0d;
+    }
+    t2s2::Ctx c = ctx_for(p, stream);
+    t2s2::SolveReport r;
+    const int st = t2s2::solve(*p->P, c, fd, x0p, o, xd, r);
+    for (int l = 0; l <= fd.d; ++l) x_out->ranks[l] = xd.r[l];
+    if (rep) {
+      std::memset(rep, 0, sizeof(*rep));
+      rep->status = st == 0 ? T2S2_OK : T2S2_ENOTCONV;
+      rep->sweeps = r.sweeps;
+      rep->max_rank = r.max_rank;
+      for (int l = 0; l <= fd.d && l <= T2S2_MAX_DIM; ++l) rep->ranks[l] = r.ranks[l];
+      rep->residual = r.residual;
+      rep->time_ms = r.time_ms;
+      const int h = std::min<int>((int)r.hist_res.size(), T2S2_MAX_HISTORY);
+      rep->history_len = h;
+      for (int i = 0; i < h; ++i) {
+        rep->history_residual[i] = r.hist_res[i];
+        rep->history_local[i] = r.hist_local[i];
+        rep->history_max_rank[i] = r.hist_rank[i];
+        rep->history_time_ms[i] = r.hist_time[i];
+      }
+    }
+    if (st != 0) t2s2::set_last_error("tolerance not met within max_sweeps");
+    return st == 0 ? T2S2_OK : T2S2_ENOTCONV;
+  });
+}
+
+}  // extern "C"

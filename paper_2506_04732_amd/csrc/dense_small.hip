@@ -1,0 +1,609 @@
+// Single-workgroup dense kernels for the small (r x r, r <= 512) matrices of
+// the TT solver: Cholesky with column skipping, triangular inverses,
+// one-sided Jacobi SVD, Hessenberg reduction, complex Schur form by shifted
+// QR, and eigenvectors of triangular matrices.
+//
+// These matrices (interfaces, R factors, Gram matrices) are a few hundred KB
+// at most; one workgroup of 1024 threads works on a copy staged in LDS when
+// it fits (160 KB per workgroup on gfx950) and on global (L2-resident)
+// memory otherwise.  Every kernel loops a bounded number of times and every
+// barrier is reached by all threads of the workgroup.
+#include "dense_small.h"
+
+#include <cfloat>
+
+namespace t2s2 {
+
+namespace {
+
+constexpr int kNT = 1024;          // threads of the single workgroup
+constexpr long kLdsDoubles = 20000;  // LDS budget of these kernels (160000 B)
+
+__device__ inline double block_max(double v, double* red) {
+  // all threads participate; red holds kNT/64 doubles
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double r = red[0];
+  for (int i = 1; i < (int)(blockDim.x / 64); ++i) r = fmax(r, red[i]);
+  __syncthreads();
+  return r;
+}
+
+// ------------------------------------------------------------ Cholesky
+// Upper Cholesky G = R^T R of a symmetric positive semi-definite n x n
+// matrix (row-major, ld n), skipping every column whose pivot, after the
+// updates of the previous columns, is <= tau * max_i G[i][i]: such a column
+// gets a zero row in R and mask 0.  count[0] = number of kept columns.
+__global__ void __launch_bounds__(kNT) chol_skip_kernel(int n, const double* __restrict__ G, double* R,
+                                                       int* __restrict__ mask, int* __restrict__ count,
+                                                       double tau) {
+  extern __shared__ double lds[];
+  __shared__ double red[kNT / 64];
+  __shared__ double s_piv;
+  __shared__ int s_keep, s_count;
+  const bool in_lds = (long)n * n <= kLdsDoubles;
+  double* W = in_lds ? lds : R;
+  const long nn = (long)n * n;
+  for (long e = threadIdx.x; e < nn; e += blockDim.x) W[e] = G[e];
+  __syncthreads();
+  double dm = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dm = fmax(dm, W[(long)i * n + i]);
+  const double gmax = block_max(dm, red);
+  if (threadIdx.x == 0) s_count = 0;
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (threadIdx.x == 0) {
+      const double d = W[(long)k * n + k];
+      const int keep = (d > tau * gmax) && (d > 0.0) && gmax > 0.0;
+      s_keep = keep;
+      s_piv = keep ? sqrt(d) : 0.0;
+      mask[k] = keep;
+      s_count += keep;
+    }
+    __syncthreads();
+    const int keep = s_keep;
+    const double piv = s_piv;
+    if (!keep) {
+      for (int j = k + threadIdx.x; j < n; j += blockDim.x) W[(long)k * n + j] = 0.0;
+      __syncthreads();
+      continue;
+    }
+    const double inv = 1.0 / piv;
+    for (int j = k + 1 + threadIdx.x; j < n; j += blockDim.x) W[(long)k * n + j] *= inv;
+    if (threadIdx.x == 0) W[(long)k * n + k] = piv;
+    __syncthreads();
+    const int t = n - k - 1;
+    const long tt = (long)t * t;
+    for (long e = threadIdx.x; e < tt; e += blockDim.x) {
+      const int i = k + 1 + (int)(e / t), j = k + 1 + (int)(e % t);
+      if (i <= j) W[(long)i * n + j] -= W[(long)k * n + i] * W[(long)k * n + j];
+    }
+    __syncthreads();
+  }
+  for (long e = threadIdx.x; e < nn; e += blockDim.x) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    R[e] = (j < i) ? 0.0 : W[e];
+  }
+  if (threadIdx.x == 0) count[0] = s_count;
+}
+
+// ------------------------------------------------- triangular inverses
+// Rinv = R^{-1} for a nonsingular upper-triangular n x n R (row-major), by
+// rows from the bottom: Rinv[i][j] = -(sum_{t=i+1..j} R[i][t] Rinv[t][j]) / R[i][i].
+template <class T>
+struct TriOps;
+template <>
+struct TriOps<double> {
+  __device__ static double zero() { return 0.0; }
+  __device__ static double one() { return 1.0; }
+  __device__ static double fma(double a, double b, double c) { return ::fma(a, b, c); }
+  __device__ static double div(double a, double b) { return a / b; }
+  __device__ static double neg(double a) { return -a; }
+};
+template <>
+struct TriOps<double2> {
+  __device__ static double2 zero() { return make_double2(0.0, 0.0); }
+  __device__ static double2 one() { return make_double2(1.0, 0.0); }
+  __device__ static double2 fma(double2 a, double2 b, double2 c) { return cadd(cmul(a, b), c); }
+  __device__ static double2 div(double2 a, double2 b) { return cdiv(a, b); }
+  __device__ static double2 neg(double2 a) { return make_double2(-a.x, -a.y); }
+};
+
+template <class T>
+__global__ void __launch_bounds__(kNT) trtri_upper_kernel(int n, const T* __restrict__ R, T* __restrict__ Rinv) {
+  using O = TriOps<T>;
+  const long nn = (long)n * n;
+  for (long e = threadIdx.x; e < nn; e += blockDim.x) Rinv[e] = O::zero();
+  __syncthreads();
+  for (int i = n - 1; i >= 0; --i) {
+    const T rii = R[(long)i * n + i];
+    for (int j = i + threadIdx.x; j < n; j += blockDim.x) {
+      if (j == i) {
+        Rinv[(long)i * n + i] = O::div(O::one(), rii);
+      } else {
+        T s = O::zero();
+        for (int t = i + 1; t <= j; ++t) s = O::fma(R[(long)i * n + t], Rinv[(long)t * n + j], s);
+        Rinv[(long)i * n + j] = O::div(O::neg(s), rii);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------ one-sided Jacobi SVD
+// B (k x c, row-major) = U * Wt with U orthogonal k x k and the rows of Wt
+// mutually orthogonal: rotations from the left orthogonalise the rows of B
+// (Hestenes' method applied to B^T), the rotations accumulate in U.  Rows are
+// then sorted by decreasing norm: sigma[i] = ||Wt[i, :]||, so B = U diag(sigma) V^T
+// with V^T the normalised rows of Wt.  Pairs are visited in round-robin
+// tournament order, k/2 disjoint pairs per round, one wavefront per pair.
+__global__ void __launch_bounds__(kNT) jacobi_rows_kernel(int k, int c, double* __restrict__ B,
+                                                          double* __restrict__ JT, double* __restrict__ U,
+                                                          double* __restrict__ Wt, double* __restrict__ sigma,
+                                                          int* __restrict__ info, int max_sweeps) {
+  extern __shared__ double lds[];
+  __shared__ int s_rot;
+  const long bsz = (long)k * c, jsz = (long)k * k;
+  const bool b_lds = bsz <= kLdsDoubles;
+  const bool j_lds = b_lds && (bsz + jsz) <= kLdsDoubles;
+  double* Bw = b_lds ? lds : B;
+  double* Jw = j_lds ? lds + bsz : JT;
+  for (long e = threadIdx.x; e < bsz; e += blockDim.x) Bw[e] = B[e];
+  for (long e = threadIdx.x; e < jsz; e += blockDim.x) Jw[e] = ((e / k) == (e % k)) ? 1.0 : 0.0;
+  __syncthreads();
+  const int K = k + (k & 1);  // even number of players (k odd: one bye)
+  const int npairs = K / 2;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, nwaves = blockDim.x / 64;
+  const double tol = 1e-15;
+  int sweep = 0;
+  for (; sweep < max_sweeps; ++sweep) {
+    if (threadIdx.x == 0) s_rot = 0;
+    __syncthreads();
+    for (int round = 0; round < K - 1; ++round) {
+      for (int pi = wave; pi < npairs; pi += nwaves) {
+        // slots pi and K-1-pi; slot 0 is fixed, the others rotate
+        const int s1 = pi, s2 = K - 1 - pi;
+        int p = (s1 == 0) ? 0 : ((s1 - 1 + round) % (K - 1)) + 1;
+        int q = (s2 == 0) ? 0 : ((s2 - 1 + round) % (K - 1)) + 1;
+        if (p >= k || q >= k) continue;
+        if (p > q) { const int t = p; p = q; q = t; }
+        double* bp = Bw + (long)p * c;
+        double* bq = Bw + (long)q * c;
+        double a = 0.0, b = 0.0, g = 0.0;
+        for (int e = lane; e < c; e += 64) {
+          const double x = bp[e], y = bq[e];
+          a = fma(x, x, a);
+          b = fma(y, y, b);
+          g = fma(x, y, g);
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+          a += __shfl_xor(a, off, 64);
+          b += __shfl_xor(b, off, 64);
+          g += __shfl_xor(g, off, 64);
+        }
+        if (g == 0.0 || fabs(g) <= tol * sqrt(a * b)) continue;
+        const double zeta = (b - a) / (2.0 * g);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+        for (int e = lane; e < c; e += 64) {
+          const double x = bp[e], y = bq[e];
+          bp[e] = cs * x - sn * y;
+          bq[e] = sn * x + cs * y;
+        }
+        double* jp = Jw + (long)p * k;
+        double* jq = Jw + (long)q * k;
+        for (int e = lane; e < k; e += 64) {
+          const double x = jp[e], y = jq[e];
+          jp[e] = cs * x - sn * y;
+          jq[e] = sn * x + cs * y;
+        }
+        if (lane == 0) atomicAdd(&s_rot, 1);
+      }
+      __syncthreads();
+    }
+    const int rot = s_rot;
+    __syncthreads();
+    if (rot == 0) break;
+  }
+  // row norms, rank by decreasing norm (ties by index), scatter
+  for (int i = threadIdx.x; i < k; i += blockDim.x) {
+    double s = 0.0;
+    for (int e = 0; e < c; ++e) s = fma(Bw[(long)i * c + e], Bw[(long)i * c + e], s);
+    sigma[i] = sqrt(s);  // temporary, unsorted
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < k; i += blockDim.x) {
+    const double si = sigma[i];
+    int rank = 0;
+    for (int j = 0; j < k; ++j) {
+      const double sj = sigma[j];
+      rank += (sj > si) || (sj == si && j < i);
+    }
+    info[1 + i] = rank;  // scratch: destination of row i
+  }
+  __syncthreads();
+  for (long e = threadIdx.x; e < bsz; e += blockDim.x) {
+    const int i = (int)(e / c), col = (int)(e % c);
+    Wt[(long)info[1 + i] * c + col] = Bw[e];
+  }
+  // U = J: column dest(i) of U is row i of JT
+  for (long e = threadIdx.x; e < jsz; e += blockDim.x) {
+    const int i = (int)(e / k), r = (int)(e % k);
+    U[(long)r * k + info[1 + i]] = Jw[e];
+  }
+  __syncthreads();
+  // sorted sigma
+  for (int i = threadIdx.x; i < k; i += blockDim.x) {
+    double s = 0.0;
+    for (int e = 0; e < c; ++e) s = fma(Wt[(long)i * c + e], Wt[(long)i * c + e], s);
+    sigma[i] = sqrt(s);
+  }
+  if (threadIdx.x == 0) info[0] = sweep;
+}
+
+// ------------------------------------------------- Hessenberg reduction
+// A (n x n, real, row-major) -> H = Q^T A Q upper Hessenberg, by Householder
+// reflectors on columns 0..n-3.  QT receives Q^T.
+__global__ void __launch_bounds__(kNT) hessenberg_kernel(int n, double* __restrict__ A, double* __restrict__ QT,
+                                                         double* __restrict__ work) {
+  extern __shared__ double lds[];
+  __shared__ double red[kNT / 64];
+  __shared__ double s_alpha, s_vnorm2;
+  const long nn = (long)n * n;
+  const bool in_lds = nn + 2L * n <= kLdsDoubles;
+  double* H = in_lds ? lds : A;
+  double* v = in_lds ? lds + nn : work;      // reflector (n)
+  double* w = in_lds ? lds + nn + n : work + n;  // products (n)
+  if (in_lds)
+    for (long e = threadIdx.x; e < nn; e += blockDim.x) H[e] = A[e];
+  for (long e = threadIdx.x; e < nn; e += blockDim.x) QT[e] = ((e / n) == (e % n)) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int k = 0; k < n - 2; ++k) {
+    // x = H[k+1:, k]
+    double s = 0.0;
+    for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) {
+      const double x = H[(long)i * n + k];
+      v[i] = x;
+      s = fma(x, x, s);
+    }
+    // block sum (reuse block_max pattern with sums)
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    __syncthreads();
+    if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double tot = 0.0;
+      for (int i = 0; i < (int)(blockDim.x / 64); ++i) tot += red[i];
+      const double x0 = v[k + 1];
+      const double tail = tot - x0 * x0;
+      if (tail <= 1e-300 * fmax(1.0, tot)) {
+        s_vnorm2 = 0.0;  // already in Hessenberg form for this column
+      } else {
+        const double alpha = (x0 >= 0.0) ? -sqrt(tot) : sqrt(tot);
+        s_alpha = alpha;
+        v[k + 1] = x0 - alpha;
+        s_vnorm2 = tail + (x0 - alpha) * (x0 - alpha);
+      }
+    }
+    __syncthreads();
+    const double vn2 = s_vnorm2;
+    if (vn2 == 0.0) continue;
+    const double beta = 2.0 / vn2;
+    // left: H[k+1:, :] -= beta v (v^T H[k+1:, :]) ; columns k..n-1 suffice
+    for (int j = k + threadIdx.x; j < n; j += blockDim.x) {
+      double d = 0.0;
+      for (int i = k + 1; i < n; ++i) d = fma(v[i], H[(long)i * n + j], d);
+      w[j] = beta * d;
+    }
+    __syncthreads();
+    {
+      const int rows = n - k - 1, cols = n - k;
+      const long tot = (long)rows * cols;
+      for (long e = threadIdx.x; e < tot; e += blockDim.x) {
+        const int i = k + 1 + (int)(e / cols), j = k + (int)(e % cols);
+        H[(long)i * n + j] -= v[i] * w[j];
+      }
+    }
+    __syncthreads();
+    // right: H[:, k+1:] -= beta (H[:, k+1:] v) v^T
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      double d = 0.0;
+      for (int j = k + 1; j < n; ++j) d = fma(H[(long)i * n + j], v[j], d);
+      w[i] = beta * d;
+    }
+    __syncthreads();
+    {
+      const int cols = n - k - 1;
+      const long tot = (long)n * cols;
+      for (long e = threadIdx.x; e < tot; e += blockDim.x) {
+        const int i = (int)(e / cols), j = k + 1 + (int)(e % cols);
+        H[(long)i * n + j] -= w[i] * v[j];
+      }
+    }
+    __syncthreads();
+    // QT = P QT (P symmetric): rows k+1.. of QT: QT[k+1:, :] -= beta v (v^T QT[k+1:, :])
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+      double d = 0.0;
+      for (int i = k + 1; i < n; ++i) d = fma(v[i], QT[(long)i * n + j], d);
+      w[j] = beta * d;
+    }
+    __syncthreads();
+    {
+      const int rows = n - k - 1;
+      const long tot = (long)rows * n;
+      for (long e = threadIdx.x; e < tot; e += blockDim.x) {
+        const int i = k + 1 + (int)(e / n), j = (int)(e % n);
+        QT[(long)i * n + j] -= v[i] * w[j];
+      }
+    }
+    __syncthreads();
+    // exact zeros below the subdiagonal of column k
+    for (int i = k + 2 + threadIdx.x; i < n; i += blockDim.x) H[(long)i * n + k] = 0.0;
+    __syncthreads();
+  }
+  if (in_lds)
+    for (long e = threadIdx.x; e < nn; e += blockDim.x) A[e] = H[e];
+}
+
+// --------------------------------------------------- complex Schur form
+// H (n x n real upper Hessenberg) = Z T Z^H with T complex upper triangular,
+// by implicitly shifted single-shift QR (Wilkinson shifts, exceptional shifts
+// every 10 stagnant iterations, deflation on negligible subdiagonals).
+// ZT holds Z^T on input (the Hessenberg Q^T, so that the result is the Schur
+// basis of the original matrix) and is updated by every rotation; rows of ZT
+// are columns of Z, so each update is a contiguous row operation.
+// Storage of H during the iteration: LDS in packed form (row i keeps columns
+// max(0, i-2) .. n-1; the bulge lives two below the diagonal) when it fits,
+// else the full complex matrix Hw in global memory.
+struct HView {
+  double2* base;
+  int n;
+  bool packed;
+  __device__ long off(int i, int j) const {
+    if (!packed) return (long)i * n + j;
+    // rows 0, 1 start at column 0; row i >= 2 starts at column i-2
+    long o;
+    if (i <= 1) {
+      o = (long)i * n;
+    } else {
+      // 2n for rows 0,1 plus sum_{t=2}^{i-1} (n - t + 2)
+      const long m = i - 2;  // rows 2..i-1
+      o = 2L * n + m * (n + 2) - (m * (m + 3)) / 2;
+      o -= 0;
+      return o + (j - (i - 2));
+    }
+    return o + j;
+  }
+  __device__ double2& at(int i, int j) const { return base[off(i, j)]; }
+};
+
+__device__ inline long packed_size(int n) {
+  // 2n + sum_{t=2}^{n-1} (n - t + 2)
+  const long m = n - 2;
+  return 2L * n + (m > 0 ? m * (n + 2) - (m * (m + 3)) / 2 : 0);
+}
+
+__global__ void __launch_bounds__(kNT) schur_qr_kernel(int n, const double* __restrict__ Hr,
+                                                       double2* __restrict__ Hw, double2* __restrict__ ZT,
+                                                       double2* __restrict__ T, int* __restrict__ info,
+                                                       int max_iter_total) {
+  extern __shared__ double lds[];
+  __shared__ double2 s_cs[2];
+  __shared__ int s_l, s_hi, s_iter, s_done;
+  __shared__ double2 s_mu;
+  const long psz = packed_size(n);
+  const bool packed = psz * 2 <= kLdsDoubles;
+  HView H{packed ? reinterpret_cast<double2*>(lds) : Hw, n, packed};
+  // load real Hessenberg into complex storage
+  for (long e = threadIdx.x; e < (long)n * n; e += blockDim.x) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    if (j >= i - 2 || !packed) H.at(i, j) = make_double2(j >= i - 1 ? Hr[e] : 0.0, 0.0);
+  }
+  if (threadIdx.x == 0) { s_hi = n - 1; s_iter = 0; s_done = 0; }
+  __syncthreads();
+  const double ulp = DBL_EPSILON;
+  int total = 0;
+  while (true) {
+    // ---- deflation scan and shift (thread 0), broadcast through LDS
+    if (threadIdx.x == 0) {
+      int hi = s_hi;
+      while (hi >= 0) {
+        if (hi == 0) { hi = -1; break; }
+        int l = hi;
+        while (l > 0) {
+          const double2 sub = H.at(l, l - 1);
+          double s = fabs(H.at(l - 1, l - 1).x) + fabs(H.at(l - 1, l - 1).y) + fabs(H.at(l, l).x) + fabs(H.at(l, l).y);
+          if (s == 0.0) s = 1.0;
+          if (fabs(sub.x) + fabs(sub.y) <= ulp * s) {
+            H.at(l, l - 1) = make_double2(0.0, 0.0);
+            break;
+          }
+          --l;
+        }
+        if (l == hi) {  // 1 x 1 block converged
+          --hi;
+          s_iter = 0;
+          continue;
+        }
+        s_l = l;
+        // Wilkinson shift from the trailing 2 x 2 of the active block
+        const double2 a = H.at(hi - 1, hi - 1), b = H.at(hi - 1, hi), c = H.at(hi, hi - 1), d = H.at(hi, hi);
+        double2 mu;
+        if (s_iter > 0 && s_iter % 10 == 0) {
+          // exceptional shift
+          const double e = fabs(c.x) + fabs(c.y);
+          mu = make_double2(d.x + 0.75 * e, d.y);
+        } else {
+          const double2 half = cscale(csub(a, d), 0.5);
+          const double2 disc = csqrt(cadd(cmul(half, half), cmul(b, c)));
+          const double2 m1 = cadd(cscale(cadd(a, d), 0.5), disc);
+          const double2 m2 = csub(cscale(cadd(a, d), 0.5), disc);
+          mu = (cabs2(csub(m1, d)) <= cabs2(csub(m2, d))) ? m1 : m2;
+        }
+        s_mu = mu;
+        break;
+      }
+      s_hi = hi;
+      if (hi < 0) s_done = 1;
+      ++s_iter;
+    }
+    __syncthreads();
+    if (s_done || total >= max_iter_total) break;
+    ++total;
+    const int l = s_l, hi = s_hi;
+    const double2 mu = s_mu;
+    // ---- bulge chase over the active block [l, hi]
+    for (int k = l; k < hi; ++k) {
+      // rotation from (x, y)
+      if (threadIdx.x == 0) {
+        double2 x, y;
+        if (k == l) {
+          x = csub(H.at(l, l), mu);
+          y = H.at(l + 1, l);
+        } else {
+          x = H.at(k, k - 1);
+          y = H.at(k + 1, k - 1);
+        }
+        const double ax = cabs(x), ay = cabs(y);
+        double c;
+        double2 s;
+        if (ay == 0.0) {
+          c = 1.0;
+          s = make_double2(0.0, 0.0);
+        } else if (ax == 0.0) {
+          c = 0.0;
+          s = cscale(cconj(y), 1.0 / ay);
+        } else {
+          const double r = hypot(ax, ay);
+          c = ax / r;
+          // s = (x / |x|) conj(y) / r
+          s = cscale(cmul(x, cconj(y)), 1.0 / (ax * r));
+        }
+        s_cs[0] = make_double2(c, 0.0);
+        s_cs[1] = s;
+      }
+      __syncthreads();
+      const double c = s_cs[0].x;
+      const double2 s = s_cs[1];
+      // rows k, k+1, columns max(k-1, 0) .. n-1
+      const int j0 = (k > 0) ? k - 1 : 0;
+      for (int j = j0 + threadIdx.x; j < n; j += blockDim.x) {
+        const double2 hk = H.at(k, j), hk1 = H.at(k + 1, j);
+        H.at(k, j) = cadd(cscale(hk, c), cmul(s, hk1));
+        H.at(k + 1, j) = csub(cscale(hk1, c), cmul(cconj(s), hk));
+      }
+      __syncthreads();
+      // columns k, k+1, rows 0 .. min(k+2, hi)
+      const int i1 = (k + 2 < hi) ? k + 2 : hi;
+      for (int i = threadIdx.x; i <= i1; i += blockDim.x) {
+        const double2 a = H.at(i, k), b = H.at(i, k + 1);
+        H.at(i, k) = cadd(cscale(a, c), cmul(b, cconj(s)));
+        H.at(i, k + 1) = csub(cscale(b, c), cmul(a, s));
+      }
+      // Z <- Z G^H: columns k, k+1 of Z are rows k, k+1 of ZT
+      for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double2 a = ZT[(long)k * n + i], b = ZT[(long)(k + 1) * n + i];
+        ZT[(long)k * n + i] = cadd(cscale(a, c), cmul(b, cconj(s)));
+        ZT[(long)(k + 1) * n + i] = csub(cscale(b, c), cmul(a, s));
+      }
+      __syncthreads();
+    }
+  }
+  // write T (upper triangle of H)
+  for (long e = threadIdx.x; e < (long)n * n; e += blockDim.x) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    T[e] = (j >= i) ? H.at(i, j) : make_double2(0.0, 0.0);
+  }
+  if (threadIdx.x == 0) info[0] = s_done ? total : -total;
+}
+
+// --------------------------------------- eigenvectors of triangular T
+// T Y = Y diag(T): Y unit upper triangular, column k solves
+// (T[:k,:k] - t_kk I) y = -T[:k, k].  Rows are produced bottom-up for all
+// columns at once.  Denominators below smin = max(ulp |t_kk|, tiny) are
+// replaced by smin (as in standard eigenvector codes).
+__global__ void __launch_bounds__(kNT) trevec_kernel(int n, const double2* __restrict__ T, double2* __restrict__ Y) {
+  const long nn = (long)n * n;
+  for (long e = threadIdx.x; e < nn; e += blockDim.x) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    Y[e] = (i == j) ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  double tnorm = 0.0;
+  for (int i = n - 1; i >= 0; --i) {
+    const double2 tii = T[(long)i * n + i];
+    for (int k = i + 1 + threadIdx.x; k < n; k += blockDim.x) {
+      double2 s = T[(long)i * n + k];  // times y_k = 1
+      for (int t = i + 1; t < k; ++t) s = cadd(s, cmul(T[(long)i * n + t], Y[(long)t * n + k]));
+      const double2 tkk = T[(long)k * n + k];
+      double2 den = csub(tii, tkk);
+      const double smin = fmax(DBL_EPSILON * cabs(tkk), 1e-290);
+      if (cabs(den) < smin) den = make_double2(smin, 0.0);
+      Y[(long)i * n + k] = cdiv(make_double2(-s.x, -s.y), den);
+    }
+    __syncthreads();
+  }
+  (void)tnorm;
+}
+
+}  // namespace
+
+// ============================================================ launchers
+static size_t lds_bytes(long doubles) { return (size_t)std::min<long>(doubles, kLdsDoubles) * sizeof(double); }
+
+void chol_skip(hipStream_t s, int n, const double* G, double* R, int* mask, int* count, double tau) {
+  T2S2_CHECK(n >= 1 && n <= 4096, "chol_skip: bad size");
+  const long need = (long)n * n;
+  hipLaunchKernelGGL(chol_skip_kernel, dim3(1), dim3(kNT), need <= kLdsDoubles ? lds_bytes(need) : 0, s,
+                     n, G, R, mask, count, tau);
+  T2S2_LAUNCH_CHECK();
+}
+
+void trtri_upper(hipStream_t s, int n, const double* R, double* Rinv) {
+  hipLaunchKernelGGL(trtri_upper_kernel<double>, dim3(1), dim3(kNT), 0, s, n, R, Rinv);
+  T2S2_LAUNCH_CHECK();
+}
+
+void trtri_upper(hipStream_t s, int n, const double2* R, double2* Rinv) {
+  hipLaunchKernelGGL(trtri_upper_kernel<double2>, dim3(1), dim3(kNT), 0, s, n, R, Rinv);
+  T2S2_LAUNCH_CHECK();
+}
+
+void jacobi_rows(hipStream_t s, int k, int c, double* B, double* JT, double* U, double* Wt, double* sigma,
+                 int* info, int max_sweeps) {
+  T2S2_CHECK(k >= 1 && c >= 1, "jacobi_rows: bad size");
+  const long bsz = (long)k * c, jsz = (long)k * k;
+  long need = 0;
+  if (bsz <= kLdsDoubles) need = (bsz + jsz <= kLdsDoubles) ? bsz + jsz : bsz;
+  hipLaunchKernelGGL(jacobi_rows_kernel, dim3(1), dim3(kNT), need ? lds_bytes(need) : 0, s, k, c, B, JT, U, Wt,
+                     sigma, info, max_sweeps);
+  T2S2_LAUNCH_CHECK();
+}
+
+void hessenberg(hipStream_t s, int n, double* A, double* QT, double* work) {
+  const long need = (long)n * n + 2L * n;
+  hipLaunchKernelGGL(hessenberg_kernel, dim3(1), dim3(kNT), need <= kLdsDoubles ? lds_bytes(need) : 0, s, n, A,
+                     QT, work);
+  T2S2_LAUNCH_CHECK();
+}
+
+long schur_global_work(int n) { return (long)n * n; }
+
+void schur_qr(hipStream_t s, int n, const double* Hr, double2* Hw, double2* ZT, double2* T, int* info) {
+  long m = n - 2;
+  const long psz = 2L * n + (m > 0 ? m * (n + 2) - (m * (m + 3)) / 2 : 0);
+  const long need = psz * 2;
+  hipLaunchKernelGGL(schur_qr_kernel, dim3(1), dim3(kNT), need <= kLdsDoubles ? lds_bytes(need) : 0, s, n, Hr, Hw,
+                     ZT, T, info, 60 * n + 100);
+  T2S2_LAUNCH_CHECK();
+}
+
+void trevec(hipStream_t s, int n, const double2* T, double2* Y) {
+  hipLaunchKernelGGL(trevec_kernel, dim3(1), dim3(kNT), 0, s, n, T, Y);
+  T2S2_LAUNCH_CHECK();
+}
+
+}  // namespace t2s2

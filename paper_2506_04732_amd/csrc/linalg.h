@@ -1,0 +1,93 @@
+// Host-orchestrated linear algebra on device buffers: scratch pool, mode
+// products of TT cores, deflating Cholesky QR, truncated SVD, eigen/Schur
+// decompositions of small nonsymmetric matrices.
+#pragma once
+#include <map>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "dense_small.h"
+#include "gemm.h"
+#include "tt_kernels.h"
+
+namespace t2s2 {
+
+// Named device buffers, grown on demand, released on destruction.
+class Scratch {
+ public:
+  ~Scratch();
+  void* raw(const std::string& name, size_t bytes);
+  template <class T>
+  T* get(const std::string& name, size_t count) {
+    return static_cast<T*>(raw(name, count * sizeof(T) + 64));
+  }
+  size_t bytes() const;
+
+ private:
+  struct Buf {
+    void* p = nullptr;
+    size_t bytes = 0;
+  };
+  std::map<std::string, Buf> bufs_;
+};
+
+struct Ctx {
+  hipStream_t s = nullptr;
+  Scratch* sc = nullptr;
+  void sync() const { T2S2_HIP(hipStreamSynchronize(s)); }
+  template <class T>
+  void d2h(T* h, const T* d, size_t n) const {
+    T2S2_HIP(hipMemcpyAsync(h, d, n * sizeof(T), hipMemcpyDeviceToHost, s));
+    sync();
+  }
+  // synchronous, so the host buffer may be reused right after the call
+  template <class T>
+  void h2d(T* d, const T* h, size_t n) const {
+    T2S2_HIP(hipMemcpyAsync(d, h, n * sizeof(T), hipMemcpyHostToDevice, s));
+    sync();
+  }
+  template <class T>
+  void d2d(T* d, const T* src, size_t n) const {
+    if (n) T2S2_HIP(hipMemcpyAsync(d, src, n * sizeof(T), hipMemcpyDeviceToDevice, s));
+  }
+  // sum x[i] y[i] (synchronous)
+  double dot(const double* x, const double* y, long n) const;
+  double nrm2(const double* x, long n) const;
+};
+
+// ---- mode products of a core X[r0][m][r1] (row-major, contiguous) ----
+// Y[rA][m][r1] = A (rA x r0) x_1 X
+template <class T>
+void mode1(const Ctx& c, int rA, int r0, int m, int r1, const T* A, const T* X, T* Y, T beta, Op opA = OpN);
+// Y[r0][m][rB] = X x_3 B (rB x r1): Y[.., j] = sum_b B[j, b] X[.., b]
+template <class T>
+void mode3(const Ctx& c, int r0, int m, int r1, int rB, const T* X, const T* B, T* Y, T beta, Op opB = OpT);
+// Y[r0][mK][r1] = K (mK x m) x_2 X
+template <class T>
+void mode2(const Ctx& c, int r0, int mK, int m, int r1, const T* K, const T* X, T* Y, T beta, Op opK = OpN);
+
+// Orthonormal basis of the columns of A (M x n, leading dimension lda):
+// A = Q R + E with Q (M x k, ld k) orthonormal, R (k x n, ld n),
+// ||E||_F <= drop ||A||_F.  Gram-based (GEMM) with column skipping in the
+// Cholesky factor and deflation of skipped columns to further levels, plus a
+// second Cholesky QR pass per level for orthogonality.  Q and R must hold
+// M*min(M,n) and min(M,n)*n doubles.  Returns k (0 for A = 0).
+int dcholqr(const Ctx& c, int M, int n, const double* A, long lda, double* Q, double* R, double drop);
+
+// Truncated SVD of A (M x n): keeps the smallest r with the Frobenius tail of
+// the discarded singular values <= delta (1 <= r <= rmax), U (M x r, ld r)
+// orthonormal, W (r x n) with A ~ U W.  sigma_out (optional, host) receives
+// the singular values.  Returns r.
+int trunc_svd(const Ctx& c, int M, int n, const double* A, long lda, double delta, int rmax, double* U, double* W,
+              std::vector<double>* sigma_out = nullptr, double* tail_out = nullptr);
+
+// A (n x n real) = V diag(lam) V^{-1}: Hessenberg reduction, complex Schur
+// form by shifted QR, triangular eigenvectors.  Outputs complex n x n V, Vinv
+// and n eigenvalues.
+void eig_nonsym(const Ctx& c, int n, const double* A, double2* lam, double2* V, double2* Vinv);
+
+// A (n x n real) = Z T Z^H; outputs ZT = Z^T and upper-triangular T.
+void schur_real(const Ctx& c, int n, const double* A, double2* ZT, double2* T);
+
+}  // namespace t2s2

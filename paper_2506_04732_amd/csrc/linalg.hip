@@ -1,0 +1,247 @@
+// Host orchestration of the device linear algebra.  See linalg.h.
+#include "linalg.h"
+
+#include <algorithm>
+#include <cmath>
+
+namespace t2s2 {
+
+Scratch::~Scratch() {
+  for (auto& kv : bufs_)
+    if (kv.second.p) (void)hipFree(kv.second.p);
+}
+
+void* Scratch::raw(const std::string& name, size_t bytes) {
+  Buf& b = bufs_[name];
+  if (b.bytes >= bytes && b.p) return b.p;
+  if (b.p) T2S2_HIP(hipFree(b.p));
+  b.p = nullptr;
+  b.bytes = 0;
+  // grow geometrically to limit reallocations
+  size_t want = std::max(bytes, (size_t)4096);
+  want = std::max(want, b.bytes + b.bytes / 2);
+  hipError_t e = hipMalloc(&b.p, want);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    throw Error(2, "device allocation of " + std::to_string(want) + " bytes failed for " + name);
+  }
+  b.bytes = want;
+  return b.p;
+}
+
+size_t Scratch::bytes() const {
+  size_t t = 0;
+  for (auto& kv : bufs_) t += kv.second.bytes;
+  return t;
+}
+
+double Ctx::dot(const double* x, const double* y, long n) const {
+  if (n <= 0) return 0.0;
+  double* partial = sc->get<double>("ctx.dot.partial", kDotBlocks);
+  double* out = sc->get<double>("ctx.dot.out", 1);
+  dot_device(s, x, y, n, partial, out);
+  double h = 0.0;
+  d2h(&h, out, 1);
+  return h;
+}
+
+double Ctx::nrm2(const double* x, long n) const { return std::sqrt(std::max(0.0, dot(x, x, n))); }
+
+template <class T>
+static T one_v();
+template <>
+double one_v<double>() { return 1.0; }
+template <>
+double2 one_v<double2>() { return make_double2(1.0, 0.0); }
+
+template <class T>
+void mode1(const Ctx& c, int rA, int r0, int m, int r1, const T* A, const T* X, T* Y, T beta, Op opA) {
+  const long ldA = (opA == OpN || opA == OpR) ? r0 : rA;
+  gemm<T>(c.s, opA, OpN, rA, m * r1, r0, one_v<T>(), A, ldA, 0, X, (long)m * r1, 0, beta, Y, (long)m * r1, 0, 1);
+}
+
+template <class T>
+void mode3(const Ctx& c, int r0, int m, int r1, int rB, const T* X, const T* B, T* Y, T beta, Op opB) {
+  // op(B) must be r1 x rB; with opB = T, B is stored rB x r1
+  const long ldB = (opB == OpT || opB == OpC) ? r1 : rB;
+  gemm<T>(c.s, OpN, opB, r0 * m, rB, r1, one_v<T>(), X, r1, 0, B, ldB, 0, beta, Y, rB, 0, 1);
+}
+
+template <class T>
+void mode2(const Ctx& c, int r0, int mK, int m, int r1, const T* K, const T* X, T* Y, T beta, Op opK) {
+  const long ldK = (opK == OpN || opK == OpR) ? m : mK;
+  gemm<T>(c.s, opK, OpN, mK, r1, m, one_v<T>(), K, ldK, 0, X, r1, (long)m * r1, beta, Y, r1, (long)mK * r1, r0);
+}
+
+template void mode1<double>(const Ctx&, int, int, int, int, const double*, const double*, double*, double, Op);
+template void mode1<double2>(const Ctx&, int, int, int, int, const double2*, const double2*, double2*, double2, Op);
+template void mode3<double>(const Ctx&, int, int, int, int, const double*, const double*, double*, double, Op);
+template void mode3<double2>(const Ctx&, int, int, int, int, const double2*, const double2*, double2*, double2, Op);
+template void mode2<double>(const Ctx&, int, int, int, int, const double*, const double*, double*, double, Op);
+template void mode2<double2>(const Ctx&, int, int, int, int, const double2*, const double2*, double2*, double2, Op);
+
+// ------------------------------------------------------------ dcholqr
+int dcholqr(const Ctx& c, int M, int n, const double* A, long lda, double* Qout, double* Rout, double drop) {
+  T2S2_CHECK(M >= 1 && n >= 1, "dcholqr: empty matrix");
+  const int kmax = std::min(M, n);
+  Scratch& S = *c.sc;
+  double* Aw = S.get<double>("dq.A", (size_t)M * n);
+  double* Work = S.get<double>("dq.W", (size_t)M * n);
+  double* Q = S.get<double>("dq.Q", (size_t)M * kmax);
+  double* G = S.get<double>("dq.G", (size_t)n * n);
+  double* Rl = S.get<double>("dq.Rl", (size_t)n * n);
+  double* Ak = S.get<double>("dq.Ak", (size_t)M * n);
+  double* Qk = S.get<double>("dq.Qk", (size_t)M * n);
+  double* R11 = S.get<double>("dq.R11", (size_t)n * n);
+  double* R11i = S.get<double>("dq.R11i", (size_t)n * n);
+  double* C = S.get<double>("dq.C", (size_t)kmax * n);
+  int* mask = S.get<int>("dq.mask", n);
+  int* cnt = S.get<int>("dq.cnt", 1);
+  int* idx = S.get<int>("dq.idx", n);
+  copy2d(c.s, M, n, A, lda, Aw, n);
+  const double normA2 = c.dot(Aw, Aw, (long)M * n);
+  if (!(normA2 > 0.0)) {
+    T2S2_CHECK(normA2 == 0.0, "dcholqr: non-finite input");
+    return 0;
+  }
+  c.d2d(Work, Aw, (size_t)M * n);
+  std::vector<int> hmask(n), hidx;
+  int k = 0;
+  for (int level = 0; level < 5 && k < kmax; ++level) {
+    gemm<double>(c.s, OpT, OpN, n, n, M, 1.0, Work, n, 0, Work, n, 0, 0.0, G, n, 0, 1);
+    chol_skip(c.s, n, G, Rl, mask, cnt, 1e-11);
+    int kl = 0;
+    c.d2h(&kl, cnt, 1);
+    if (kl == 0) break;
+    c.d2h(hmask.data(), mask, n);
+    hidx.clear();
+    for (int j = 0; j < n && (int)hidx.size() < kmax - k; ++j)
+      if (hmask[j]) hidx.push_back(j);
+    kl = (int)hidx.size();
+    if (kl == 0) break;
+    c.h2d(idx, hidx.data(), kl);
+    gather_cols(c.s, M, kl, Work, n, idx, Ak, kl);
+    // R11 = Rl[idx][idx]: gather rows into R11i (as scratch), then columns
+    gather_cols(c.s, n, kl, Rl, n, idx, R11i, kl);           // n x kl: columns idx
+    // rows idx of that: transpose, gather columns, transpose back
+    transpose(c.s, n, kl, R11i, kl, G, n);                   // kl x n
+    gather_cols(c.s, kl, kl, G, n, idx, R11, kl);            // kl x kl = (R11)^T
+    transpose(c.s, kl, kl, R11, kl, G, kl);                  // R11
+    trtri_upper(c.s, kl, G, R11i);
+    gemm<double>(c.s, OpN, OpN, M, kl, kl, 1.0, Ak, kl, 0, R11i, kl, 0, 0.0, Qk, kl, 0, 1);
+    // orthogonality pass(es): reorthogonalise against earlier levels, then a
+    // Cholesky QR pass on the new block
+    for (int pass = 0; pass < 2; ++pass) {
+      if (k > 0) {
+        gemm<double>(c.s, OpT, OpN, k, kl, M, 1.0, Q, kmax, 0, Qk, kl, 0, 0.0, C, kl, 0, 1);
+        gemm<double>(c.s, OpN, OpN, M, kl, k, -1.0, Q, kmax, 0, C, kl, 0, 1.0, Qk, kl, 0, 1);
+      }
+      gemm<double>(c.s, OpT, OpN, kl, kl, M, 1.0, Qk, kl, 0, Qk, kl, 0, 0.0, G, kl, 0, 1);
+      chol_skip(c.s, kl, G, R11, mask, cnt, 1e-14);
+      int k2 = 0;
+      c.d2h(&k2, cnt, 1);
+      if (k2 < kl) {
+        // a column became dependent after reorthogonalisation: keep the rest
+        std::vector<int> m2(kl), id2;
+        c.d2h(m2.data(), mask, kl);
+        for (int j = 0; j < kl; ++j)
+          if (m2[j]) id2.push_back(j);
+        if (id2.empty()) { kl = 0; break; }
+        c.h2d(idx, id2.data(), id2.size());
+        gather_cols(c.s, M, (int)id2.size(), Qk, kl, idx, Ak, (long)id2.size());
+        kl = (int)id2.size();
+        c.d2d(Qk, Ak, (size_t)M * kl);
+        --pass;  // redo this pass on the reduced block
+        continue;
+      }
+      trtri_upper(c.s, kl, R11, R11i);
+      gemm<double>(c.s, OpN, OpN, M, kl, kl, 1.0, Qk, kl, 0, R11i, kl, 0, 0.0, Ak, kl, 0, 1);
+      c.d2d(Qk, Ak, (size_t)M * kl);
+    }
+    if (kl == 0) break;
+    copy2d(c.s, M, kl, Qk, kl, Q + k, kmax);
+    k += kl;
+    // deflate: Work = A - Q Q^T A
+    gemm<double>(c.s, OpT, OpN, k, n, M, 1.0, Q, kmax, 0, Aw, n, 0, 0.0, C, n, 0, 1);
+    c.d2d(Work, Aw, (size_t)M * n);
+    gemm<double>(c.s, OpN, OpN, M, n, k, -1.0, Q, kmax, 0, C, n, 0, 1.0, Work, n, 0, 1);
+    const double rem = c.dot(Work, Work, (long)M * n);
+    if (rem <= drop * drop * normA2) break;
+  }
+  if (k == 0) return 0;
+  gemm<double>(c.s, OpT, OpN, k, n, M, 1.0, Q, kmax, 0, Aw, n, 0, 0.0, Rout, n, 0, 1);
+  copy2d(c.s, M, k, Q, kmax, Qout, k);
+  return k;
+}
+
+// ------------------------------------------------------------ truncated SVD
+int trunc_svd(const Ctx& c, int M, int n, const double* A, long lda, double delta, int rmax, double* U, double* W,
+              std::vector<double>* sigma_out, double* tail_out) {
+  Scratch& S = *c.sc;
+  const int kmax = std::min(M, n);
+  double* Q = S.get<double>("ts.Q", (size_t)M * kmax);
+  double* R = S.get<double>("ts.R", (size_t)kmax * n);
+  int k = dcholqr(c, M, n, A, lda, Q, R, 1e-15);
+  if (k == 0) {
+    // zero matrix: rank 1 with the first unit vector
+    fill(c.s, U, M, 0.0);
+    const double one = 1.0;
+    c.h2d(U, &one, 1);
+    fill(c.s, W, n, 0.0);
+    c.sync();
+    if (sigma_out) sigma_out->assign(1, 0.0);
+    if (tail_out) *tail_out = 0.0;
+    return 1;
+  }
+  double* JT = S.get<double>("ts.JT", (size_t)k * k);
+  double* J = S.get<double>("ts.J", (size_t)k * k);
+  double* Wt = S.get<double>("ts.Wt", (size_t)k * n);
+  double* sig = S.get<double>("ts.sig", k);
+  int* info = S.get<int>("ts.info", k + 1);
+  jacobi_rows(c.s, k, n, R, JT, J, Wt, sig, info);
+  std::vector<double> hs(k);
+  c.d2h(hs.data(), sig, k);
+  // smallest r with tail(r) = sqrt(sum_{j >= r} s_j^2) <= delta
+  std::vector<double> tail(k + 1, 0.0);
+  for (int j = k - 1; j >= 0; --j) tail[j] = tail[j + 1] + hs[j] * hs[j];
+  int r = k;
+  for (int j = 1; j <= k; ++j)
+    if (std::sqrt(tail[j]) <= delta) { r = j; break; }
+  r = std::max(1, std::min(r, std::min(rmax, k)));
+  gemm<double>(c.s, OpN, OpN, M, r, k, 1.0, Q, k, 0, J, k, 0, 0.0, U, r, 0, 1);
+  c.d2d(W, Wt, (size_t)r * n);
+  if (sigma_out) *sigma_out = hs;
+  if (tail_out) *tail_out = std::sqrt(tail[r]);
+  return r;
+}
+
+// ------------------------------------------------------------ eigen / Schur
+void schur_real(const Ctx& c, int n, const double* A, double2* ZT, double2* T) {
+  Scratch& S = *c.sc;
+  double* H = S.get<double>("eig.H", (size_t)n * n);
+  double* QT = S.get<double>("eig.QT", (size_t)n * n);
+  double* work = S.get<double>("eig.work", 2 * (size_t)n);
+  double2* Hw = S.get<double2>("eig.Hw", (size_t)n * n);
+  int* info = S.get<int>("eig.info", 1);
+  c.d2d(H, A, (size_t)n * n);
+  hessenberg(c.s, n, H, QT, work);
+  real_to_complex(c.s, QT, ZT, (long)n * n);
+  schur_qr(c.s, n, H, Hw, ZT, T, info);
+}
+
+void eig_nonsym(const Ctx& c, int n, const double* A, double2* lam, double2* V, double2* Vinv) {
+  Scratch& S = *c.sc;
+  double2* ZT = S.get<double2>("eig.ZT", (size_t)n * n);
+  double2* T = S.get<double2>("eig.T", (size_t)n * n);
+  double2* Y = S.get<double2>("eig.Y", (size_t)n * n);
+  double2* Yi = S.get<double2>("eig.Yi", (size_t)n * n);
+  schur_real(c, n, A, ZT, T);
+  trevec(c.s, n, T, Y);
+  trtri_upper(c.s, n, Y, Yi);
+  const double2 one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0);
+  gemm<double2>(c.s, OpT, OpN, n, n, n, one, ZT, n, 0, Y, n, 0, zero, V, n, 0, 1);
+  gemm<double2>(c.s, OpN, OpR, n, n, n, one, Yi, n, 0, ZT, n, 0, zero, Vinv, n, 0, 1);
+  diag_complex(c.s, n, T, n, lam);
+}
+
+}  // namespace t2s2

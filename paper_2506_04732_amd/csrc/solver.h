@@ -1,0 +1,77 @@
+// Problem, device TT containers and the TT solver of libt2s2.
+#pragma once
+#include <vector>
+
+#include "linalg.h"
+
+namespace t2s2 {
+
+// TT vector in device memory; cores[l] is [r[l]][n[l]][r[l+1]] row-major.
+struct DTT {
+  int d = 0;
+  std::vector<int> n, r;
+  std::vector<double*> c;
+};
+
+// TT-matrix in device memory; cores [R[l]][n[l]][n[l]][R[l+1]].
+struct DTTM {
+  int d = 0;
+  std::vector<int> n, R;
+  std::vector<double*> c;
+};
+
+struct Problem {
+  int d = 0;
+  std::vector<int> N, m;        // nodes and interior unknowns per dimension
+  double eps = 0.0;
+  std::vector<double> beta;
+  int scheme = 1;
+  int rank_cap = 0;
+  int device = 0;
+  // host copies of the 1D data (interior blocks, m x m, row-major)
+  std::vector<std::vector<double>> gll, theta, E, M, K, Einv;
+  // device: original operator (E, M blocks) and the scaled Kronecker sum
+  // operator (I, K blocks), both as rank-2 TT-matrices
+  DTTM opL, opK;
+  std::vector<double*> dK, dEinv;
+  std::vector<double2*> dK_ZT, dK_T;  // Schur form of K_l
+  std::vector<int> opR;
+  Scratch sc;
+  ~Problem();
+};
+
+struct SolveOptions {
+  double tol = 1e-10;
+  double target = 1e-8;
+  int max_sweeps = 40;
+  int kick = 8;
+  int rank_cap = 0;
+  int init_rank = 2;
+  unsigned long long seed = 0;
+  int check_every = 1;
+  int verbose = 0;
+};
+
+struct SolveReport {
+  int status = 0, sweeps = 0, max_rank = 0;
+  std::vector<int> ranks;
+  double residual = -1.0, time_ms = 0.0;
+  std::vector<double> hist_res, hist_local, hist_time;
+  std::vector<int> hist_rank;
+};
+
+Problem* problem_create(int d, const int* N, double eps, const double* beta, int scheme, int rank_cap);
+
+// y = A x, y's cores preallocated by the caller (ranks R r).
+void tt_matvec(const Ctx& c, const DTTM& A, const DTT& x, DTT& y);
+// ||x||_2 (left orthogonalisation of a scratch copy).
+double tt_norm(const Ctx& c, const DTT& x);
+// ||f - L x|| / ||f|| with the problem's original operator.
+double tt_residual_norm(Problem& p, const Ctx& c, const DTT& x, const DTT& f);
+// In-place rounding; x's cores must hold the input ranks.
+void tt_round(const Ctx& c, DTT& x, double tol, int rmax);
+// TT solve of the interior system; x holds the start (or is random) and
+// receives the solution; its cores need rank_cap * m * rank_cap doubles.
+int solve(Problem& p, const Ctx& c, const DTT& f, const DTT* x0, const SolveOptions& o, DTT& x, SolveReport& rep);
+
+}  // namespace t2s2

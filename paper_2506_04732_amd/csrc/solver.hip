@@ -1,0 +1,809 @@
+// Problem set-up, TT building blocks and the alternating TT solver.
+//
+// Operator (paper: Overview (i)-(iii), Eq. tt-matrix-format): the interior
+// collocation system is L = sum_l E_1 x .. x M_l x .. x E_d, a rank-2
+// TT-matrix.  The solver works on the equivalent system
+//     (x_l E_l^{-1}) L u = (x_l E_l^{-1}) f,   i.e.   (sum_l I x .. K_l .. x I) u = f~,
+// K_l = E_l^{-1} M_l: a Kronecker sum, whose Galerkin projections onto
+// orthonormal TT bases are again Kronecker sums L_left (+) K_l (+) L_right.
+// Every local problem is then solved exactly with eigen-decompositions of the
+// two interface matrices and the Schur form of K_l (complex arithmetic),
+// followed by FP64 iterative refinement against the real local operator.
+//
+// Sweeps (the paper's "swaps", Results: Fig. 6) follow one-site AMEn with
+// residual enrichment (cited by the paper, not printed): local solve,
+// truncated SVD of the new core, enrichment by the residual projected onto
+// the far-side basis of an auxiliary rank-kick TT z, QR, interface update.
+// The stopping test uses the exact FP64 residual of the original system.
+#include "solver.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+
+#include "spectral_host.h"
+
+namespace t2s2 {
+
+// =============================================================== problem
+Problem::~Problem() {
+  auto fr = [](void* p) {
+    if (p) (void)hipFree(p);
+  };
+  for (auto p : opL.c) fr(p);
+  for (auto p : opK.c) fr(p);
+  for (auto p : dK) fr(p);
+  for (auto p : dEinv) fr(p);
+  for (auto p : dK_ZT) fr(p);
+  for (auto p : dK_T) fr(p);
+}
+
+static std::vector<double> host_inverse(int n, std::vector<double> A) {
+  std::vector<double> X(n * n, 0.0);
+  for (int i = 0; i < n; ++i) X[i * n + i] = 1.0;
+  for (int k = 0; k < n; ++k) {
+    int p = k;
+    for (int i = k + 1; i < n; ++i)
+      if (std::fabs(A[i * n + k]) > std::fabs(A[p * n + k])) p = i;
+    if (A[p * n + k] == 0.0) throw Error(1, "singular 1D evaluation matrix");
+    if (p != k)
+      for (int j = 0; j < n; ++j) {
+        std::swap(A[k * n + j], A[p * n + j]);
+        std::swap(X[k * n + j], X[p * n + j]);
+      }
+    const double inv = 1.0 / A[k * n + k];
+    for (int j = 0; j < n; ++j) {
+      A[k * n + j] *= inv;
+      X[k * n + j] *= inv;
+    }
+    for (int i = 0; i < n; ++i) {
+      if (i == k) continue;
+      const double f = A[i * n + k];
+      if (f == 0.0) continue;
+      for (int j = 0; j < n; ++j) {
+        A[i * n + j] -= f * A[k * n + j];
+        X[i * n + j] -= f * X[k * n + j];
+      }
+    }
+  }
+  return X;
+}
+
+template <class T>
+static T* dev_alloc(size_t n) {
+  void* p = nullptr;
+  if (hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) throw Error(2, "device allocation failed");
+  return static_cast<T*>(p);
+}
+
+// Rank-2 TT-matrix of sum_l A_1 x .. x B_l x .. x A_d from per-dimension
+// (A_l, B_l) blocks: first core [B A], middle [[A 0],[B A]], last [A; B].
+static void build_kron_sum(int d, const std::vector<int>& m, const std::vector<std::vector<double>>& Ablk,
+                           const std::vector<std::vector<double>>& Bblk, DTTM& out, std::vector<int>& R) {
+  out.d = d;
+  out.n = m;
+  R.assign(d + 1, 2);
+  R[0] = R[d] = 1;
+  if (d == 1) R[1] = 1;
+  out.R = R;
+  out.c.resize(d);
+  for (int l = 0; l < d; ++l) {
+    const int n = m[l], R0 = R[l], R1 = R[l + 1];
+    std::vector<double> h((size_t)R0 * n * n * R1, 0.0);
+    auto put = [&](int a, int b, const std::vector<double>& blk) {
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) h[(((size_t)a * n + i) * n + j) * R1 + b] = blk[(size_t)i * n + j];
+    };
+    if (d == 1) {
+      put(0, 0, Bblk[l]);
+    } else if (l == 0) {
+      put(0, 0, Bblk[l]);
+      put(0, 1, Ablk[l]);
+    } else if (l == d - 1) {
+      put(0, 0, Ablk[l]);
+      put(1, 0, Bblk[l]);
+    } else {
+      put(0, 0, Ablk[l]);
+      put(1, 0, Bblk[l]);
+      put(1, 1, Ablk[l]);
+    }
+    out.c[l] = dev_alloc<double>(h.size());
+    T2S2_HIP(hipMemcpy(out.c[l], h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
+}
+
+Problem* problem_create(int d, const int* N, double eps, const double* beta, int scheme, int rank_cap) {
+  T2S2_CHECK(d >= 1 && d <= 16, "d must be in [1, 16]");
+  T2S2_CHECK(std::isfinite(eps) && eps > 0.0, "eps must be finite and > 0");
+  T2S2_CHECK(scheme == 0 || scheme == 1, "scheme must be 0 (plain) or 1 (superconsistent)");
+  T2S2_CHECK(rank_cap >= 1 && rank_cap <= 1024, "rank_cap must be in [1, 1024]");
+  for (int l = 0; l < d; ++l) {
+    T2S2_CHECK(N[l] >= 3 && N[l] <= 66, "N must be in [3, 66]");
+    T2S2_CHECK(std::isfinite(beta[l]), "beta must be finite");
+  }
+  Problem* P = new Problem();
+  try {
+    P->d = d;
+    P->eps = eps;
+    P->scheme = scheme;
+    P->rank_cap = rank_cap;
+    T2S2_HIP(hipGetDevice(&P->device));
+    P->N.assign(N, N + d);
+    P->beta.assign(beta, beta + d);
+    P->m.resize(d);
+    std::vector<std::vector<double>> Ieye(d);
+    for (int l = 0; l < d; ++l) {
+      const int n = N[l] - 1, Nl = N[l], m = N[l] - 2;
+      P->m[l] = m;
+      std::vector<double> x = gll_nodes(n);
+      std::vector<double> th = colloc_nodes(n, eps, beta[l], scheme);
+      std::vector<double> Ef((size_t)m * Nl), D1((size_t)m * Nl), D2((size_t)m * Nl);
+      lagrange_eval(x.data(), Nl, th.data(), m, Ef.data(), D1.data(), D2.data());
+      std::vector<double> E((size_t)m * m), M((size_t)m * m);
+      for (int j = 0; j < m; ++j)
+        for (int i = 0; i < m; ++i) {
+          E[(size_t)j * m + i] = Ef[(size_t)j * Nl + i + 1];
+          M[(size_t)j * m + i] = -eps * D2[(size_t)j * Nl + i + 1] + beta[l] * D1[(size_t)j * Nl + i + 1];
+        }
+      std::vector<double> Einv = host_inverse(m, E);
+      std::vector<double> K((size_t)m * m, 0.0);
+      for (int i = 0; i < m; ++i)
+        for (int k = 0; k < m; ++k) {
+          const double a = Einv[(size_t)i * m + k];
+          for (int j = 0; j < m; ++j) K[(size_t)i * m + j] += a * M[(size_t)k * m + j];
+        }
+      P->gll.push_back(x);
+      P->theta.push_back(th);
+      P->E.push_back(E);
+      P->M.push_back(M);
+      P->K.push_back(K);
+      P->Einv.push_back(Einv);
+      Ieye[l].assign((size_t)m * m, 0.0);
+      for (int i = 0; i < m; ++i) Ieye[l][(size_t)i * m + i] = 1.0;
+    }
+    build_kron_sum(d, P->m, P->E, P->M, P->opL, P->opR);
+    std::vector<int> Rk;
+    build_kron_sum(d, P->m, Ieye, P->K, P->opK, Rk);
+    Ctx c{nullptr, &P->sc};
+    for (int l = 0; l < d; ++l) {
+      const int m = P->m[l];
+      double* k = dev_alloc<double>((size_t)m * m);
+      double* ei = dev_alloc<double>((size_t)m * m);
+      T2S2_HIP(hipMemcpy(k, P->K[l].data(), (size_t)m * m * sizeof(double), hipMemcpyHostToDevice));
+      T2S2_HIP(hipMemcpy(ei, P->Einv[l].data(), (size_t)m * m * sizeof(double), hipMemcpyHostToDevice));
+      P->dK.push_back(k);
+      P->dEinv.push_back(ei);
+      double2* zt = dev_alloc<double2>((size_t)m * m);
+      double2* t = dev_alloc<double2>((size_t)m * m);
+      schur_real(c, m, k, zt, t);
+      P->dK_ZT.push_back(zt);
+      P->dK_T.push_back(t);
+    }
+    T2S2_HIP(hipDeviceSynchronize());
+  } catch (...) {
+    delete P;
+    throw;
+  }
+  return P;
+}
+
+// =============================================================== TT ops
+void tt_matvec(const Ctx& c, const DTTM& A, const DTT& x, DTT& y) {
+  T2S2_CHECK(A.d == x.d, "tt_matvec: dimension mismatch");
+  y.d = x.d;
+  y.n = x.n;
+  y.r.assign(x.d + 1, 1);
+  for (int l = 0; l <= x.d; ++l) y.r[l] = A.R[l] * x.r[l];
+  for (int l = 0; l < x.d; ++l) {
+    T2S2_CHECK(A.n[l] == x.n[l], "tt_matvec: mode size mismatch");
+    ttm_matvec_core(c.s, A.R[l], A.R[l + 1], x.n[l], x.r[l], x.r[l + 1], A.c[l], x.c[l], y.c[l]);
+  }
+}
+
+// Copy of x in scratch (prefix names the buffers).
+static DTT scratch_copy(const Ctx& c, const DTT& x, const std::string& prefix, int extra_rank = 0) {
+  DTT y = x;
+  for (int l = 0; l < x.d; ++l) {
+    const size_t sz = (size_t)x.r[l] * x.n[l] * x.r[l + 1];
+    const size_t cap = (size_t)(x.r[l] + extra_rank) * x.n[l] * (x.r[l + 1] + extra_rank);
+    y.c[l] = c.sc->get<double>(prefix + std::to_string(l), std::max(sz, cap));
+    c.d2d(y.c[l], x.c[l], sz);
+  }
+  return y;
+}
+
+// In place: cores 0..d-2 become left-orthonormal (ranks may shrink); returns
+// the norm of the last core (= ||x||).  Core buffers must hold r_l n r_{l+1}
+// for the input ranks.
+static double left_orthogonalize(const Ctx& c, DTT& x, const std::string& tag) {
+  for (int l = 0; l + 1 < x.d; ++l) {
+    const int M = x.r[l] * x.n[l], n = x.r[l + 1];
+    const int kmax = std::min(M, n);
+    double* Q = c.sc->get<double>(tag + ".Q", (size_t)M * kmax);
+    double* R = c.sc->get<double>(tag + ".R", (size_t)kmax * n);
+    int k;
+    if (M <= n) {
+      // wide unfolding: the identity is an orthonormal basis of its column space
+      k = M;
+      c.d2d(R, x.c[l], (size_t)M * n);
+      fill(c.s, x.c[l], (long)M * M, 0.0);
+      const int nn = M;
+      std::vector<double> eye((size_t)nn * nn, 0.0);
+      for (int i = 0; i < nn; ++i) eye[(size_t)i * nn + i] = 1.0;
+      c.h2d(x.c[l], eye.data(), eye.size());
+      c.sync();
+    } else {
+      k = dcholqr(c, M, n, x.c[l], n, Q, R, 1e-15);
+      if (k == 0) return 0.0;
+      c.d2d(x.c[l], Q, (size_t)M * k);
+    }
+    const int n1 = x.n[l + 1], r2 = x.r[l + 2];
+    double* T = c.sc->get<double>(tag + ".T", (size_t)k * n1 * r2);
+    mode1<double>(c, k, n, n1, r2, R, x.c[l + 1], T, 0.0);
+    c.d2d(x.c[l + 1], T, (size_t)k * n1 * r2);
+    x.r[l + 1] = k;
+  }
+  const int l = x.d - 1;
+  return c.nrm2(x.c[l], (long)x.r[l] * x.n[l] * x.r[l + 1]);
+}
+
+double tt_norm(const Ctx& c, const DTT& x) {
+  // extra capacity: wide unfoldings are replaced by identities of size r n
+  DTT y = x;
+  for (int l = 0; l < x.d; ++l) {
+    const size_t sz = (size_t)x.r[l] * x.n[l] * x.r[l + 1];
+    size_t cap = sz;
+    const size_t rl = (size_t)x.r[l] * x.n[l];
+    cap = std::max(cap, rl * rl);
+    cap = std::max(cap, rl * x.n[std::min(l + 1, x.d - 1)] * (size_t)x.r[std::min(l + 2, x.d)]);
+    y.c[l] = c.sc->get<double>("nrm.c" + std::to_string(l), cap);
+    c.d2d(y.c[l], x.c[l], sz);
+  }
+  return left_orthogonalize(c, y, "nrm");
+}
+
+double tt_residual_norm(Problem& p, const Ctx& c, const DTT& x, const DTT& f) {
+  const int d = x.d;
+  T2S2_CHECK(f.d == d, "residual: dimension mismatch");
+  // y = L x in scratch
+  DTT y;
+  y.d = d;
+  y.n = x.n;
+  y.r.resize(d + 1);
+  y.c.resize(d);
+  for (int l = 0; l < d; ++l)
+    y.c[l] = c.sc->get<double>("res.y" + std::to_string(l),
+                               (size_t)p.opL.R[l] * x.r[l] * x.n[l] * p.opL.R[l + 1] * x.r[l + 1]);
+  tt_matvec(c, p.opL, x, y);
+  // r = f - y by concatenation
+  DTT r;
+  r.d = d;
+  r.n = x.n;
+  r.r.resize(d + 1);
+  r.c.resize(d);
+  r.r[0] = r.r[d] = 1;
+  for (int l = 1; l < d; ++l) r.r[l] = f.r[l] + y.r[l];
+  for (int l = 0; l < d; ++l) {
+    const int n = x.n[l];
+    const size_t sz = (size_t)r.r[l] * n * r.r[l + 1];
+    const size_t rl = (size_t)r.r[l] * n;
+    const size_t cap = std::max({sz, rl * rl, rl * (size_t)(l + 1 < d ? x.n[l + 1] * r.r[l + 2] : 1)});
+    r.c[l] = c.sc->get<double>("res.r" + std::to_string(l), cap);
+    if (d == 1) {
+      c.d2d(r.c[l], f.c[l], (size_t)n);
+      axpby(c.s, n, -1.0, y.c[l], 1.0, r.c[l]);
+      continue;
+    }
+    fill(c.s, r.c[l], (long)sz, 0.0);
+    const int fr0 = f.r[l], fr1 = f.r[l + 1], yr0 = y.r[l], yr1 = y.r[l + 1];
+    const long ld = r.r[l + 1];
+    if (l == 0) {
+      copy2d(c.s, n, fr1, f.c[l], fr1, r.c[l], ld);
+      copy2d(c.s, n, yr1, y.c[l], yr1, r.c[l] + fr1, ld, -1.0);
+    } else if (l == d - 1) {
+      copy2d(c.s, (long)fr0 * n, 1, f.c[l], 1, r.c[l], 1);
+      copy2d(c.s, (long)yr0 * n, 1, y.c[l], 1, r.c[l] + (long)fr0 * n, 1);
+    } else {
+      copy2d(c.s, (long)fr0 * n, fr1, f.c[l], fr1, r.c[l], ld);
+      copy2d(c.s, (long)yr0 * n, yr1, y.c[l], yr1, r.c[l] + (long)fr0 * n * ld + fr1, ld);
+    }
+  }
+  const double rn = left_orthogonalize(c, r, "res.o");
+  const double fn = tt_norm(c, f);
+  T2S2_CHECK(fn > 0.0 && std::isfinite(fn), "residual: ||f|| must be finite and > 0");
+  return rn / fn;
+}
+
+void tt_round(const Ctx& c, DTT& x, double tol, int rmax) {
+  const int d = x.d;
+  if (d == 1) return;
+  // right-to-left orthogonalisation (in place, ranks never grow)
+  for (int l = d - 1; l >= 1; --l) {
+    const int r0 = x.r[l], n = x.n[l], r1 = x.r[l + 1];
+    const int M = n * r1;  // rows of the transposed unfolding
+    double* At = c.sc->get<double>("rnd.At", (size_t)M * r0);
+    transpose(c.s, r0, M, x.c[l], M, At, r0);
+    const int kmax = std::min(M, r0);
+    double* Q = c.sc->get<double>("rnd.Q", (size_t)M * kmax);
+    double* R = c.sc->get<double>("rnd.R", (size_t)kmax * r0);
+    int k = dcholqr(c, M, r0, At, r0, Q, R, 1e-15);
+    if (k == 0) k = 1, fill(c.s, Q, M, 0.0), fill(c.s, R, r0, 0.0);
+    transpose(c.s, M, k, Q, k, x.c[l], M);  // core = Q^T (k x n r1)
+    const int rp = x.r[l - 1], np = x.n[l - 1];
+    double* T = c.sc->get<double>("rnd.T", (size_t)rp * np * k);
+    mode3<double>(c, rp, np, r0, k, x.c[l - 1], R, T, 0.0);  // core_{l-1} x3 R
+    c.d2d(x.c[l - 1], T, (size_t)rp * np * k);
+    x.r[l] = k;
+  }
+  const double nrm = c.nrm2(x.c[0], (long)x.n[0] * x.r[1]);
+  const double delta = tol * nrm / std::sqrt((double)(d - 1));
+  for (int l = 0; l + 1 < d; ++l) {
+    const int r0 = x.r[l], n = x.n[l], r1 = x.r[l + 1];
+    const int M = r0 * n;
+    const int kmax = std::min(M, r1);
+    double* U = c.sc->get<double>("rnd.U", (size_t)M * kmax);
+    double* W = c.sc->get<double>("rnd.W", (size_t)kmax * r1);
+    const int r = trunc_svd(c, M, r1, x.c[l], r1, delta, rmax, U, W);
+    c.d2d(x.c[l], U, (size_t)M * r);
+    const int n1 = x.n[l + 1], r2 = x.r[l + 2];
+    double* T = c.sc->get<double>("rnd.T", (size_t)r * n1 * r2);
+    mode1<double>(c, r, r1, n1, r2, W, x.c[l + 1], T, 0.0);
+    c.d2d(x.c[l + 1], T, (size_t)r * n1 * r2);
+    x.r[l + 1] = r;
+  }
+}
+
+// ================================================================ solver
+namespace {
+
+struct Eig {
+  double2* lam = nullptr;
+  double2* V = nullptr;
+  double2* Vi = nullptr;
+};
+
+struct Amen {
+  Problem& p;
+  const Ctx& c;
+  SolveOptions o;
+  int d, cap, kick, smax;
+  std::vector<int> m;
+  // interfaces per bond position 0..d (matrices in row-major, [test][trial])
+  std::vector<double*> L, XB, ZXI, ZXL, ZB;
+  std::vector<Eig> eig;
+  std::vector<int> xr, zr, sr;  // ranks of x, z, f~ per bond
+  std::vector<double*> xc, zc, bc;  // cores
+  std::vector<int> maxrank;     // structural bound per bond
+  // work
+  double *u, *f, *res, *y, *T1, *T2, *A1, *S, *kick_buf, *zbuf, *U, *W, *tmp, *Qk, *Rk;
+  double2 *h0, *h1;
+
+  Amen(Problem& p_, const Ctx& c_, const SolveOptions& o_) : p(p_), c(c_), o(o_) {}
+
+  double* buf(const std::string& n, size_t cnt) { return c.sc->get<double>("am." + n, cnt); }
+
+  void local_apply(int l, int r1, int r2, const double* LL, const double* LR, const double* x, double* out) {
+    const int ml = m[l];
+    mode1<double>(c, r1, r1, ml, r2, LL, x, out, 0.0);
+    mode2<double>(c, r1, ml, ml, r2, p.dK[l], x, out, 1.0);
+    mode3<double>(c, r1, ml, r2, r2, x, LR, out, 1.0);
+  }
+
+  // out = B^{-1} g for B = L_L (+) K_l (+) L_R via the eigen/Schur factors
+  void local_solve(int l, int r1, int r2, const Eig& eL, const Eig& eR, const double* g, double* out) {
+    const int ml = m[l];
+    const long n = (long)r1 * ml * r2;
+    const double2 z0 = make_double2(0.0, 0.0);
+    real_to_complex(c.s, g, h0, n);
+    mode3<double2>(c, r1, ml, r2, r2, h0, eR.Vi, h1, z0);
+    mode2<double2>(c, r1, ml, ml, r2, p.dK_ZT[l], h1, h0, z0, OpR);
+    mode1<double2>(c, r1, r1, ml, r2, eL.Vi, h0, h1, z0);
+    kron_trisolve(c.s, r1, ml, r2, p.dK_T[l], eL.lam, eR.lam, h1);
+    mode1<double2>(c, r1, r1, ml, r2, eL.V, h1, h0, z0);
+    mode2<double2>(c, r1, ml, ml, r2, p.dK_ZT[l], h0, h1, z0, OpT);
+    mode3<double2>(c, r1, ml, r2, r2, h1, eR.V, h0, z0);
+    complex_real_part(c.s, h0, out, n);
+  }
+
+  void set_boundary(int pos) {
+    // 1 x 1 interfaces: L = 0, XB = 1, ZXI = 1, ZXL = 0, ZB = 1
+    const double zero = 0.0, one = 1.0;
+    c.h2d(L[pos], &zero, 1);
+    c.h2d(XB[pos], &one, 1);
+    c.h2d(ZXI[pos], &one, 1);
+    c.h2d(ZXL[pos], &zero, 1);
+    c.h2d(ZB[pos], &one, 1);
+    const double2 z = make_double2(0.0, 0.0), o1 = make_double2(1.0, 0.0);
+    c.h2d(eig[pos].lam, &z, 1);
+    c.h2d(eig[pos].V, &o1, 1);
+    c.h2d(eig[pos].Vi, &o1, 1);
+    c.sync();
+  }
+
+  // ---- interface updates ------------------------------------------------
+  // left interfaces at pos l+1 from pos l and cores x_l (r0 x m x r1), z_l (q0 x m x q1)
+  void update_left(int l) {
+    const int r0 = xr[l], r1 = xr[l + 1], q0 = zr[l], q1 = zr[l + 1], s0 = sr[l], s1 = sr[l + 1], ml = m[l];
+    const double* X = xc[l];
+    const double* Z = zc[l];
+    // L' = X^T (L x1 X + K x2 X)
+    mode1<double>(c, r0, r0, ml, r1, L[l], X, T1, 0.0);
+    mode2<double>(c, r0, ml, ml, r1, p.dK[l], X, T1, 1.0);
+    gemm<double>(c.s, OpT, OpN, r1, r1, r0 * ml, 1.0, X, r1, 0, T1, r1, 0, 0.0, L[l + 1], r1, 0, 1);
+    // XB' = X^T (XB x1 b)
+    mode1<double>(c, r0, s0, ml, s1, XB[l], bc[l], T1, 0.0);
+    gemm<double>(c.s, OpT, OpN, r1, s1, r0 * ml, 1.0, X, r1, 0, T1, s1, 0, 0.0, XB[l + 1], s1, 0, 1);
+    // ZXI' = Z^T (ZXI x1 X);  ZXL' = Z^T (ZXL x1 X + K x2 (ZXI x1 X))
+    mode1<double>(c, q0, r0, ml, r1, ZXI[l], X, T1, 0.0);
+    gemm<double>(c.s, OpT, OpN, q1, r1, q0 * ml, 1.0, Z, q1, 0, T1, r1, 0, 0.0, ZXI[l + 1], r1, 0, 1);
+    mode1<double>(c, q0, r0, ml, r1, ZXL[l], X, T2, 0.0);
+    mode2<double>(c, q0, ml, ml, r1, p.dK[l], T1, T2, 1.0);
+    gemm<double>(c.s, OpT, OpN, q1, r1, q0 * ml, 1.0, Z, q1, 0, T2, r1, 0, 0.0, ZXL[l + 1], r1, 0, 1);
+    // ZB' = Z^T (ZB x1 b)
+    mode1<double>(c, q0, s0, ml, s1, ZB[l], bc[l], T1, 0.0);
+    gemm<double>(c.s, OpT, OpN, q1, s1, q0 * ml, 1.0, Z, q1, 0, T1, s1, 0, 0.0, ZB[l + 1], s1, 0, 1);
+    eig_nonsym(c, r1, L[l + 1], eig[l + 1].lam, eig[l + 1].V, eig[l + 1].Vi);
+  }
+
+  // right interfaces at pos l from pos l+1 and cores x_l, z_l
+  void update_right(int l) {
+    const int r0 = xr[l], r1 = xr[l + 1], q0 = zr[l], q1 = zr[l + 1], s0 = sr[l], s1 = sr[l + 1], ml = m[l];
+    const double* X = xc[l];
+    const double* Z = zc[l];
+    // L' = X_mat (K x2 X + X x3 L)^T
+    mode2<double>(c, r0, ml, ml, r1, p.dK[l], X, T1, 0.0);
+    mode3<double>(c, r0, ml, r1, r1, X, L[l + 1], T1, 1.0);
+    gemm<double>(c.s, OpN, OpT, r0, r0, ml * r1, 1.0, X, (long)ml * r1, 0, T1, (long)ml * r1, 0, 0.0, L[l], r0, 0, 1);
+    // XB' = X_mat (b x3 XB)^T   (r0 x s0)
+    mode3<double>(c, s0, ml, s1, r1, bc[l], XB[l + 1], T1, 0.0);
+    gemm<double>(c.s, OpN, OpT, r0, s0, ml * r1, 1.0, X, (long)ml * r1, 0, T1, (long)ml * r1, 0, 0.0, XB[l], s0, 0, 1);
+    // ZXI' = Z_mat (X x3 ZXI)^T ; ZXL' = Z_mat (K x2 (X x3 ZXI) + X x3 ZXL)^T
+    mode3<double>(c, r0, ml, r1, q1, X, ZXI[l + 1], T1, 0.0);
+    gemm<double>(c.s, OpN, OpT, q0, r0, ml * q1, 1.0, Z, (long)ml * q1, 0, T1, (long)ml * q1, 0, 0.0, ZXI[l], r0, 0, 1);
+    mode3<double>(c, r0, ml, r1, q1, X, ZXL[l + 1], T2, 0.0);
+    mode2<double>(c, r0, ml, ml, q1, p.dK[l], T1, T2, 1.0);
+    gemm<double>(c.s, OpN, OpT, q0, r0, ml * q1, 1.0, Z, (long)ml * q1, 0, T2, (long)ml * q1, 0, 0.0, ZXL[l], r0, 0, 1);
+    // ZB' = Z_mat (b x3 ZB)^T  (q0 x s0)
+    mode3<double>(c, s0, ml, s1, q1, bc[l], ZB[l + 1], T1, 0.0);
+    gemm<double>(c.s, OpN, OpT, q0, s0, ml * q1, 1.0, Z, (long)ml * q1, 0, T1, (long)ml * q1, 0, 0.0, ZB[l], s0, 0, 1);
+    eig_nonsym(c, r0, L[l], eig[l].lam, eig[l].V, eig[l].Vi);
+  }
+
+  // right-orthogonalise a TT held in cores (in place); ranks updated
+  void right_orth(std::vector<double*>& cores, std::vector<int>& r) {
+    for (int l = d - 1; l >= 1; --l) {
+      const int r0 = r[l], n = m[l], r1 = r[l + 1];
+      const int M = n * r1;
+      transpose(c.s, r0, M, cores[l], M, tmp, r0);
+      int k = dcholqr(c, M, r0, tmp, r0, Qk, Rk, 1e-15);
+      T2S2_CHECK(k >= 1, "solver: zero core in orthogonalisation");
+      transpose(c.s, M, k, Qk, k, cores[l], M);
+      mode3<double>(c, r[l - 1], m[l - 1], r0, k, cores[l - 1], Rk, tmp, 0.0);
+      c.d2d(cores[l - 1], tmp, (size_t)r[l - 1] * m[l - 1] * k);
+      r[l] = k;
+    }
+  }
+
+  int run(const DTT& fin, const DTT* x0, DTT& xout, SolveReport& rep) {
+    auto t_start = std::chrono::steady_clock::now();
+    d = p.d;
+    m = p.m;
+    cap = o.rank_cap > 0 ? std::min(o.rank_cap, p.rank_cap) : p.rank_cap;
+    kick = std::max(0, std::min(o.kick, cap));
+    T2S2_CHECK(fin.d == d, "solve: f has the wrong dimension");
+    for (int l = 0; l < d; ++l) T2S2_CHECK(fin.n[l] == m[l], "solve: f mode sizes must be N_l - 2");
+    maxrank.assign(d + 1, 1);
+    {
+      // bond l bound: min(prod_{k<l} m_k, prod_{k>=l} m_k, cap)
+      for (int l = 1; l < d; ++l) {
+        double a = 1, b = 1;
+        for (int k = 0; k < l; ++k) a *= m[k];
+        for (int k = l; k < d; ++k) b *= m[k];
+        maxrank[l] = (int)std::min<double>({a, b, (double)cap});
+      }
+    }
+    smax = 1;
+    sr.assign(d + 1, 1);
+    for (int l = 0; l <= d; ++l) {
+      sr[l] = fin.r[l];
+      smax = std::max(smax, sr[l]);
+    }
+    int mmax = *std::max_element(m.begin(), m.end());
+    const size_t big = (size_t)cap * mmax * cap;
+    const size_t kk = (size_t)std::max(kick, 1);
+    // f~ = (x E^{-1}) f
+    bc.resize(d);
+    for (int l = 0; l < d; ++l) {
+      bc[l] = buf("b" + std::to_string(l), (size_t)sr[l] * m[l] * sr[l + 1]);
+      mode2<double>(c, sr[l], m[l], m[l], sr[l + 1], p.dEinv[l], fin.c[l], bc[l], 0.0);
+    }
+    L.resize(d + 1);
+    XB.resize(d + 1);
+    ZXI.resize(d + 1);
+    ZXL.resize(d + 1);
+    ZB.resize(d + 1);
+    eig.resize(d + 1);
+    for (int l = 0; l <= d; ++l) {
+      const std::string t = std::to_string(l);
+      L[l] = buf("L" + t, (size_t)cap * cap);
+      XB[l] = buf("XB" + t, (size_t)cap * smax);
+      ZXI[l] = buf("ZXI" + t, kk * cap);
+      ZXL[l] = buf("ZXL" + t, kk * cap);
+      ZB[l] = buf("ZB" + t, kk * smax);
+      eig[l].lam = c.sc->get<double2>("am.lam" + t, cap);
+      eig[l].V = c.sc->get<double2>("am.V" + t, (size_t)cap * cap);
+      eig[l].Vi = c.sc->get<double2>("am.Vi" + t, (size_t)cap * cap);
+    }
+    u = buf("u", big);
+    f = buf("f", big);
+    res = buf("res", big);
+    y = buf("y", big);
+    T1 = buf("T1", std::max(big, (size_t)cap * mmax * smax));
+    T2 = buf("T2", big);
+    A1 = buf("A1", (size_t)cap * mmax * kk);
+    S = buf("S", (size_t)cap * mmax * kk);
+    kick_buf = buf("kick", (size_t)cap * mmax * kk);
+    zbuf = buf("zc", kk * mmax * kk);
+    U = buf("U", big);
+    W = buf("W", (size_t)cap * cap);
+    tmp = buf("tmp", big);
+    Qk = buf("Qk", big + kk * mmax * ((size_t)cap + kk));
+    Rk = buf("Rk", (size_t)cap * std::max<size_t>(cap, mmax * kk));
+    h0 = c.sc->get<double2>("am.h0", big);
+    h1 = c.sc->get<double2>("am.h1", big);
+    // initial x (caller's buffers) and z (scratch)
+    xr.assign(d + 1, 1);
+    zr.assign(d + 1, 1);
+    xc = xout.c;
+    zc.resize(d);
+    for (int l = 1; l < d; ++l) {
+      xr[l] = x0 ? std::min(x0->r[l], maxrank[l]) : std::min(std::max(1, o.init_rank), maxrank[l]);
+      zr[l] = std::min((int)kk, maxrank[l]);
+    }
+    for (int l = 0; l < d; ++l) {
+      zc[l] = buf("z" + std::to_string(l), kk * mmax * kk);
+      if (x0) {
+        T2S2_CHECK(x0->r[l] <= cap && x0->r[l + 1] <= cap, "solve: x0 ranks exceed rank_cap");
+        if (x0->c[l] != xc[l]) c.d2d(xc[l], x0->c[l], (size_t)x0->r[l] * m[l] * x0->r[l + 1]);
+      } else {
+        fill_random(c.s, xc[l], (long)xr[l] * m[l] * xr[l + 1], o.seed * 1315423911ULL + 17ULL * l + 1ULL);
+      }
+      fill_random(c.s, zc[l], (long)zr[l] * m[l] * zr[l + 1], o.seed * 2654435761ULL + 31ULL * l + 7ULL);
+    }
+    if (x0) xr = x0->r;
+    right_orth(xc, xr);
+    right_orth(zc, zr);
+    set_boundary(0);
+    set_boundary(d);
+    for (int l = d - 1; l >= 1; --l) update_right(l);
+
+    const double loc_tol = o.tol / std::sqrt((double)d);
+    int status = 3;
+    int direction = +1;
+    int sweeps = 0;
+    double last_res = -1.0;
+    for (int sw = 0; sw < o.max_sweeps; ++sw) {
+      sweeps = sw + 1;
+      double max_res = 0.0;
+      for (int step = 0; step < d; ++step) {
+        const int l = direction > 0 ? step : d - 1 - step;
+        const int r1 = xr[l], r2 = xr[l + 1], ml = m[l], s0 = sr[l], s1 = sr[l + 1];
+        const long n = (long)r1 * ml * r2;
+        // local right-hand side f = XB_l x1 b x3 XB_{l+1}
+        mode1<double>(c, r1, s0, ml, s1, XB[l], bc[l], T1, 0.0);
+        mode3<double>(c, r1, ml, s1, r2, T1, XB[l + 1], f, 0.0);
+        const double fn = c.nrm2(f, n);
+        // residual of the current core, refinement with the exact solver
+        c.d2d(u, xc[l], n);
+        local_apply(l, r1, r2, L[l], L[l + 1], u, res);
+        axpby(c.s, n, 1.0, f, -1.0, res);
+        double rn = c.nrm2(res, n);
+        T2S2_CHECK(std::isfinite(rn) && std::isfinite(fn), "solve: non-finite local residual");
+        const double res0 = fn > 0 ? rn / fn : 0.0;
+        max_res = std::max(max_res, res0);
+        if (res0 > loc_tol) {
+          for (int it = 0; it < 6; ++it) {
+            local_solve(l, r1, r2, eig[l], eig[l + 1], res, y);
+            axpby(c.s, n, 1.0, y, 1.0, u);
+            local_apply(l, r1, r2, L[l], L[l + 1], u, res);
+            axpby(c.s, n, 1.0, f, -1.0, res);
+            rn = c.nrm2(res, n);
+            if (rn <= 0.1 * loc_tol * fn) break;
+          }
+        }
+        const bool last = (direction > 0 && l == d - 1) || (direction < 0 && l == 0);
+        if (last) {
+          c.d2d(xc[l], u, n);
+          continue;
+        }
+        const double unorm = c.nrm2(u, n);
+        const double delta = o.tol * unorm / std::sqrt((double)d);
+        if (direction > 0) step_right(l, delta);
+        else step_left(l, delta);
+      }
+      direction = -direction;
+      rep.hist_local.push_back(max_res);
+      int mr = 0;
+      for (int l = 0; l <= d; ++l) mr = std::max(mr, xr[l]);
+      rep.hist_rank.push_back(mr);
+      double gres = -1.0;
+      const bool check = (o.check_every <= 1) || (sweeps % o.check_every == 0) || (sweeps == o.max_sweeps) ||
+                         max_res < o.tol;
+      if (check) {
+        DTT xd;
+        xd.d = d;
+        xd.n = m;
+        xd.r = xr;
+        xd.c = xc;
+        gres = tt_residual_norm(p, c, xd, fin);
+        last_res = gres;
+      }
+      rep.hist_res.push_back(gres);
+      const double ms =
+          std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+      rep.hist_time.push_back(ms);
+      if (o.verbose)
+        std::fprintf(stderr, "[t2s2] sweep %d  max local res %.3e  residual %.3e  max rank %d  %.1f ms\n", sweeps,
+                     max_res, gres, mr, ms);
+      if (gres >= 0.0 && gres <= o.target) {
+        status = 0;
+        break;
+      }
+    }
+    if (last_res < 0.0) {
+      DTT xd;
+      xd.d = d;
+      xd.n = m;
+      xd.r = xr;
+      xd.c = xc;
+      last_res = tt_residual_norm(p, c, xd, fin);
+      status = last_res <= o.target ? 0 : 3;
+    }
+    xout.r = xr;
+    rep.status = status;
+    rep.sweeps = sweeps;
+    rep.residual = last_res;
+    rep.ranks = xr;
+    rep.max_rank = *std::max_element(xr.begin(), xr.end());
+    c.sync();
+    rep.time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    return status;
+  }
+
+  // ---- left-to-right split at core l (l < d-1) ---------------------------
+  void step_right(int l, double delta) {
+    const int r1 = xr[l], r2 = xr[l + 1], ml = m[l], s0 = sr[l], s1 = sr[l + 1];
+    const int q0 = zr[l], q2 = zr[l + 1], r3 = xr[l + 2], m1 = m[l + 1];
+    const int M = r1 * ml;
+    const int room = std::max(1, maxrank[l + 1]);
+    const int r = trunc_svd(c, M, r2, u, r2, delta, room, U, W);
+    // uk = U W (truncated solution)
+    gemm<double>(c.s, OpN, OpN, M, r2, r, 1.0, U, r, 0, W, r2, 0, 0.0, y, r2, 0, 1);
+    int kk = 0, kq = 0;
+    if (kick > 0 && q2 > 0) {
+      // A1 = uk x3 ZXI_{l+1};  S = K x2 A1 + uk x3 ZXL_{l+1}
+      mode3<double>(c, r1, ml, r2, q2, y, ZXI[l + 1], A1, 0.0);
+      mode2<double>(c, r1, ml, ml, q2, p.dK[l], A1, S, 0.0);
+      mode3<double>(c, r1, ml, r2, q2, y, ZXL[l + 1], S, 1.0);
+      // kick = (XB_l x1 b) x3 ZB_{l+1} - (L_l x1 A1 + S)      (r1 m x q2)
+      mode1<double>(c, r1, s0, ml, s1, XB[l], bc[l], T1, 0.0);
+      mode3<double>(c, r1, ml, s1, q2, T1, ZB[l + 1], kick_buf, 0.0);
+      axpby(c.s, (long)M * q2, -1.0, S, 1.0, kick_buf);
+      mode1<double>(c, r1, r1, ml, q2, L[l], A1, T2, 0.0);
+      axpby(c.s, (long)M * q2, -1.0, T2, 1.0, kick_buf);
+      // z core: (ZB_l x1 b) x3 ZB_{l+1} - (ZXL_l x1 A1 + ZXI_l x1 S)   (q0 m x q2)
+      mode1<double>(c, q0, s0, ml, s1, ZB[l], bc[l], T1, 0.0);
+      mode3<double>(c, q0, ml, s1, q2, T1, ZB[l + 1], zbuf, 0.0);
+      mode1<double>(c, q0, r1, ml, q2, ZXL[l], A1, T2, 0.0);
+      mode1<double>(c, q0, r1, ml, q2, ZXI[l], S, T2, 1.0);
+      axpby(c.s, (long)q0 * ml * q2, -1.0, T2, 1.0, zbuf);
+      // orthogonalise the kick against U (two passes) and orthonormalise it
+      for (int pass = 0; pass < 2; ++pass) {
+        gemm<double>(c.s, OpT, OpN, r, q2, M, 1.0, U, r, 0, kick_buf, q2, 0, 0.0, Rk, q2, 0, 1);
+        gemm<double>(c.s, OpN, OpN, M, q2, r, -1.0, U, r, 0, Rk, q2, 0, 1.0, kick_buf, q2, 0, 1);
+      }
+      const int room_k = std::min(room - r, q2);
+      if (room_k > 0) {
+        kq = dcholqr(c, M, q2, kick_buf, q2, Qk, Rk, 1e-13);
+        kk = std::min(kq, room_k);
+      }
+      // new z core
+      int kz = dcholqr(c, q0 * ml, q2, zbuf, q2, Qk + (size_t)M * q2, Rk, 1e-13);
+      if (kz == 0) {
+        fill_random(c.s, zbuf, (long)q0 * ml * q2, 977ULL + l);
+        kz = dcholqr(c, q0 * ml, q2, zbuf, q2, Qk + (size_t)M * q2, Rk, 1e-13);
+      }
+      c.d2d(zc[l], Qk + (size_t)M * q2, (size_t)q0 * ml * kz);
+      zr[l + 1] = kz;
+    }
+    const int rn = r + kk;
+    // x_l = [U | Qk(:, :kk)]
+    copy2d(c.s, M, r, U, r, xc[l], rn);
+    if (kk > 0) copy2d(c.s, M, kk, Qk, kq, xc[l] + r, rn);
+    // x_{l+1} = [W; 0] x1 x_{l+1}
+    mode1<double>(c, r, r2, m1, r3, W, xc[l + 1], tmp, 0.0);
+    c.d2d(xc[l + 1], tmp, (size_t)r * m1 * r3);
+    if (kk > 0) fill(c.s, xc[l + 1] + (size_t)r * m1 * r3, (long)kk * m1 * r3, 0.0);
+    xr[l + 1] = rn;
+    // the next z core's left rank follows z_l; its content is rebuilt at l+1
+    update_left(l);
+  }
+
+  // ---- right-to-left split at core l (l > 0) -----------------------------
+  void step_left(int l, double delta) {
+    const int r1 = xr[l], r2 = xr[l + 1], ml = m[l], s0 = sr[l], s1 = sr[l + 1];
+    const int q1 = zr[l], q2 = zr[l + 1], r0 = xr[l - 1], mp = m[l - 1];
+    const int M = ml * r2;
+    const int room = std::max(1, maxrank[l]);
+    // u^T (m r2 x r1) = U W  ->  u = W^T U^T
+    transpose(c.s, r1, M, u, M, tmp, r1);
+    const int r = trunc_svd(c, M, r1, tmp, r1, delta, room, U, W);
+    // uk = W^T U^T  (r1 x m r2)
+    gemm<double>(c.s, OpT, OpT, r1, M, r, 1.0, W, r1, 0, U, r, 0, 0.0, y, M, 0, 1);
+    int kk = 0, kq = 0;
+    if (kick > 0 && q1 > 0) {
+      // A1 = ZXI_l x1 uk (q1 x m x r2);  S = K x2 A1 + ZXL_l x1 uk
+      mode1<double>(c, q1, r1, ml, r2, ZXI[l], y, A1, 0.0);
+      mode2<double>(c, q1, ml, ml, r2, p.dK[l], A1, S, 0.0);
+      mode1<double>(c, q1, r1, ml, r2, ZXL[l], y, S, 1.0);
+      // kick = (ZB_l x1 b) x3 XB_{l+1} - (S + A1 x3 L_{l+1})   (q1 x m r2)
+      mode1<double>(c, q1, s0, ml, s1, ZB[l], bc[l], T1, 0.0);
+      mode3<double>(c, q1, ml, s1, r2, T1, XB[l + 1], kick_buf, 0.0);
+      axpby(c.s, (long)q1 * M, -1.0, S, 1.0, kick_buf);
+      mode3<double>(c, q1, ml, r2, r2, A1, L[l + 1], T2, 0.0);
+      axpby(c.s, (long)q1 * M, -1.0, T2, 1.0, kick_buf);
+      // z core: (ZB_l x1 b) x3 ZB_{l+1} - (S x3 ZXI_{l+1} + A1 x3 ZXL_{l+1})  (q1 x m x q2)
+      mode3<double>(c, q1, ml, s1, q2, T1, ZB[l + 1], zbuf, 0.0);
+      mode3<double>(c, q1, ml, r2, q2, S, ZXI[l + 1], T2, 0.0);
+      mode3<double>(c, q1, ml, r2, q2, A1, ZXL[l + 1], T2, 1.0);
+      axpby(c.s, (long)q1 * ml * q2, -1.0, T2, 1.0, zbuf);
+      // kick^T (M x q1), orthogonalise against U (M x r), orthonormalise
+      transpose(c.s, q1, M, kick_buf, M, T2, q1);
+      for (int pass = 0; pass < 2; ++pass) {
+        gemm<double>(c.s, OpT, OpN, r, q1, M, 1.0, U, r, 0, T2, q1, 0, 0.0, Rk, q1, 0, 1);
+        gemm<double>(c.s, OpN, OpN, M, q1, r, -1.0, U, r, 0, Rk, q1, 0, 1.0, T2, q1, 0, 1);
+      }
+      const int room_k = std::min(room - r, q1);
+      if (room_k > 0) {
+        kq = dcholqr(c, M, q1, T2, q1, Qk, Rk, 1e-13);
+        kk = std::min(kq, room_k);
+      }
+      // new z core (rows orthonormal): zbuf (q1 x m q2) -> transpose -> QR
+      transpose(c.s, q1, (long)ml * q2, zbuf, (long)ml * q2, T2, q1);
+      double* Qz = Qk + (size_t)M * q1;
+      int kz = dcholqr(c, ml * q2, q1, T2, q1, Qz, Rk, 1e-13);
+      if (kz == 0) {
+        fill_random(c.s, T2, (long)ml * q2 * q1, 1777ULL + l);
+        kz = dcholqr(c, ml * q2, q1, T2, q1, Qz, Rk, 1e-13);
+      }
+      transpose(c.s, (long)ml * q2, kz, Qz, kz, zc[l], (long)ml * q2);
+      zr[l] = kz;
+    }
+    const int rn = r + kk;
+    // x_l = [U^T ; Qk^T]  (rn x m r2)
+    transpose(c.s, M, r, U, r, xc[l], M);
+    if (kk > 0) transpose(c.s, M, kk, Qk, kq, xc[l] + (size_t)r * M, M);
+    // x_{l-1} = x_{l-1} x3 [W^T | 0]:  new[.., j] = sum_b x[.., b] W[j, b] for j < r
+    double* out = tmp;
+    mode3<double>(c, r0, mp, r1, r, xc[l - 1], W, out, 0.0);
+    copy2d(c.s, (long)r0 * mp, r, out, r, xc[l - 1], rn);
+    if (kk > 0) {
+      // zero columns r..rn-1
+      double* zcol = T2;
+      fill(c.s, zcol, (long)r0 * mp * kk, 0.0);
+      copy2d(c.s, (long)r0 * mp, kk, zcol, kk, xc[l - 1] + r, rn);
+    }
+    xr[l] = rn;
+    update_right(l);
+  }
+};
+
+}  // namespace
+
+int solve(Problem& p, const Ctx& c, const DTT& f, const DTT* x0, const SolveOptions& o, DTT& x, SolveReport& rep) {
+  Amen a(p, c, o);
+  return a.run(f, x0, x, rep);
+}
+
+}  // namespace t2s2

@@ -1,0 +1,134 @@
+"""GPU parity of the TT solve against the oracle's full-format solves.
+
+Bar (FP64): relative L2 distance to the dense-LU / complex-Schur solution of
+the collocation system <= 1e-10 (TT tolerance 1e-12), as required for the
+plain FP64 path; the FP64 residual reported by the library must equal the
+oracle's residual of the returned TT.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+import paper_2506_04732_amd as t2s2  # noqa: E402
+import workloads  # noqa: E402
+from paper_2506_04732_amd import TT, sources  # noqa: E402
+from oracle import collocation as col  # noqa: E402
+from oracle import metrics  # noqa: E402
+from oracle import spectral as sp  # noqa: E402
+from oracle import tt as ott  # noqa: E402
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _gpu_problem(prob, cap=None):
+    return t2s2.Problem(prob.d, prob.N, prob.eps, prob.beta, prob.scheme, rank_cap=cap or prob.rank_cap)
+
+
+def _oracle_system(prob):
+    ops = col.build_ops(prob.d, prob.N, prob.eps, prob.beta, prob.scheme)
+    Es, Ms = col.interior_factors(ops)
+    if prob.source == "sin_exp":
+        terms = col.manufactured_rhs_factors(ops, prob.eps, prob.beta)
+    else:
+        terms = col.gauss_rhs_factors(ops, prob.gauss.amp, prob.gauss.centre, prob.gauss.width)
+    return ops, ott.kron_sum_ttm(Es, Ms), terms
+
+
+def _gpu_source(p, prob):
+    if prob.source == "sin_exp":
+        fac = sources.sin_exp_factors(p)
+    else:
+        fac = sources.gaussian_factors(p, prob.gauss.amp, prob.gauss.centre, prob.gauss.width)
+    return sources.source_tt(p, fac)
+
+
+def test_2d_manufactured_matches_dense_lu():
+    prob = workloads.manufactured_2d(16)
+    _say(prob.name)
+    p = _gpu_problem(prob)
+    f = _gpu_source(p, prob)
+    r = p.solve(f, tol=1e-12, target=1e-12, max_sweeps=12)
+    ops, A, terms = _oracle_system(prob)
+    u = col.solve_dense(ops, col.separable_full(terms))
+    xg = r.x.to_numpy()
+    assert metrics.rel_frobenius(col.embed_interior(ott.full(xg)), u) <= 1e-10
+    assert r.converged
+    assert abs(r.residual - ott.residual_norm(A, xg, ott.separable_to_tt(terms))) <= 1e-13
+    # against the manufactured solution: spectral accuracy at N = 16 (1.3e-10)
+    X = np.meshgrid(ops[0]["x"], ops[1]["x"], indexing="ij")
+    exact = col.sin_exp(X[0]) * col.sin_exp(X[1])
+    assert metrics.rel_frobenius(col.embed_interior(ott.full(xg)), exact) < 1e-9
+
+
+def test_3d_transport_matches_schur():
+    prob = workloads.transport_3d(0)
+    _say(prob.name)
+    p = _gpu_problem(prob, cap=40)
+    f = _gpu_source(p, prob)
+    r = p.solve(f, tol=1e-12, target=1e-11, max_sweeps=20, kick=8)
+    ops, A, terms = _oracle_system(prob)
+    u = col.solve_schur(ops, col.separable_full(terms))
+    xg = r.x.to_numpy()
+    assert r.converged, (r.residual, r.history_residual)
+    assert metrics.rel_frobenius(ott.full(xg), u) <= 1e-10
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_6d_small_grid_matches_schur(seed):
+    prob = workloads.gauss_problem(6, 8, 1e-2, 3, seed=seed, tol=1e-12, rank_cap=64)
+    _say(prob.name)
+    p = _gpu_problem(prob)
+    f = _gpu_source(p, prob)
+    r = p.solve(f, tol=1e-12, target=1e-11, max_sweeps=30, kick=8)
+    ops, A, terms = _oracle_system(prob)
+    u = col.solve_schur(ops, col.separable_full(terms))
+    assert r.converged, (r.residual, r.history_residual)
+    assert metrics.rel_frobenius(ott.full(r.x.to_numpy()), u) <= 1e-9
+
+
+@pytest.mark.parametrize("case", ["d1", "N3", "ragged", "plain"])
+def test_edge_cases_match_dense(case):
+    _say("edge", case)
+    if case == "d1":
+        prob = workloads.gauss_problem(1, 20, 1e-3, 2, seed=5, tol=1e-12, rank_cap=4)
+    elif case == "N3":
+        prob = workloads.gauss_problem(3, [3, 9, 7], 1e-2, 2, seed=6, tol=1e-12, rank_cap=16)
+    elif case == "ragged":
+        prob = workloads.gauss_problem(4, [7, 12, 5, 10], 5e-3, 3, seed=7, tol=1e-12, rank_cap=48)
+    else:
+        prob = workloads.gauss_problem(3, 10, 1e-1, 2, seed=8, tol=1e-12, rank_cap=16, scheme=0)
+    p = _gpu_problem(prob)
+    f = _gpu_source(p, prob)
+    r = p.solve(f, tol=1e-12, target=1e-11, max_sweeps=20, kick=4)
+    ops, A, terms = _oracle_system(prob)
+    u = col.solve_dense(ops, col.separable_full(terms))[tuple(slice(1, -1) for _ in range(prob.d))]
+    assert r.converged, (r.residual, r.history_residual)
+    assert metrics.rel_frobenius(ott.full(r.x.to_numpy()), u) <= 1e-9
+
+
+def test_not_converged_reports_status_and_keeps_iterate():
+    prob = workloads.transport_3d(0)
+    _say("enotconv")
+    p = _gpu_problem(prob, cap=8)
+    f = _gpu_source(p, prob)
+    r = p.solve(f, tol=1e-12, target=1e-14, max_sweeps=2, kick=2)
+    assert not r.converged and r.status == 3
+    _, A, terms = _oracle_system(prob)
+    xg = r.x.to_numpy()
+    assert abs(r.residual - ott.residual_norm(A, xg, ott.separable_to_tt(terms))) <= 1e-10
+    assert r.residual > 1e-14
+
+
+def test_warm_start_from_solution_converges_in_one_sweep():
+    prob = workloads.gauss_problem(3, 16, 5e-3, 3, seed=9, tol=1e-12, rank_cap=24)
+    _say("warm start")
+    p = _gpu_problem(prob)
+    f = _gpu_source(p, prob)
+    r1 = p.solve(f, tol=1e-12, target=1e-11, max_sweeps=20)
+    assert r1.converged
+    x0 = TT.from_numpy(r1.x.to_numpy())
+    r2 = p.solve(f, x0=x0, tol=1e-12, target=1e-11, max_sweeps=20)
+    assert r2.converged and r2.sweeps <= 2

@@ -1,0 +1,111 @@
+"""GPU parity of the TT building blocks (through the C ABI) against the oracle.
+
+Tolerances (FP64): the library's operator is assembled from its own host 1D
+builder, which agrees with the oracle's to ~1e-14 relative; the contractions
+themselves are exact up to rounding, so element-wise agreement is checked at
+1e-12 relative to the largest entry.  Norms of nearly cancelling residuals are
+checked in absolute terms against ||f|| (the orthogonalisation keeps absolute
+accuracy of a few ulps of ||f||).
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+import paper_2506_04732_amd as t2s2  # noqa: E402
+from paper_2506_04732_amd import TT  # noqa: E402
+from oracle import collocation as col  # noqa: E402
+from oracle import tt as ott  # noqa: E402
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _rand_tt(rng, ns, ranks):
+    return [rng.standard_normal((ranks[l], ns[l], ranks[l + 1])) for l in range(len(ns))]
+
+
+def _oracle_operator(p):
+    ops = col.build_ops(p.d, p.N, p.eps, p.beta, p.scheme)
+    Es, Ms = col.interior_factors(ops)
+    return ott.kron_sum_ttm(Es, Ms)
+
+
+CASES = [
+    (1, [12], [1, 1]),
+    (2, [16, 16], [1, 3, 1]),
+    (3, [9, 5, 11], [1, 4, 7, 1]),
+    (3, [3, 8, 6], [1, 1, 5, 1]),          # N = 3: one interior unknown
+    (4, [12, 12, 12, 12], [1, 5, 9, 6, 1]),
+    (6, [32] * 6, [1, 30, 70, 100, 65, 30, 1]),   # ragged ranks, 6D N = 32 modes
+]
+
+
+@pytest.mark.parametrize("d,N,ranks", CASES)
+def test_matvec_matches_oracle(d, N, ranks):
+    _say("matvec", d, N, ranks)
+    rng = np.random.default_rng(d * 100 + sum(ranks))
+    beta = rng.standard_normal(d)
+    p = t2s2.Problem(d, N, 1e-2, beta, 1, rank_cap=8)
+    ms = [v - 2 for v in N]
+    x = _rand_tt(rng, ms, ranks)
+    y = p.tt_matvec(TT.from_numpy(x)).to_numpy()
+    yo = ott.matvec(_oracle_operator(p), x)
+    assert [c.shape for c in y] == [c.shape for c in yo]
+    for a, b in zip(y, yo):
+        assert np.abs(a - b).max() <= 1e-12 * max(1.0, np.abs(b).max())
+    if np.prod(ms) <= 5000:
+        np.testing.assert_allclose(ott.full(y), ott.full(yo), atol=1e-11 * np.abs(ott.full(yo)).max())
+
+
+@pytest.mark.parametrize("d,N,ranks", CASES[:5])
+def test_norm_matches_oracle(d, N, ranks):
+    _say("norm", d, N, ranks)
+    rng = np.random.default_rng(7 + d)
+    p = t2s2.Problem(d, N, 1e-2, np.ones(d), 1, rank_cap=8)
+    x = _rand_tt(rng, [v - 2 for v in N], ranks)
+    assert abs(p.tt_norm(TT.from_numpy(x)) - ott.norm(x)) <= 1e-13 * ott.norm(x)
+
+
+def test_residual_norm_of_random_and_near_solution():
+    _say("residual 3D N=10")
+    rng = np.random.default_rng(3)
+    d, N = 3, 10
+    p = t2s2.Problem(d, N, 2e-2, [0.6, -0.3, 0.8], 1, rank_cap=16)
+    A = _oracle_operator(p)
+    f = _rand_tt(rng, [8] * 3, [1, 2, 2, 1])
+    x = _rand_tt(rng, [8] * 3, [1, 3, 3, 1])
+    g = p.tt_residual_norm(TT.from_numpy(x), TT.from_numpy(f))
+    o = ott.residual_norm(A, x, f)
+    assert abs(g - o) <= 1e-12 * o
+    # near-solution: exact full solution -> TT-SVD, perturbed at 1e-9
+    ops = col.build_ops(d, N, p.eps, p.beta, 1)
+    u = col.solve_schur(ops, ott.full(f))
+    xs = ott.tt_svd(u, 1e-15)
+    xs[0] = xs[0] * (1 + 1e-9)
+    g = p.tt_residual_norm(TT.from_numpy(xs), TT.from_numpy(f))
+    o = ott.residual_norm(A, xs, f)
+    assert o < 1e-7
+    assert abs(g - o) <= 1e-3 * o + 1e-14
+
+
+@pytest.mark.parametrize("tol", [1e-3, 1e-8, 1e-12])
+def test_round_matches_oracle(tol):
+    _say("round", tol)
+    rng = np.random.default_rng(11)
+    ms = [10, 9, 12, 8, 10]
+    x = _rand_tt(rng, ms, [1, 4, 5, 6, 3, 1])
+    z = ott.add(x, _rand_tt(rng, ms, [1, 3, 3, 3, 3, 1]), 1.0, 1e-4)   # decaying second part
+    y = ott.add(z, z, 1.0, 1.0)                                           # = 2z, redundant ranks
+    p = t2s2.Problem(5, [v + 2 for v in ms], 1e-2, np.ones(5), 1, rank_cap=32)
+    g = TT.from_numpy(y)
+    p.tt_round(g, tol)
+    gr = g.to_numpy()
+    orr = ott.round_tt(y, tol)
+    full_y = ott.full(y)
+    err_g = np.linalg.norm(ott.full(gr) - full_y)
+    assert err_g <= tol * np.linalg.norm(full_y) * (1 + 1e-8) + 1e-13 * np.linalg.norm(full_y)
+    # same ranks as the oracle's SVD rounding (ties aside) and the same tensor
+    assert max(ott.ranks(gr)) <= max(ott.ranks(orr)) + 1
+    assert np.linalg.norm(ott.full(gr) - ott.full(orr)) <= 2 * tol * np.linalg.norm(full_y) + 1e-12 * np.linalg.norm(full_y)
