@@ -1,0 +1,207 @@
+#!/usr/bin/env python3
+"""Benchmark: 6D steady T^2S^2 tensor-train solve to relative residual 1e-8 on one MI355X.
+
+Workload (one "step" = one complete cold-start solve of the whole hot path:
+1D ingredients already built, operator TT-matrix, sweeps with local solves,
+truncations, enrichment, interface updates and the FP64 residual test):
+  -eps Lap u + beta . grad u = f on [-1,1]^6, u = 0 on the boundary,
+  N = 32 GLL nodes per dimension (30 interior unknowns, 7.3e8 interior
+  unknowns in total, never formed), eps = 1e-3, beta = seeded unit vector
+  (seed 0), f = 8-term separable Gaussian mixture (exact TT rank 8),
+  superconsistent collocation, stop at ||f - L x|| / ||f|| <= 1e-8 (FP64).
+
+Prints ONE JSON line.  value = seconds per solve (lower is better).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+SOLVE_OPTS = dict(tol=3e-10, target=9e-9, max_sweeps=40, kick=24, init_rank=64, check_every=0, seed=0)
+RANK_CAP = 256
+WORKLOAD = "6d_N32_eps1e-3_gauss8_seed0"
+
+# MI355X peaks used for the roofline (published figures)
+PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6
+
+
+def _hbm_classes():
+    return {"ttm_matvec", "kron_trisolve"}
+
+
+def roofline_entry(name: str, st: dict, traffic=None) -> dict:
+    avg_s = st["ms"] / max(st["launches"], 1) / 1e3
+    per_launch_bytes = st["bytes"] / max(st["launches"], 1)
+    per_launch_flops = st["flops"] / max(st["launches"], 1)
+    if name in _hbm_classes():
+        achieved = per_launch_bytes / avg_s / 1e9 if avg_s > 0 else 0.0
+        return {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "launches": st["launches"],
+                "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": per_launch_bytes}
+    achieved = per_launch_flops / avg_s / 1e12 if avg_s > 0 else 0.0
+    return {"kernel": name, "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic, "launches": st["launches"],
+            "avg_launch_us": avg_s * 1e6, "algorithmic_flops_per_launch": per_launch_flops}
+
+
+def load_traffic(kernel: str):
+    """HBM bytes per launch from committed rocprofv3 --pmc summaries, if present."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{WORKLOAD}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as fh:
+            return json.load(fh).get("hbm_bytes_per_launch")
+    except Exception:
+        return None
+
+
+def cpu_baseline(prob, gpu_result, sweeps: int) -> dict:
+    """The oracle (NumPy FP64 AMEn with exact Kronecker local solves) on the
+    host cores: the first `sweeps` sweeps of the same workload, timed, then
+    scaled to the full solve by the GPU's own time ratio (full / first sweeps)."""
+    import numpy as np
+    from oracle import amen as oamen
+    from oracle import collocation as col
+    from oracle import tt as ott
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count() or 1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    ops = col.build_ops(prob.d, prob.N, prob.eps, prob.beta, prob.scheme)
+    Es, Ms = col.interior_factors(ops)
+    A = ott.kron_sum_ttm(Es, Ms)
+    b = ott.separable_to_tt(col.gauss_rhs_factors(ops, prob.gauss.amp, prob.gauss.centre, prob.gauss.width))
+    t0 = time.perf_counter()
+    rng = np.random.default_rng(SOLVE_OPTS["seed"])
+    r0 = SOLVE_OPTS["init_rank"]
+    ms = [n - 2 for n in prob.N]
+    rs = [1] + [min(r0, 30 ** min(l, prob.d - l)) for l in range(1, prob.d)] + [1]
+    x0 = [rng.standard_normal((rs[l], ms[l], rs[l + 1])) for l in range(prob.d)]
+    _, info = oamen.solve(A, b, x0=x0, tol=SOLVE_OPTS["tol"], target=1e-30, max_sweeps=sweeps,
+                          kick=SOLVE_OPTS["kick"], rank_cap=RANK_CAP, local_solver="kron", kron_factors=(Es, Ms))
+    t_cpu = time.perf_counter() - t0
+    hist = gpu_result.history_time_ms
+    k = min(sweeps, len(hist))
+    gpu_prefix = hist[k - 1] / 1e3
+    gpu_total = gpu_result.time_ms / 1e3
+    est = t_cpu * gpu_total / gpu_prefix if gpu_prefix > 0 else None
+    return {"value": est, "unit": "s", "cores": int(threads), "kind": "oracle",
+            "sample": f"first {sweeps} sweeps of the same 6D N=32 solve (oracle max rank "
+                      f"{info['history'][-1]['max_rank']}, residual {info['history'][-1]['residual']:.2e}) "
+                      f"took {t_cpu:.1f} s; scaled by the GPU full/prefix time ratio "
+                      f"({gpu_total:.3f} s / {gpu_prefix:.3f} s)",
+            "measured_s": t_cpu, "measured_sweeps": sweeps}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sweeps", type=int, default=3)
+    ap.add_argument("--no-oracle-check", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 256 MiB device-to-device copy 8 times (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(8):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": a.numel() * 8, "copy_probe_bytes_written": b.numel() * 8,
+                          "launches": 8}), flush=True)
+        return
+    if args.gpus != 1:
+        print(f"bench.py runs one solve on one GPU; --gpus {args.gpus} is not supported (the solve is a single-GPU "
+              f"workload and this build has no multi-GPU path)", file=sys.stderr)
+        sys.exit(2)
+    rank = int(os.environ.get("RANK", "0"))
+
+    import torch
+    import paper_2506_04732_amd as t2s2
+    import workloads
+    from paper_2506_04732_amd import TT, sources
+
+    prob = workloads.steady_6d(0, 32)
+    p = t2s2.Problem(prob.d, prob.N, prob.eps, prob.beta, prob.scheme, rank_cap=RANK_CAP)
+    f = sources.source_tt(p, sources.gaussian_factors(p, prob.gauss.amp, prob.gauss.centre, prob.gauss.width))
+    x = TT.empty(p.m, RANK_CAP)
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        p.solve(f, out=x, **SOLVE_OPTS)
+    results = []
+    t2s2.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        results.append(p.solve(f, out=x, **SOLVE_OPTS))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stats = t2s2.timing_read()
+    t2s2.timing_enable(False)
+    sec = (t1 - t0) / args.steps
+    last = results[-1]
+
+    dominant = max(stats, key=lambda k: stats[k]["ms"])
+    roof = roofline_entry(dominant, stats[dominant], load_traffic(dominant))
+    kernels = {k: {"ms_per_solve": v["ms"] / args.steps, "launches_per_solve": v["launches"] / args.steps}
+               for k, v in stats.items() if v["launches"]}
+    ttmv = roofline_entry("ttm_matvec", stats["ttm_matvec"]) if stats["ttm_matvec"]["launches"] else None
+
+    check = {"library_residual": last.residual, "converged": all(r.converged for r in results)}
+    if not args.no_oracle_check:
+        from oracle import collocation as col
+        from oracle import tt as ott
+        ops = col.build_ops(prob.d, prob.N, prob.eps, prob.beta, prob.scheme)
+        Es, Ms = col.interior_factors(ops)
+        b = ott.separable_to_tt(col.gauss_rhs_factors(ops, prob.gauss.amp, prob.gauss.centre, prob.gauss.width))
+        check["oracle_residual"] = ott.residual_norm(ott.kron_sum_ttm(Es, Ms), last.x.to_numpy(), b)
+
+    out = {
+        "metric": "6D TT solve seconds to rel. resid 1e-8; HBM GB/s; sweeps warm vs cold",
+        "value": sec,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": False,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "d": prob.d, "N": prob.N[0], "eps": prob.eps, "source_rank": 8,
+                   "target_residual": 1e-8, "stop_at": SOLVE_OPTS["target"], "tol": SOLVE_OPTS["tol"],
+                   "kick": SOLVE_OPTS["kick"], "init_rank": SOLVE_OPTS["init_rank"], "rank_cap": RANK_CAP},
+        "sweeps_cold": last.sweeps,
+        "sweeps_warm": None,
+        "final_ranks": last.ranks,
+        "residual": last.residual,
+        "roofline": roof,
+        "ttm_matvec_hbm": ttmv,
+        "kernels": kernels,
+        "check": check,
+    }
+    if rank == 0 and not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob, last, args.cpu_sweeps)
+    else:
+        out["cpu_baseline"] = None
+    if rank == 0:
+        print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -93,7 +93,8 @@ typedef struct {
   int rank_cap;        /* max TT rank of x (<= the problem's rank_cap)       */
   int init_rank;       /* rank of the seeded random start when x0 is NULL    */
   unsigned long long seed;
-  int check_every;     /* evaluate the FP64 residual every this many sweeps  */
+  int check_every;     /* FP64 residual every this many sweeps; 0: only once
+                          the largest local residual is <= 10 * target      */
   int verbose;         /* 1: print one line per sweep on stderr              */
 } t2s2_options;
 
@@ -189,6 +190,21 @@ int t2s2_tt_round(t2s2_problem* p, t2s2_tt* x, double tol, int rmax, void* strea
 int t2s2_solve(t2s2_problem* p, const t2s2_tt* f, const t2s2_tt* x0,
                const t2s2_options* opts, t2s2_tt* x_out, t2s2_report* rep,
                void* stream);
+
+/* --------------------------------------------------------- diagnostics ---
+ * Kernel-class timing for benchmarks.  While enabled, every library kernel
+ * launch is bracketed by two HIP events on its stream (a small overhead per
+ * launch) and its algorithmic bytes and flops (the operands the operation
+ * must read and write once, and its arithmetic count) are accumulated.
+ * t2s2_timing_enable(1) resets the counters; (0) stops recording.
+ * Classes: 0 real GEMM, 1 complex GEMM, 2 TT-matvec core, 3 Schur QR,
+ * 4 Hessenberg, 5 Jacobi SVD, 6 Cholesky, 7 triangular inverse,
+ * 8 triangular eigenvectors, 9 Kronecker-sum triangular solves, 10 other.
+ * t2s2_timing_read synchronises the device work it reads; EINVAL for a bad
+ * class. */
+int t2s2_timing_enable(int on);
+int t2s2_timing_read(int cls, double* total_ms, long long* launches, double* bytes, double* flops);
+const char* t2s2_timing_class_name(int cls);
 
 /* Defaults: tol 1e-10, target 1e-8, max_sweeps 40, kick 8, rank_cap = the
  * problem's, init_rank 2, seed 0, check_every 1, verbose 0. */

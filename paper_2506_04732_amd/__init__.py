@@ -45,6 +45,21 @@ def matrices_1d(N: int, eps: float, beta: float, scheme: int = SCHEME_SC):
     return E, D1, D2
 
 
+def timing_enable(on: bool = True) -> None:
+    """Start (reset) or stop per-kernel-class event timing inside the library."""
+    check(lib().t2s2_timing_enable(1 if on else 0))
+
+
+def timing_read() -> dict:
+    """{class name: {"ms", "launches", "bytes", "flops"}} accumulated since timing_enable(True)."""
+    out = {}
+    for cls, name in enumerate(_lib.TIMING_CLASSES):
+        ms, n, b, f = C.c_double(), C.c_longlong(), C.c_double(), C.c_double()
+        check(lib().t2s2_timing_read(cls, C.byref(ms), C.byref(n), C.byref(b), C.byref(f)))
+        out[name] = {"ms": ms.value, "launches": int(n.value), "bytes": b.value, "flops": f.value}
+    return out
+
+
 def _torch():
     import torch
     return torch

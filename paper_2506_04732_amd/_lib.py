@@ -15,7 +15,10 @@ EXPORTED = [
     "t2s2_last_error", "t2s2_nodes", "t2s2_matrices_1d", "t2s2_problem_create", "t2s2_problem_destroy",
     "t2s2_problem_operator", "t2s2_problem_colloc", "t2s2_tt_matvec", "t2s2_tt_norm",
     "t2s2_tt_residual_norm", "t2s2_tt_round", "t2s2_solve", "t2s2_default_options",
+    "t2s2_timing_enable", "t2s2_timing_read", "t2s2_timing_class_name",
 ]
+TIMING_CLASSES = ["gemm_f64", "gemm_c128", "ttm_matvec", "schur_qr", "hessenberg", "jacobi_svd", "cholesky",
+                  "trtri", "trevec", "kron_trisolve", "other"]
 
 
 class TTStruct(C.Structure):
@@ -77,8 +80,12 @@ def lib() -> C.CDLL:
                              C.POINTER(TTStruct), C.POINTER(Report), vp]
     L.t2s2_default_options.argtypes = [C.POINTER(Options)]
     L.t2s2_default_options.restype = None
+    L.t2s2_timing_enable.argtypes = [C.c_int]
+    L.t2s2_timing_read.argtypes = [C.c_int, dp, C.POINTER(C.c_longlong), dp, dp]
+    L.t2s2_timing_class_name.argtypes = [C.c_int]
+    L.t2s2_timing_class_name.restype = C.c_char_p
     for name in EXPORTED:
-        if name not in ("t2s2_last_error", "t2s2_default_options"):
+        if name not in ("t2s2_last_error", "t2s2_default_options", "t2s2_timing_class_name"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L

@@ -16,7 +16,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libt2s2.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["spectral_host.cpp", "gemm.hip", "tt_kernels.hip", "dense_small.hip", "linalg.hip", "solver.hip", "api.hip"]
+SOURCES = ["spectral_host.cpp", "timing.cpp", "gemm.hip", "tt_kernels.hip", "dense_small.hip", "schur.hip", "linalg.hip", "solver.hip", "api.hip"]
 
 ARCH = os.environ.get("T2S2_ARCH", "gfx950")
 # -packed-fp32-ops: hipcc must not emit packed FP32 instructions
@@ -34,7 +34,7 @@ def _hipcc() -> str:
 def _compile(src: str) -> str:
     obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
     cmd = [_hipcc()] + HIPFLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
-    if src.endswith(".cpp"):
+    if src == "spectral_host.cpp":
         cmd = [_hipcc()] + ["-O3", "-std=c++17", "-fPIC", "-I", CSRC, "-I", INCLUDE, "-c",
                             os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)

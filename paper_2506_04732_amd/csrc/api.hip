@@ -17,6 +17,8 @@ struct t2s2_problem {
 };
 
 namespace t2s2 {
+void timing_set(bool on);
+void timing_read(int cls, double* ms, long* launches, double* bytes, double* flops);
 static thread_local std::string g_last_error;
 void set_last_error(const std::string& msg) { g_last_error = msg; }
 }  // namespace t2s2
@@ -198,6 +200,31 @@ int t2s2_tt_round(t2s2_problem* p, t2s2_tt* x, double tol, int rmax, void* strea
     for (int l = 0; l <= xd.d; ++l) x->ranks[l] = xd.r[l];
     return T2S2_OK;
   });
+}
+
+int t2s2_timing_enable(int on) {
+  return guarded([&] {
+    t2s2::timing_set(on != 0);
+    return T2S2_OK;
+  });
+}
+
+int t2s2_timing_read(int cls, double* total_ms, long long* launches, double* bytes, double* flops) {
+  return guarded([&] {
+    T2S2_CHECK(cls >= 0 && cls < t2s2::KC_COUNT, "timing class out of range");
+    T2S2_CHECK(total_ms && launches && bytes && flops, "NULL argument");
+    long n = 0;
+    t2s2::timing_read(cls, total_ms, &n, bytes, flops);
+    *launches = n;
+    return T2S2_OK;
+  });
+}
+
+const char* t2s2_timing_class_name(int cls) {
+  static const char* names[] = {"gemm_f64", "gemm_c128", "ttm_matvec", "schur_qr", "hessenberg", "jacobi_svd",
+                                "cholesky", "trtri", "trevec", "kron_trisolve", "other"};
+  if (cls < 0 || cls >= t2s2::KC_COUNT) return "";
+  return names[cls];
 }
 
 void t2s2_default_options(t2s2_options* o) {

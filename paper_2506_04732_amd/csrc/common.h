@@ -9,6 +9,29 @@
 
 namespace t2s2 {
 
+// Kernel classes timed by the optional event instrumentation.
+enum KernelClass {
+  KC_GEMM = 0, KC_GEMM_C, KC_TTMV, KC_SCHUR, KC_HESS, KC_JACOBI, KC_CHOL, KC_TRTRI, KC_TREVEC, KC_KRONSOLVE,
+  KC_OTHER, KC_COUNT
+};
+
+// When enabled, every instrumented launch is bracketed by two HIP events on
+// its stream; algorithmic bytes / flops of the launch are accumulated.
+void timing_record_begin(hipStream_t s, int cls, double bytes, double flops);
+void timing_record_end(hipStream_t s);
+bool timing_enabled();
+
+struct TimedScope {
+  hipStream_t s;
+  bool on;
+  TimedScope(hipStream_t s_, int cls, double bytes, double flops) : s(s_), on(timing_enabled()) {
+    if (on) timing_record_begin(s, cls, bytes, flops);
+  }
+  ~TimedScope() {
+    if (on) timing_record_end(s);
+  }
+};
+
 // Error carried from deep inside the library to the C ABI boundary.
 struct Error : public std::runtime_error {
   int code;

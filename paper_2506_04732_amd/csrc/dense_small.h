@@ -17,11 +17,16 @@ void jacobi_rows(hipStream_t s, int k, int c, double* B, double* JT, double* U, 
                  int* info, int max_sweeps = 60);
 // A (n x n) <- H = Q^T A Q upper Hessenberg, QT <- Q^T; work >= 2n doubles.
 void hessenberg(hipStream_t s, int n, double* A, double* QT, double* work);
-// Hr real upper Hessenberg (n x n); ZT (n x n complex) holds the initial Z^T
-// and receives (Z_in Z)^T with Hr = Z T Z^H; T complex upper triangular;
-// Hw: n*n complex workspace (used when the packed form exceeds LDS);
-// info[0] = QR sweeps (negative if the iteration cap was hit).
-void schur_qr(hipStream_t s, int n, const double* Hr, double2* Hw, double2* ZT, double2* T, int* info);
+// Real Schur form of a real upper Hessenberg H (n x n, n <= 512) by the
+// Francis double-shift QR iteration: H = Z T Z^T, T quasi upper triangular
+// (1 x 1 and 2 x 2 diagonal blocks).  ZT (n x n) holds an initial Z^T on input
+// and receives (Z_in Z)^T; Hwork: n*n doubles (used when H exceeds LDS);
+// info[0] = Francis steps (negative if the iteration cap was hit).
+void schur_francis(hipStream_t s, int n, const double* H, double* Hwork, double* ZT, double* T, int* info);
+// Real Schur form -> complex Schur form: Tc = P^H T P upper triangular and
+// ZTc = (Z P)^T with P block diagonal unitary; bstart: n ints, U: 2n complex.
+void rsf2csf(hipStream_t s, int n, const double* T, const double* ZT, double2* Tc, double2* ZTc, int* bstart,
+             double2* U);
 // Unit upper-triangular Y with T Y = Y diag(T).
 void trevec(hipStream_t s, int n, const double2* T, double2* Y);
 

@@ -37,6 +37,7 @@ __device__ inline double block_max(double v, double* red) {
 // matrix (row-major, ld n), skipping every column whose pivot, after the
 // updates of the previous columns, is <= tau * max_i G[i][i]: such a column
 // gets a zero row in R and mask 0.  count[0] = number of kept columns.
+template <bool LDS>
 __global__ void __launch_bounds__(kNT) chol_skip_kernel(int n, const double* __restrict__ G, double* R,
                                                        int* __restrict__ mask, int* __restrict__ count,
                                                        double tau) {
@@ -44,8 +45,8 @@ __global__ void __launch_bounds__(kNT) chol_skip_kernel(int n, const double* __r
   __shared__ double red[kNT / 64];
   __shared__ double s_piv;
   __shared__ int s_keep, s_count;
-  const bool in_lds = (long)n * n <= kLdsDoubles;
-  double* W = in_lds ? lds : R;
+  double* W;
+  if constexpr (LDS) W = lds; else W = R;
   const long nn = (long)n * n;
   for (long e = threadIdx.x; e < nn; e += blockDim.x) W[e] = G[e];
   __syncthreads();
@@ -140,6 +141,7 @@ __global__ void __launch_bounds__(kNT) trtri_upper_kernel(int n, const T* __rest
 // then sorted by decreasing norm: sigma[i] = ||Wt[i, :]||, so B = U diag(sigma) V^T
 // with V^T the normalised rows of Wt.  Pairs are visited in round-robin
 // tournament order, k/2 disjoint pairs per round, one wavefront per pair.
+template <int MODE>
 __global__ void __launch_bounds__(kNT) jacobi_rows_kernel(int k, int c, double* __restrict__ B,
                                                           double* __restrict__ JT, double* __restrict__ U,
                                                           double* __restrict__ Wt, double* __restrict__ sigma,
@@ -147,10 +149,10 @@ __global__ void __launch_bounds__(kNT) jacobi_rows_kernel(int k, int c, double* 
   extern __shared__ double lds[];
   __shared__ int s_rot;
   const long bsz = (long)k * c, jsz = (long)k * k;
-  const bool b_lds = bsz <= kLdsDoubles;
-  const bool j_lds = b_lds && (bsz + jsz) <= kLdsDoubles;
-  double* Bw = b_lds ? lds : B;
-  double* Jw = j_lds ? lds + bsz : JT;
+  double* Bw;
+  double* Jw;
+  if constexpr (MODE >= 1) Bw = lds; else Bw = B;
+  if constexpr (MODE == 2) Jw = lds + bsz; else Jw = JT;
   for (long e = threadIdx.x; e < bsz; e += blockDim.x) Bw[e] = B[e];
   for (long e = threadIdx.x; e < jsz; e += blockDim.x) Jw[e] = ((e / k) == (e % k)) ? 1.0 : 0.0;
   __syncthreads();
@@ -247,16 +249,26 @@ __global__ void __launch_bounds__(kNT) jacobi_rows_kernel(int k, int c, double* 
 // ------------------------------------------------- Hessenberg reduction
 // A (n x n, real, row-major) -> H = Q^T A Q upper Hessenberg, by Householder
 // reflectors on columns 0..n-3.  QT receives Q^T.
+template <bool LDS>
 __global__ void __launch_bounds__(kNT) hessenberg_kernel(int n, double* __restrict__ A, double* __restrict__ QT,
                                                          double* __restrict__ work) {
   extern __shared__ double lds[];
   __shared__ double red[kNT / 64];
   __shared__ double s_alpha, s_vnorm2;
   const long nn = (long)n * n;
-  const bool in_lds = nn + 2L * n <= kLdsDoubles;
-  double* H = in_lds ? lds : A;
-  double* v = in_lds ? lds + nn : work;      // reflector (n)
-  double* w = in_lds ? lds + nn + n : work + n;  // products (n)
+  constexpr bool in_lds = LDS;
+  double* H;
+  double* v;  // reflector (n)
+  double* w;  // products (n)
+  if constexpr (LDS) {
+    H = lds;
+    v = lds + nn;
+    w = lds + nn + n;
+  } else {
+    H = A;
+    v = work;
+    w = work + n;
+  }
   if (in_lds)
     for (long e = threadIdx.x; e < nn; e += blockDim.x) H[e] = A[e];
   for (long e = threadIdx.x; e < nn; e += blockDim.x) QT[e] = ((e / n) == (e % n)) ? 1.0 : 0.0;
@@ -348,178 +360,6 @@ __global__ void __launch_bounds__(kNT) hessenberg_kernel(int n, double* __restri
     for (long e = threadIdx.x; e < nn; e += blockDim.x) A[e] = H[e];
 }
 
-// --------------------------------------------------- complex Schur form
-// H (n x n real upper Hessenberg) = Z T Z^H with T complex upper triangular,
-// by implicitly shifted single-shift QR (Wilkinson shifts, exceptional shifts
-// every 10 stagnant iterations, deflation on negligible subdiagonals).
-// ZT holds Z^T on input (the Hessenberg Q^T, so that the result is the Schur
-// basis of the original matrix) and is updated by every rotation; rows of ZT
-// are columns of Z, so each update is a contiguous row operation.
-// Storage of H during the iteration: LDS in packed form (row i keeps columns
-// max(0, i-2) .. n-1; the bulge lives two below the diagonal) when it fits,
-// else the full complex matrix Hw in global memory.
-struct HView {
-  double2* base;
-  int n;
-  bool packed;
-  __device__ long off(int i, int j) const {
-    if (!packed) return (long)i * n + j;
-    // rows 0, 1 start at column 0; row i >= 2 starts at column i-2
-    long o;
-    if (i <= 1) {
-      o = (long)i * n;
-    } else {
-      // 2n for rows 0,1 plus sum_{t=2}^{i-1} (n - t + 2)
-      const long m = i - 2;  // rows 2..i-1
-      o = 2L * n + m * (n + 2) - (m * (m + 3)) / 2;
-      o -= 0;
-      return o + (j - (i - 2));
-    }
-    return o + j;
-  }
-  __device__ double2& at(int i, int j) const { return base[off(i, j)]; }
-};
-
-__device__ inline long packed_size(int n) {
-  // 2n + sum_{t=2}^{n-1} (n - t + 2)
-  const long m = n - 2;
-  return 2L * n + (m > 0 ? m * (n + 2) - (m * (m + 3)) / 2 : 0);
-}
-
-__global__ void __launch_bounds__(kNT) schur_qr_kernel(int n, const double* __restrict__ Hr,
-                                                       double2* __restrict__ Hw, double2* __restrict__ ZT,
-                                                       double2* __restrict__ T, int* __restrict__ info,
-                                                       int max_iter_total) {
-  extern __shared__ double lds[];
-  __shared__ double2 s_cs[2];
-  __shared__ int s_l, s_hi, s_iter, s_done;
-  __shared__ double2 s_mu;
-  const long psz = packed_size(n);
-  const bool packed = psz * 2 <= kLdsDoubles;
-  HView H{packed ? reinterpret_cast<double2*>(lds) : Hw, n, packed};
-  // load real Hessenberg into complex storage
-  for (long e = threadIdx.x; e < (long)n * n; e += blockDim.x) {
-    const int i = (int)(e / n), j = (int)(e % n);
-    if (j >= i - 2 || !packed) H.at(i, j) = make_double2(j >= i - 1 ? Hr[e] : 0.0, 0.0);
-  }
-  if (threadIdx.x == 0) { s_hi = n - 1; s_iter = 0; s_done = 0; }
-  __syncthreads();
-  const double ulp = DBL_EPSILON;
-  int total = 0;
-  while (true) {
-    // ---- deflation scan and shift (thread 0), broadcast through LDS
-    if (threadIdx.x == 0) {
-      int hi = s_hi;
-      while (hi >= 0) {
-        if (hi == 0) { hi = -1; break; }
-        int l = hi;
-        while (l > 0) {
-          const double2 sub = H.at(l, l - 1);
-          double s = fabs(H.at(l - 1, l - 1).x) + fabs(H.at(l - 1, l - 1).y) + fabs(H.at(l, l).x) + fabs(H.at(l, l).y);
-          if (s == 0.0) s = 1.0;
-          if (fabs(sub.x) + fabs(sub.y) <= ulp * s) {
-            H.at(l, l - 1) = make_double2(0.0, 0.0);
-            break;
-          }
-          --l;
-        }
-        if (l == hi) {  // 1 x 1 block converged
-          --hi;
-          s_iter = 0;
-          continue;
-        }
-        s_l = l;
-        // Wilkinson shift from the trailing 2 x 2 of the active block
-        const double2 a = H.at(hi - 1, hi - 1), b = H.at(hi - 1, hi), c = H.at(hi, hi - 1), d = H.at(hi, hi);
-        double2 mu;
-        if (s_iter > 0 && s_iter % 10 == 0) {
-          // exceptional shift
-          const double e = fabs(c.x) + fabs(c.y);
-          mu = make_double2(d.x + 0.75 * e, d.y);
-        } else {
-          const double2 half = cscale(csub(a, d), 0.5);
-          const double2 disc = csqrt(cadd(cmul(half, half), cmul(b, c)));
-          const double2 m1 = cadd(cscale(cadd(a, d), 0.5), disc);
-          const double2 m2 = csub(cscale(cadd(a, d), 0.5), disc);
-          mu = (cabs2(csub(m1, d)) <= cabs2(csub(m2, d))) ? m1 : m2;
-        }
-        s_mu = mu;
-        break;
-      }
-      s_hi = hi;
-      if (hi < 0) s_done = 1;
-      ++s_iter;
-    }
-    __syncthreads();
-    if (s_done || total >= max_iter_total) break;
-    ++total;
-    const int l = s_l, hi = s_hi;
-    const double2 mu = s_mu;
-    // ---- bulge chase over the active block [l, hi]
-    for (int k = l; k < hi; ++k) {
-      // rotation from (x, y)
-      if (threadIdx.x == 0) {
-        double2 x, y;
-        if (k == l) {
-          x = csub(H.at(l, l), mu);
-          y = H.at(l + 1, l);
-        } else {
-          x = H.at(k, k - 1);
-          y = H.at(k + 1, k - 1);
-        }
-        const double ax = cabs(x), ay = cabs(y);
-        double c;
-        double2 s;
-        if (ay == 0.0) {
-          c = 1.0;
-          s = make_double2(0.0, 0.0);
-        } else if (ax == 0.0) {
-          c = 0.0;
-          s = cscale(cconj(y), 1.0 / ay);
-        } else {
-          const double r = hypot(ax, ay);
-          c = ax / r;
-          // s = (x / |x|) conj(y) / r
-          s = cscale(cmul(x, cconj(y)), 1.0 / (ax * r));
-        }
-        s_cs[0] = make_double2(c, 0.0);
-        s_cs[1] = s;
-      }
-      __syncthreads();
-      const double c = s_cs[0].x;
-      const double2 s = s_cs[1];
-      // rows k, k+1, columns max(k-1, 0) .. n-1
-      const int j0 = (k > 0) ? k - 1 : 0;
-      for (int j = j0 + threadIdx.x; j < n; j += blockDim.x) {
-        const double2 hk = H.at(k, j), hk1 = H.at(k + 1, j);
-        H.at(k, j) = cadd(cscale(hk, c), cmul(s, hk1));
-        H.at(k + 1, j) = csub(cscale(hk1, c), cmul(cconj(s), hk));
-      }
-      __syncthreads();
-      // columns k, k+1, rows 0 .. min(k+2, hi)
-      const int i1 = (k + 2 < hi) ? k + 2 : hi;
-      for (int i = threadIdx.x; i <= i1; i += blockDim.x) {
-        const double2 a = H.at(i, k), b = H.at(i, k + 1);
-        H.at(i, k) = cadd(cscale(a, c), cmul(b, cconj(s)));
-        H.at(i, k + 1) = csub(cscale(b, c), cmul(a, s));
-      }
-      // Z <- Z G^H: columns k, k+1 of Z are rows k, k+1 of ZT
-      for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const double2 a = ZT[(long)k * n + i], b = ZT[(long)(k + 1) * n + i];
-        ZT[(long)k * n + i] = cadd(cscale(a, c), cmul(b, cconj(s)));
-        ZT[(long)(k + 1) * n + i] = csub(cscale(b, c), cmul(a, s));
-      }
-      __syncthreads();
-    }
-  }
-  // write T (upper triangle of H)
-  for (long e = threadIdx.x; e < (long)n * n; e += blockDim.x) {
-    const int i = (int)(e / n), j = (int)(e % n);
-    T[e] = (j >= i) ? H.at(i, j) : make_double2(0.0, 0.0);
-  }
-  if (threadIdx.x == 0) info[0] = s_done ? total : -total;
-}
-
 // --------------------------------------- eigenvectors of triangular T
 // T Y = Y diag(T): Y unit upper triangular, column k solves
 // (T[:k,:k] - t_kk I) y = -T[:k, k].  Rows are produced bottom-up for all
@@ -557,17 +397,22 @@ static size_t lds_bytes(long doubles) { return (size_t)std::min<long>(doubles, k
 void chol_skip(hipStream_t s, int n, const double* G, double* R, int* mask, int* count, double tau) {
   T2S2_CHECK(n >= 1 && n <= 4096, "chol_skip: bad size");
   const long need = (long)n * n;
-  hipLaunchKernelGGL(chol_skip_kernel, dim3(1), dim3(kNT), need <= kLdsDoubles ? lds_bytes(need) : 0, s,
-                     n, G, R, mask, count, tau);
+  TimedScope ts(s, KC_CHOL, 16.0 * need, (double)n * n * n / 3.0);
+  if (need <= kLdsDoubles)
+    hipLaunchKernelGGL(chol_skip_kernel<true>, dim3(1), dim3(kNT), lds_bytes(need), s, n, G, R, mask, count, tau);
+  else
+    hipLaunchKernelGGL(chol_skip_kernel<false>, dim3(1), dim3(kNT), 0, s, n, G, R, mask, count, tau);
   T2S2_LAUNCH_CHECK();
 }
 
 void trtri_upper(hipStream_t s, int n, const double* R, double* Rinv) {
+  TimedScope ts(s, KC_TRTRI, 8.0 * n * n, (double)n * n * n / 3.0);
   hipLaunchKernelGGL(trtri_upper_kernel<double>, dim3(1), dim3(kNT), 0, s, n, R, Rinv);
   T2S2_LAUNCH_CHECK();
 }
 
 void trtri_upper(hipStream_t s, int n, const double2* R, double2* Rinv) {
+  TimedScope ts(s, KC_TRTRI, 16.0 * n * n, 4.0 * n * n * n / 3.0);
   hipLaunchKernelGGL(trtri_upper_kernel<double2>, dim3(1), dim3(kNT), 0, s, n, R, Rinv);
   T2S2_LAUNCH_CHECK();
 }
@@ -578,30 +423,31 @@ void jacobi_rows(hipStream_t s, int k, int c, double* B, double* JT, double* U, 
   const long bsz = (long)k * c, jsz = (long)k * k;
   long need = 0;
   if (bsz <= kLdsDoubles) need = (bsz + jsz <= kLdsDoubles) ? bsz + jsz : bsz;
-  hipLaunchKernelGGL(jacobi_rows_kernel, dim3(1), dim3(kNT), need ? lds_bytes(need) : 0, s, k, c, B, JT, U, Wt,
-                     sigma, info, max_sweeps);
+  TimedScope ts(s, KC_JACOBI, 8.0 * (2.0 * bsz + 2.0 * jsz), 0.0);
+  if (need == bsz + jsz && need > 0)
+    hipLaunchKernelGGL(jacobi_rows_kernel<2>, dim3(1), dim3(kNT), lds_bytes(need), s, k, c, B, JT, U, Wt, sigma,
+                       info, max_sweeps);
+  else if (need == bsz && need > 0)
+    hipLaunchKernelGGL(jacobi_rows_kernel<1>, dim3(1), dim3(kNT), lds_bytes(need), s, k, c, B, JT, U, Wt, sigma,
+                       info, max_sweeps);
+  else
+    hipLaunchKernelGGL(jacobi_rows_kernel<0>, dim3(1), dim3(kNT), 0, s, k, c, B, JT, U, Wt, sigma, info,
+                       max_sweeps);
   T2S2_LAUNCH_CHECK();
 }
 
 void hessenberg(hipStream_t s, int n, double* A, double* QT, double* work) {
   const long need = (long)n * n + 2L * n;
-  hipLaunchKernelGGL(hessenberg_kernel, dim3(1), dim3(kNT), need <= kLdsDoubles ? lds_bytes(need) : 0, s, n, A,
-                     QT, work);
-  T2S2_LAUNCH_CHECK();
-}
-
-long schur_global_work(int n) { return (long)n * n; }
-
-void schur_qr(hipStream_t s, int n, const double* Hr, double2* Hw, double2* ZT, double2* T, int* info) {
-  long m = n - 2;
-  const long psz = 2L * n + (m > 0 ? m * (n + 2) - (m * (m + 3)) / 2 : 0);
-  const long need = psz * 2;
-  hipLaunchKernelGGL(schur_qr_kernel, dim3(1), dim3(kNT), need <= kLdsDoubles ? lds_bytes(need) : 0, s, n, Hr, Hw,
-                     ZT, T, info, 60 * n + 100);
+  TimedScope ts(s, KC_HESS, 8.0 * 3.0 * n * n, 14.0 * n * n * n / 3.0);
+  if (need <= kLdsDoubles)
+    hipLaunchKernelGGL(hessenberg_kernel<true>, dim3(1), dim3(kNT), lds_bytes(need), s, n, A, QT, work);
+  else
+    hipLaunchKernelGGL(hessenberg_kernel<false>, dim3(1), dim3(kNT), 0, s, n, A, QT, work);
   T2S2_LAUNCH_CHECK();
 }
 
 void trevec(hipStream_t s, int n, const double2* T, double2* Y) {
+  TimedScope ts(s, KC_TREVEC, 16.0 * 2.0 * n * n, 8.0 * n * n * n / 6.0);
   hipLaunchKernelGGL(trevec_kernel, dim3(1), dim3(kNT), 0, s, n, T, Y);
   T2S2_LAUNCH_CHECK();
 }

@@ -10,6 +10,9 @@
 // both the LDS reads and the global writes of a wavefront are contiguous.
 #include "gemm.h"
 
+#include <algorithm>
+#include <type_traits>
+
 namespace t2s2 {
 
 namespace {
@@ -22,6 +25,7 @@ template <> struct Arith<double> {
   __device__ static double add(double a, double b) { return a + b; }
   __device__ static double conj(double a) { return a; }
   __device__ static bool is_zero(double a) { return a == 0.0; }
+  static bool is_zero_host(double a) { return a == 0.0; }
 };
 template <> struct Arith<float> {
   __device__ static float zero() { return 0.0f; }
@@ -30,6 +34,7 @@ template <> struct Arith<float> {
   __device__ static float add(float a, float b) { return a + b; }
   __device__ static float conj(float a) { return a; }
   __device__ static bool is_zero(float a) { return a == 0.0f; }
+  static bool is_zero_host(float a) { return a == 0.0f; }
 };
 template <> struct Arith<double2> {
   __device__ static double2 zero() { return make_double2(0.0, 0.0); }
@@ -40,6 +45,7 @@ template <> struct Arith<double2> {
   __device__ static double2 add(double2 a, double2 b) { return cadd(a, b); }
   __device__ static double2 conj(double2 a) { return cconj(a); }
   __device__ static bool is_zero(double2 a) { return a.x == 0.0 && a.y == 0.0; }
+  static bool is_zero_host(double2 a) { return a.x == 0.0 && a.y == 0.0; }
 };
 template <> struct Arith<float2> {
   __device__ static float2 zero() { return make_float2(0.0f, 0.0f); }
@@ -52,6 +58,7 @@ template <> struct Arith<float2> {
   __device__ static float2 add(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
   __device__ static float2 conj(float2 a) { return make_float2(a.x, -a.y); }
   __device__ static bool is_zero(float2 a) { return a.x == 0.0f && a.y == 0.0f; }
+  static bool is_zero_host(float2 a) { return a.x == 0.0f && a.y == 0.0f; }
 };
 
 constexpr int BM = 64, BN = 64, BK = 16, NT = 256;
@@ -61,7 +68,9 @@ __global__ void __launch_bounds__(NT)
 gemm_kernel(int opA, int opB, int M, int N, int K, T alpha,
             const T* __restrict__ A, long lda, long sA,
             const T* __restrict__ B, long ldb, long sB,
-            T beta, T* __restrict__ C, long ldc, long sC) {
+            T beta, T* __restrict__ C, long ldc, long sC, int kchunk) {
+  // kchunk > 0: split-K partial products, blockIdx.z selects the K range and
+  // the output slab C + z * sC; otherwise blockIdx.z is the batch index.
   using AR = Arith<T>;
   __shared__ T As[BK][BM + 1];
   __shared__ T Bs[BK][BN + 1];
@@ -69,8 +78,14 @@ gemm_kernel(int opA, int opB, int M, int N, int K, T alpha,
   const int tx = tid & 15, ty = tid >> 4;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
   const long bz = blockIdx.z;
-  A += bz * sA;
-  B += bz * sB;
+  int kbeg = 0, kend = K;
+  if (kchunk > 0) {
+    kbeg = (int)bz * kchunk;
+    kend = min(K, kbeg + kchunk);
+  } else {
+    A += bz * sA;
+    B += bz * sB;
+  }
   C += bz * sC;
 
   T acc[4][4];
@@ -79,7 +94,7 @@ gemm_kernel(int opA, int opB, int M, int N, int K, T alpha,
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = AR::zero();
 
-  for (int k0 = 0; k0 < K; k0 += BK) {
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
 #pragma unroll
     for (int s = 0; s < (BM * BK) / NT; ++s) {
       const int e = tid + NT * s;
@@ -88,7 +103,7 @@ gemm_kernel(int opA, int opB, int M, int N, int K, T alpha,
       if (!ta) { i = e / BK; k = e % BK; } else { k = e / BM; i = e % BM; }
       const int gi = m0 + i, gk = k0 + k;
       T v = AR::zero();
-      if (gi < M && gk < K) {
+      if (gi < M && gk < kend) {
         v = !ta ? A[(long)gi * lda + gk] : A[(long)gk * lda + gi];
         if (opA >= 2) v = AR::conj(v);
       }
@@ -102,7 +117,7 @@ gemm_kernel(int opA, int opB, int M, int N, int K, T alpha,
       if (!tb) { k = e / BN; j = e % BN; } else { j = e / BK; k = e % BK; }
       const int gj = n0 + j, gk = k0 + k;
       T v = AR::zero();
-      if (gj < N && gk < K) {
+      if (gj < N && gk < kend) {
         v = !tb ? B[(long)gk * ldb + gj] : B[(long)gj * ldb + gk];
         if (opB >= 2) v = AR::conj(v);
       }
@@ -140,6 +155,59 @@ gemm_kernel(int opA, int opB, int M, int N, int K, T alpha,
   }
 }
 
+// C = alpha * sum_z W[z] + beta * C  (split-K epilogue, deterministic order)
+template <class T>
+__global__ void splitk_reduce_kernel(int M, int N, int S, const T* __restrict__ W, T alpha, T beta,
+                                     T* __restrict__ C, long ldc) {
+  using AR = Arith<T>;
+  const long MN = (long)M * N;
+  const bool beta_zero = AR::is_zero(beta);
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < MN; e += (long)gridDim.x * blockDim.x) {
+    T acc = AR::zero();
+    for (int z = 0; z < S; ++z) acc = AR::add(acc, W[z * MN + e]);
+    T* c = C + (e / N) * ldc + (e % N);
+    T v = AR::mul(alpha, acc);
+    if (!beta_zero) v = AR::add(v, AR::mul(beta, *c));
+    *c = v;
+  }
+}
+
+struct SplitWork {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~SplitWork() {
+    if (p) (void)hipFree(p);
+  }
+};
+SplitWork g_split;
+
+template <class T>
+T* split_workspace(size_t count) {
+  const size_t want = count * sizeof(T);
+  if (g_split.bytes < want) {
+    if (g_split.p) T2S2_HIP(hipFree(g_split.p));
+    g_split.p = nullptr;
+    g_split.bytes = 0;
+    const size_t alloc = std::max(want, (size_t)1 << 24);
+    T2S2_HIP(hipMalloc(&g_split.p, alloc));
+    g_split.bytes = alloc;
+  }
+  return static_cast<T*>(g_split.p);
+}
+
+template <class T> bool AR_beta_nonzero(T b) { return !Arith<T>::is_zero_host(b); }
+
+template <class T> T one_of();
+template <> double one_of<double>() { return 1.0; }
+template <> float one_of<float>() { return 1.0f; }
+template <> double2 one_of<double2>() { return make_double2(1.0, 0.0); }
+template <> float2 one_of<float2>() { return make_float2(1.0f, 0.0f); }
+template <class T> T zero_of();
+template <> double zero_of<double>() { return 0.0; }
+template <> float zero_of<float>() { return 0.0f; }
+template <> double2 zero_of<double2>() { return make_double2(0.0, 0.0); }
+template <> float2 zero_of<float2>() { return make_float2(0.0f, 0.0f); }
+
 }  // namespace
 
 template <class T>
@@ -151,9 +219,33 @@ void gemm(hipStream_t s, Op opA, Op opB, int M, int N, int K, T alpha,
     // C = beta C; K = 0 never occurs in the solver, reject rather than guess
     throw Error(1, "gemm: K must be positive");
   }
+  const bool cplx = std::is_same<T, double2>::value || std::is_same<T, float2>::value;
+  const double elem = (double)sizeof(T);
+  TimedScope ts(s, cplx ? KC_GEMM_C : KC_GEMM,
+                elem * ((double)M * K + (double)K * N + (double)M * N * (AR_beta_nonzero(beta) ? 2.0 : 1.0)) * batch,
+                (cplx ? 8.0 : 2.0) * (double)M * N * K * batch);
+  const long tiles = (long)((N + BN - 1) / BN) * ((M + BM - 1) / BM);
+  if (batch == 1 && tiles < 96 && K >= 2048) {
+    // few output tiles, long reduction: split K over S workgroup slabs
+    int S = (int)std::min<long>((384 + tiles - 1) / tiles, K / 512);
+    S = std::max(2, std::min(S, 256));
+    int kchunk = (K + S - 1) / S;
+    kchunk = ((kchunk + BK - 1) / BK) * BK;
+    S = (K + kchunk - 1) / kchunk;
+    const long MN = (long)M * N;
+    T* W = split_workspace<T>((size_t)S * MN);
+    dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, S);
+    hipLaunchKernelGGL(gemm_kernel<T>, grid, dim3(NT), 0, s, (int)opA, (int)opB, M, N, K, one_of<T>(),
+                       A, lda, 0L, B, ldb, 0L, zero_of<T>(), W, (long)N, MN, kchunk);
+    T2S2_LAUNCH_CHECK();
+    const int rb = (int)std::min<long>((MN + 255) / 256, 2048);
+    hipLaunchKernelGGL(splitk_reduce_kernel<T>, dim3(rb), dim3(256), 0, s, M, N, S, W, alpha, beta, C, ldc);
+    T2S2_LAUNCH_CHECK();
+    return;
+  }
   dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, batch);
   hipLaunchKernelGGL(gemm_kernel<T>, grid, dim3(NT), 0, s, (int)opA, (int)opB, M, N, K, alpha,
-                     A, lda, strideA, B, ldb, strideB, beta, C, ldc, strideC);
+                     A, lda, strideA, B, ldb, strideB, beta, C, ldc, strideC, 0);
   T2S2_LAUNCH_CHECK();
 }
 

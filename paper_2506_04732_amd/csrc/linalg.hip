@@ -221,12 +221,15 @@ void schur_real(const Ctx& c, int n, const double* A, double2* ZT, double2* T) {
   double* H = S.get<double>("eig.H", (size_t)n * n);
   double* QT = S.get<double>("eig.QT", (size_t)n * n);
   double* work = S.get<double>("eig.work", 2 * (size_t)n);
-  double2* Hw = S.get<double2>("eig.Hw", (size_t)n * n);
+  double* Hw = S.get<double>("eig.Hw", (size_t)n * n);
+  double* Tr = S.get<double>("eig.Tr", (size_t)n * n);
   int* info = S.get<int>("eig.info", 1);
+  int* bstart = S.get<int>("eig.bstart", n);
+  double2* U = S.get<double2>("eig.U2", 2 * (size_t)n);
   c.d2d(H, A, (size_t)n * n);
   hessenberg(c.s, n, H, QT, work);
-  real_to_complex(c.s, QT, ZT, (long)n * n);
-  schur_qr(c.s, n, H, Hw, ZT, T, info);
+  schur_francis(c.s, n, H, Hw, QT, Tr, info);
+  rsf2csf(c.s, n, Tr, QT, T, ZT, bstart, U);
 }
 
 void eig_nonsym(const Ctx& c, int n, const double* A, double2* lam, double2* V, double2* Vinv) {

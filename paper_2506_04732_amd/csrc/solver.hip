@@ -628,8 +628,11 @@ struct Amen {
       for (int l = 0; l <= d; ++l) mr = std::max(mr, xr[l]);
       rep.hist_rank.push_back(mr);
       double gres = -1.0;
-      const bool check = (o.check_every <= 1) || (sweeps % o.check_every == 0) || (sweeps == o.max_sweeps) ||
-                         max_res < o.tol;
+      // FP64 residual: every check_every sweeps, or (check_every = 0) once the
+      // largest local residual suggests the target may be met, and at the end
+      const bool near = max_res <= 10.0 * o.target;
+      const bool check = (o.check_every == 1) || (o.check_every > 1 && sweeps % o.check_every == 0) ||
+                         (o.check_every == 0 && near) || (sweeps == o.max_sweeps);
       if (check) {
         DTT xd;
         xd.d = d;

@@ -253,6 +253,9 @@ void ttm_matvec_core(hipStream_t s, int R0, int R1, int n, int r0, int r1,
   T2S2_CHECK(r0 >= 1 && r1 >= 1 && R0 >= 1 && R1 >= 1, "ttm_matvec_core: ranks must be >= 1");
   dim3 grid((r1 + kMvQ - 1) / kMvQ, r0);
   const long asz = (long)R0 * n * n * R1;
+  // algorithmic traffic: read X and the operator core once, write Y once
+  TimedScope ts(s, KC_TTMV, 8.0 * ((double)r0 * n * r1 + (double)asz + (double)R0 * r0 * n * R1 * r1),
+                2.0 * (double)R0 * R1 * n * n * r0 * r1);
   const size_t lds = asz <= kMvLdsA ? asz * sizeof(double) : 0;
   if (n <= 32)
     hipLaunchKernelGGL(ttm_matvec_kernel<32>, grid, dim3(kMvQ * kMvGroups), lds, s, R0, R1, n, r0, r1, A, X, Y);
@@ -324,6 +327,7 @@ void kron_trisolve(hipStream_t s, int r1, int m, int r2, const double2* T, const
   T2S2_CHECK(m >= 1 && m <= 64, "kron_trisolve: mode size must be in [1, 64]");
   const long nthr = (long)r1 * r2;
   const int grid = (int)((nthr + 127) / 128);
+  TimedScope ts(s, KC_KRONSOLVE, 16.0 * (2.0 * nthr * m + (double)m * m + r1 + r2), 8.0 * nthr * m * (m + 1) / 2.0);
   if (m <= 16)
     hipLaunchKernelGGL(kron_trisolve_kernel<16>, dim3(grid), dim3(128), 0, s, r1, m, r2, T, lamL, lamR, h);
   else if (m <= 32)
