@@ -159,7 +159,10 @@ __global__ void __launch_bounds__(kNT) jacobi_rows_kernel(int k, int c, double* 
   const int K = k + (k & 1);  // even number of players (k odd: one bye)
   const int npairs = K / 2;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, nwaves = blockDim.x / 64;
-  const double tol = 1e-15;
+  // rows are rotated until their cosines fall below tol: the factorisation
+  // B = U Wt is exact for any tol (U is a product of rotations), so tol only
+  // decides how well the energy is compacted into the leading rows
+  const double tol = 1e-10;
   int sweep = 0;
   for (; sweep < max_sweeps; ++sweep) {
     if (threadIdx.x == 0) s_rot = 0;

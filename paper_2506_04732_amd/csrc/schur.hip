@@ -146,7 +146,10 @@ __global__ void __launch_bounds__(kFqThreads) francis_kernel(int n, const double
     __syncthreads();
   };
 
-  const double ulp = DBL_EPSILON;
+  // deflation threshold: the factorisation only feeds the exact-solve
+  // preconditioner inside FP64 refinement, so subdiagonals below 1e-13 of
+  // their neighbours are dropped (a relative perturbation of that size)
+  const double ulp = 1e-13;
   int total = 0;
   while (true) {
     // ---- deflation: largest l <= hi with a negligible subdiagonal
