@@ -103,6 +103,64 @@ def cpu_baseline(prob, gpu_result, sweeps: int) -> dict:
             "measured_s": t_cpu, "measured_sweeps": sweeps}
 
 
+BATCH_OPTS = dict(tol=1e-10, target=1e-8, max_sweeps=30, kick=8, init_rank=8, check_every=0, seed=0)
+
+
+def bench_batched(args, rank: int):
+    """256 uneven instances (d in {4,5,6}, N_l in [16,48], eps in [1e-4,1e-1]),
+    each solved to residual 1e-8 under rank cap 128, `workers` at a time on
+    concurrent streams.  value = seconds for the whole batch."""
+    import numpy as np
+    import torch
+    import paper_2506_04732_amd as t2s2
+    import workloads
+    from paper_2506_04732_amd import TT, sources
+
+    insts = workloads.batched_instances(256)
+    cap = insts[0].rank_cap
+    probs = [t2s2.Problem(q.d, q.N, q.eps, q.beta, q.scheme, rank_cap=cap) for q in insts]
+    fs = [sources.source_tt(p, sources.gaussian_factors(p, q.gauss.amp, q.gauss.centre, q.gauss.width))
+          for p, q in zip(probs, insts)]
+    outs = [TT.empty(p.m, cap) for p in probs]
+    for _ in range(args.warmup):
+        t2s2.solve_batched(probs[:16], fs[:16], outs=outs[:16], workers=args.workers, **BATCH_OPTS)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        res = t2s2.solve_batched(probs, fs, outs=outs, workers=args.workers, **BATCH_OPTS)
+        print(f"batched step {k + 1}: {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    seq = None
+    if args.seq_baseline:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for i, (p, f, x) in enumerate(zip(probs, fs, outs)):
+            p.solve(f, out=x, **BATCH_OPTS)
+            if i % 32 == 31:
+                print(f"sequential baseline: {i + 1} instances, {time.perf_counter() - t1:.1f} s", file=sys.stderr,
+                      flush=True)
+        torch.cuda.synchronize()
+        seq = time.perf_counter() - t1
+    conv = sum(r.converged for r in res)
+    out = {
+        "metric": "batched TT solves: seconds for 256 uneven instances to rel. resid 1e-8",
+        "value": sec, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": sec * 1e3, "higher_is_better": False, "scaling": "strong", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "batched256_d4-6_N16-48_eps1e-4-1e-1_gauss4", "instances": len(insts),
+                   "workers": args.workers, "rank_cap": cap, **{k: v for k, v in BATCH_OPTS.items()}},
+        "instances_per_s": len(insts) / sec,
+        "converged": conv,
+        "max_rank_p50": float(np.median([max(r.ranks) for r in res])),
+        "sequential_s": seq,
+        "speedup_vs_sequential": (seq / sec) if seq else None,
+        "roofline": None, "cpu_baseline": None,
+    }
+    if rank == 0:
+        print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +169,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=3)
     ap.add_argument("--no-oracle-check", action="store_true")
+    ap.add_argument("--workload", choices=["6d", "batched256"], default="6d",
+                    help="6d: the 6D N=32 solve (default); batched256: 256 uneven instances solved concurrently")
+    ap.add_argument("--workers", type=int, default=8, help="batched256: concurrent instances")
+    ap.add_argument("--seq-baseline", action="store_true",
+                    help="batched256: also time the 256 instances solved one after another")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy 8 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -129,6 +192,8 @@ def main():
               f"workload and this build has no multi-GPU path)", file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
+    if args.workload == "batched256":
+        return bench_batched(args, rank)
 
     import torch
     import paper_2506_04732_amd as t2s2

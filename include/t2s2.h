@@ -58,6 +58,17 @@ extern "C" {
 #define T2S2_SCHEME_PLAIN 0
 #define T2S2_SCHEME_SC 1
 
+/* Arithmetic of the local solves (t2s2_options.precision).  FP64: local
+ * systems are factorised and solved in FP64.  MIXED: the eigen/Schur
+ * factorisations of the interface matrices and the complex transforms of
+ * the local solve run in FP32, inside FP64 iterative refinement of each
+ * local system (FP64 local residual and update); should the FP32 factors
+ * contract the residual too slowly, that local system switches to FP64
+ * factors.  Truncations, orthogonalisation, interfaces and the global
+ * residual test are FP64 in both modes, so the stopping test is the same. */
+#define T2S2_PRECISION_FP64 0
+#define T2S2_PRECISION_MIXED 1
+
 #define T2S2_MAX_DIM 16
 #define T2S2_MAX_HISTORY 128
 
@@ -96,6 +107,7 @@ typedef struct {
   int check_every;     /* FP64 residual every this many sweeps; 0: only once
                           the largest local residual is <= 10 * target      */
   int verbose;         /* 1: print one line per sweep on stderr              */
+  int precision;       /* T2S2_PRECISION_FP64 or T2S2_PRECISION_MIXED        */
 } t2s2_options;
 
 /* Per-solve report (host struct filled by t2s2_solve). */
@@ -111,6 +123,11 @@ typedef struct {
   double history_local[T2S2_MAX_HISTORY];       /* max local rel. residual  */
   int history_max_rank[T2S2_MAX_HISTORY];
   double history_time_ms[T2S2_MAX_HISTORY];
+  int precision;                                /* as requested             */
+  int local_systems;                            /* local systems solved     */
+  int refinement_steps;                         /* preconditioned FP64 steps */
+  int fp64_fallbacks;                           /* MIXED: FP32 factors too
+                                                   weak, FP64 ones used     */
 } t2s2_report;
 
 /* Message of the last failing call on this thread ("" if none). */
@@ -186,10 +203,34 @@ int t2s2_tt_round(t2s2_problem* p, t2s2_tt* x, double tol, int rmax, void* strea
  *          (first/last: N_l*rank_cap); ranks written
  *   rep    optional host report
  * Returns T2S2_OK when the FP64 residual meets opts->target, T2S2_ENOTCONV
- * (x_out still holds the last iterate) when max_sweeps is reached first. */
+ * (x_out still holds the last iterate) when max_sweeps is reached first,
+ * T2S2_EINVAL for a precision other than T2S2_PRECISION_FP64 / _MIXED. */
 int t2s2_solve(t2s2_problem* p, const t2s2_tt* f, const t2s2_tt* x0,
                const t2s2_options* opts, t2s2_tt* x_out, t2s2_report* rep,
                void* stream);
+
+/* Batched solve of count independent instances of uneven size (each its own
+ * d, N_l, eps, beta, source; the batched workload of hundreds of small
+ * problems).  Instance i is solved exactly as t2s2_solve(probs[i], f[i],
+ * x0 ? x0[i] : NULL, opts, x_out[i], reps ? &reps[i] : NULL) would, so its
+ * result is bitwise the same; instances run concurrently, up to `workers`
+ * at a time (0: 16, at most 64), each on its own non-blocking HIP stream of
+ * default priority driven by its own host thread, taken from a shared
+ * queue in decreasing order of an estimated cost (sum of m_l times
+ * log10(10 / eps)).  Every worker stream first waits for the work already
+ * queued on `stream`; all work is complete when the call returns.
+ *   probs  count distinct problems (a problem is not shared between
+ *          concurrent solves: EINVAL if a pointer repeats)
+ *   x0     NULL, or count entries each NULL or a start TT
+ *   opts   one option set for every instance (NULL: defaults)
+ *   reps   NULL or count host reports
+ * Returns T2S2_OK if every instance converged; otherwise the worst code
+ * (a hard error before T2S2_ENOTCONV), with the first such instance named
+ * in t2s2_last_error; reps[i].status holds each instance's outcome. */
+int t2s2_solve_batched(int count, t2s2_problem* const* probs,
+                       const t2s2_tt* const* f, const t2s2_tt* const* x0,
+                       const t2s2_options* opts, t2s2_tt* const* x_out,
+                       t2s2_report* reps, int workers, void* stream);
 
 /* --------------------------------------------------------- diagnostics ---
  * Kernel-class timing for benchmarks.  While enabled, every library kernel

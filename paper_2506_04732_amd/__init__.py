@@ -7,7 +7,7 @@ without the built library every entry point raises ``LibraryMissing``.
 
 Names follow the C ABI: ``nodes``, ``matrices_1d``, ``Problem`` (create /
 operator / colloc / tt_matvec / tt_norm / tt_residual_norm / tt_round /
-solve).
+solve) and ``solve_batched``.
 """
 from __future__ import annotations
 
@@ -18,9 +18,11 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 from . import _lib
-from ._lib import (SCHEME_PLAIN, SCHEME_SC, T2S2_ENOTCONV, LibraryMissing, T2S2Error, check, lib)
+from ._lib import (PRECISION_FP64, PRECISION_MIXED, SCHEME_PLAIN, SCHEME_SC, T2S2_ENOTCONV, LibraryMissing,
+                   T2S2Error, check, lib)
 
-__all__ = ["nodes", "matrices_1d", "TT", "Problem", "SolveResult", "SCHEME_PLAIN", "SCHEME_SC",
+__all__ = ["nodes", "matrices_1d", "TT", "Problem", "SolveResult", "solve_batched", "SCHEME_PLAIN", "SCHEME_SC",
+           "PRECISION_FP64", "PRECISION_MIXED",
            "LibraryMissing", "T2S2Error", "lib"]
 
 
@@ -144,6 +146,10 @@ class SolveResult:
     history_local: List[float] = field(default_factory=list)
     history_max_rank: List[int] = field(default_factory=list)
     history_time_ms: List[float] = field(default_factory=list)
+    precision: int = PRECISION_FP64
+    local_systems: int = 0
+    refinement_steps: int = 0
+    fp64_fallbacks: int = 0
 
     @property
     def converged(self) -> bool:
@@ -221,14 +227,11 @@ class Problem:
     # ------------------------------------------------------------------ solve
     def solve(self, f: TT, x0: Optional[TT] = None, *, tol: float = 1e-10, target: float = 1e-8,
               max_sweeps: int = 40, kick: int = 8, rank_cap: Optional[int] = None, init_rank: int = 2,
-              seed: int = 0, check_every: int = 1, verbose: bool = False, out: Optional[TT] = None) -> SolveResult:
+              seed: int = 0, check_every: int = 1, verbose: bool = False, out: Optional[TT] = None,
+              precision: int = PRECISION_FP64) -> SolveResult:
         cap = int(rank_cap or self.rank_cap)
         x = out if out is not None else TT.empty(self.m, cap)
-        o = _lib.Options()
-        lib().t2s2_default_options(C.byref(o))
-        o.tol, o.target, o.max_sweeps, o.kick = float(tol), float(target), int(max_sweeps), int(kick)
-        o.rank_cap, o.init_rank, o.seed = cap, int(init_rank), int(seed)
-        o.check_every, o.verbose = int(check_every), int(bool(verbose))
+        o = _options(tol, target, max_sweeps, kick, cap, init_rank, seed, check_every, verbose, precision)
         rep = _lib.Report()
         fs, xs = f._struct(), x._struct()
         x0s = x0._struct() if x0 is not None else None
@@ -236,10 +239,63 @@ class Problem:
                                 C.byref(xs), C.byref(rep), _stream())
         check(code, allow=(T2S2_ENOTCONV,))
         x._read_ranks()
-        h = rep.history_len
-        return SolveResult(x=x, status=code, sweeps=rep.sweeps, residual=rep.residual,
-                           ranks=list(rep.ranks[: self.d + 1]), time_ms=rep.time_ms,
-                           history_residual=list(rep.history_residual[:h]),
-                           history_local=list(rep.history_local[:h]),
-                           history_max_rank=list(rep.history_max_rank[:h]),
-                           history_time_ms=list(rep.history_time_ms[:h]))
+        return _result(x, code, rep, self.d)
+
+
+def _options(tol, target, max_sweeps, kick, cap, init_rank, seed, check_every, verbose, precision):
+    o = _lib.Options()
+    lib().t2s2_default_options(C.byref(o))
+    o.tol, o.target, o.max_sweeps, o.kick = float(tol), float(target), int(max_sweeps), int(kick)
+    o.rank_cap, o.init_rank, o.seed = int(cap), int(init_rank), int(seed)
+    o.check_every, o.verbose = int(check_every), int(bool(verbose))
+    o.precision = int(precision)
+    return o
+
+
+def _result(x: TT, code: int, rep, d: int) -> SolveResult:
+    h = rep.history_len
+    return SolveResult(x=x, status=rep.status if code in (0, T2S2_ENOTCONV) else code, sweeps=rep.sweeps,
+                       residual=rep.residual, ranks=list(rep.ranks[: d + 1]), time_ms=rep.time_ms,
+                       history_residual=list(rep.history_residual[:h]),
+                       history_local=list(rep.history_local[:h]),
+                       history_max_rank=list(rep.history_max_rank[:h]),
+                       history_time_ms=list(rep.history_time_ms[:h]), precision=rep.precision,
+                       local_systems=rep.local_systems, refinement_steps=rep.refinement_steps,
+                       fp64_fallbacks=rep.fp64_fallbacks)
+
+
+def solve_batched(problems: Sequence["Problem"], fs: Sequence[TT], *, x0s: Optional[Sequence[Optional[TT]]] = None,
+                  outs: Optional[Sequence[TT]] = None, workers: int = 16, tol: float = 1e-10,
+                  target: float = 1e-8, max_sweeps: int = 40, kick: int = 8, rank_cap: Optional[int] = None,
+                  init_rank: int = 2, seed: int = 0, check_every: int = 1,
+                  precision: int = PRECISION_FP64) -> List[SolveResult]:
+    """t2s2_solve_batched: every instance solved as Problem.solve would, up to
+    `workers` at a time on their own streams.  rank_cap None: each problem's own."""
+    count = len(problems)
+    if len(fs) != count or (x0s is not None and len(x0s) != count) or (outs is not None and len(outs) != count):
+        raise ValueError("problems, fs, x0s and outs must have the same length")
+    if count == 0:
+        return []
+    caps = [int(rank_cap or p.rank_cap) for p in problems]
+    if len(set(caps)) != 1:
+        raise ValueError("one rank_cap applies to every instance: pass rank_cap or use equal problem caps")
+    xs = list(outs) if outs is not None else [TT.empty(p.m, caps[0]) for p in problems]
+    o = _options(tol, target, max_sweeps, kick, caps[0], init_rank, seed, check_every, False, precision)
+    reps = (_lib.Report * count)()
+    fst = [f._struct() for f in fs]
+    xst = [x._struct() for x in xs]
+    ttp = C.POINTER(_lib.TTStruct)
+    f_arr = (ttp * count)(*[C.pointer(v) for v in fst])
+    x_arr = (ttp * count)(*[C.pointer(v) for v in xst])
+    x0_arr = None
+    if x0s is not None:
+        x0st = [x0._struct() if x0 is not None else None for x0 in x0s]
+        x0_arr = (ttp * count)(*[C.pointer(v) if v is not None else ttp() for v in x0st])
+    h_arr = (C.c_void_p * count)(*[p._h.value for p in problems])
+    code = lib().t2s2_solve_batched(count, h_arr, f_arr, x0_arr, C.byref(o), x_arr, reps, int(workers), _stream())
+    check(code, allow=(T2S2_ENOTCONV,))
+    out = []
+    for i, x in enumerate(xs):
+        x._read_ranks()
+        out.append(_result(x, code, reps[i], problems[i].d))
+    return out

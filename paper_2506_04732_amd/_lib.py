@@ -9,12 +9,13 @@ LIB_PATH = os.path.join(HERE, "libt2s2.so")
 
 T2S2_OK, T2S2_EINVAL, T2S2_ENOMEM, T2S2_ENOTCONV, T2S2_EHIP = 0, 1, 2, 3, 4
 SCHEME_PLAIN, SCHEME_SC = 0, 1
+PRECISION_FP64, PRECISION_MIXED = 0, 1
 MAX_DIM, MAX_HISTORY = 16, 128
 
 EXPORTED = [
     "t2s2_last_error", "t2s2_nodes", "t2s2_matrices_1d", "t2s2_problem_create", "t2s2_problem_destroy",
     "t2s2_problem_operator", "t2s2_problem_colloc", "t2s2_tt_matvec", "t2s2_tt_norm",
-    "t2s2_tt_residual_norm", "t2s2_tt_round", "t2s2_solve", "t2s2_default_options",
+    "t2s2_tt_residual_norm", "t2s2_tt_round", "t2s2_solve", "t2s2_solve_batched", "t2s2_default_options",
     "t2s2_timing_enable", "t2s2_timing_read", "t2s2_timing_class_name",
 ]
 TIMING_CLASSES = ["gemm_f64", "gemm_c128", "ttm_matvec", "schur_qr", "hessenberg", "jacobi_svd", "cholesky",
@@ -34,7 +35,7 @@ class TTMStruct(C.Structure):
 class Options(C.Structure):
     _fields_ = [("tol", C.c_double), ("target", C.c_double), ("max_sweeps", C.c_int), ("kick", C.c_int),
                 ("rank_cap", C.c_int), ("init_rank", C.c_int), ("seed", C.c_ulonglong),
-                ("check_every", C.c_int), ("verbose", C.c_int)]
+                ("check_every", C.c_int), ("verbose", C.c_int), ("precision", C.c_int)]
 
 
 class Report(C.Structure):
@@ -42,7 +43,8 @@ class Report(C.Structure):
                 ("ranks", C.c_int * (MAX_DIM + 1)), ("residual", C.c_double), ("time_ms", C.c_double),
                 ("history_len", C.c_int), ("history_residual", C.c_double * MAX_HISTORY),
                 ("history_local", C.c_double * MAX_HISTORY), ("history_max_rank", C.c_int * MAX_HISTORY),
-                ("history_time_ms", C.c_double * MAX_HISTORY)]
+                ("history_time_ms", C.c_double * MAX_HISTORY), ("precision", C.c_int),
+                ("local_systems", C.c_int), ("refinement_steps", C.c_int), ("fp64_fallbacks", C.c_int)]
 
 
 class LibraryMissing(RuntimeError):
@@ -78,6 +80,9 @@ def lib() -> C.CDLL:
     L.t2s2_tt_round.argtypes = [vp, C.POINTER(TTStruct), C.c_double, C.c_int, vp]
     L.t2s2_solve.argtypes = [vp, C.POINTER(TTStruct), C.POINTER(TTStruct), C.POINTER(Options),
                              C.POINTER(TTStruct), C.POINTER(Report), vp]
+    ttp = C.POINTER(TTStruct)
+    L.t2s2_solve_batched.argtypes = [C.c_int, C.POINTER(vp), C.POINTER(ttp), C.POINTER(ttp), C.POINTER(Options),
+                                     C.POINTER(ttp), C.POINTER(Report), C.c_int, vp]
     L.t2s2_default_options.argtypes = [C.POINTER(Options)]
     L.t2s2_default_options.restype = None
     L.t2s2_timing_enable.argtypes = [C.c_int]

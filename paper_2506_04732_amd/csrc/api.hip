@@ -2,9 +2,13 @@
 // translation and marshalling only; the work happens in solver.hip.
 #include "../../include/t2s2.h"
 
+#include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "solver.h"
@@ -62,6 +66,72 @@ t2s2::Ctx ctx_for(t2s2_problem* p, void* stream) {
   c.s = static_cast<hipStream_t>(stream);
   c.sc = &p->P->sc;
   return c;
+}
+
+// One solve on stream s; throws on argument or runtime errors, returns
+// T2S2_OK or T2S2_ENOTCONV.
+int solve_one(t2s2_problem* p, const t2s2_tt* f, const t2s2_tt* x0, const t2s2_options* opts, t2s2_tt* x_out,
+              t2s2_report* rep, hipStream_t stream) {
+  T2S2_CHECK(p && f && x_out, "NULL argument");
+  t2s2::DTT fd = to_dtt(f);
+  T2S2_CHECK(fd.d == p->P->d, "f has the wrong dimension");
+  for (int l = 0; l < fd.d; ++l) T2S2_CHECK(fd.n[l] == p->P->m[l], "f mode sizes must be N_l - 2");
+  T2S2_CHECK(x_out->d == fd.d && x_out->cores && x_out->ranks, "invalid x_out descriptor");
+  t2s2::SolveOptions o;
+  if (opts) {
+    T2S2_CHECK(std::isfinite(opts->tol) && opts->tol > 0.0 && std::isfinite(opts->target), "bad tolerances");
+    T2S2_CHECK(opts->max_sweeps >= 1 && opts->kick >= 0 && opts->init_rank >= 1, "bad sweep/kick/rank options");
+    o.tol = opts->tol;
+    o.target = opts->target;
+    o.max_sweeps = opts->max_sweeps;
+    o.kick = opts->kick;
+    o.rank_cap = opts->rank_cap;
+    o.init_rank = opts->init_rank;
+    o.seed = opts->seed;
+    o.check_every = opts->check_every;
+    o.verbose = opts->verbose;
+    T2S2_CHECK(opts->precision == T2S2_PRECISION_FP64 || opts->precision == T2S2_PRECISION_MIXED,
+               "precision must be T2S2_PRECISION_FP64 or T2S2_PRECISION_MIXED");
+    o.precision = opts->precision;
+  }
+  t2s2::DTT xd;
+  xd.d = fd.d;
+  xd.n = fd.n;
+  xd.r.assign(fd.d + 1, 1);
+  xd.c.assign(x_out->cores, x_out->cores + fd.d);
+  t2s2::DTT x0d;
+  const t2s2::DTT* x0p = nullptr;
+  if (x0) {
+    x0d = to_dtt(x0);
+    x0p = &x0d;
+  }
+  t2s2::Ctx c = ctx_for(p, stream);
+  t2s2::SolveReport r;
+  const int st = t2s2::solve(*p->P, c, fd, x0p, o, xd, r);
+  for (int l = 0; l <= fd.d; ++l) x_out->ranks[l] = xd.r[l];
+  if (rep) {
+    std::memset(rep, 0, sizeof(*rep));
+    rep->status = st == 0 ? T2S2_OK : T2S2_ENOTCONV;
+    rep->sweeps = r.sweeps;
+    rep->max_rank = r.max_rank;
+    for (int l = 0; l <= fd.d && l <= T2S2_MAX_DIM; ++l) rep->ranks[l] = r.ranks[l];
+    rep->residual = r.residual;
+    rep->time_ms = r.time_ms;
+    const int h = std::min<int>((int)r.hist_res.size(), T2S2_MAX_HISTORY);
+    rep->history_len = h;
+    rep->precision = o.precision;
+    rep->local_systems = r.local_systems;
+    rep->refinement_steps = r.refinement_steps;
+    rep->fp64_fallbacks = r.fp64_fallbacks;
+    for (int i = 0; i < h; ++i) {
+      rep->history_residual[i] = r.hist_res[i];
+      rep->history_local[i] = r.hist_local[i];
+      rep->history_max_rank[i] = r.hist_rank[i];
+      rep->history_time_ms[i] = r.hist_time[i];
+    }
+  }
+  if (st != 0) t2s2::set_last_error("tolerance not met within max_sweeps");
+  return st == 0 ? T2S2_OK : T2S2_ENOTCONV;
 }
 
 }  // namespace
@@ -238,64 +308,90 @@ void t2s2_default_options(t2s2_options* o) {
   o->seed = 0;
   o->check_every = 1;
   o->verbose = 0;
+  o->precision = T2S2_PRECISION_FP64;
 }
 
 int t2s2_solve(t2s2_problem* p, const t2s2_tt* f, const t2s2_tt* x0, const t2s2_options* opts, t2s2_tt* x_out,
                t2s2_report* rep, void* stream) {
+  return guarded([&] { return solve_one(p, f, x0, opts, x_out, rep, static_cast<hipStream_t>(stream)); });
+}
+
+int t2s2_solve_batched(int count, t2s2_problem* const* probs, const t2s2_tt* const* f, const t2s2_tt* const* x0,
+                       const t2s2_options* opts, t2s2_tt* const* x_out, t2s2_report* reps, int workers,
+                       void* stream) {
   return guarded([&] {
-    T2S2_CHECK(p && f && x_out, "NULL argument");
-    t2s2::DTT fd = to_dtt(f);
-    T2S2_CHECK(fd.d == p->P->d, "f has the wrong dimension");
-    for (int l = 0; l < fd.d; ++l) T2S2_CHECK(fd.n[l] == p->P->m[l], "f mode sizes must be N_l - 2");
-    T2S2_CHECK(x_out->d == fd.d && x_out->cores && x_out->ranks, "invalid x_out descriptor");
-    t2s2::SolveOptions o;
-    if (opts) {
-      T2S2_CHECK(std::isfinite(opts->tol) && opts->tol > 0.0 && std::isfinite(opts->target), "bad tolerances");
-      T2S2_CHECK(opts->max_sweeps >= 1 && opts->kick >= 0 && opts->init_rank >= 1, "bad sweep/kick/rank options");
-      o.tol = opts->tol;
-      o.target = opts->target;
-      o.max_sweeps = opts->max_sweeps;
-      o.kick = opts->kick;
-      o.rank_cap = opts->rank_cap;
-      o.init_rank = opts->init_rank;
-      o.seed = opts->seed;
-      o.check_every = opts->check_every;
-      o.verbose = opts->verbose;
+    T2S2_CHECK(count >= 0, "count must be >= 0");
+    if (count == 0) return T2S2_OK;
+    T2S2_CHECK(probs && f && x_out, "NULL argument");
+    T2S2_CHECK(workers >= 0 && workers <= 64, "workers must be in [0, 64]");
+    std::vector<t2s2_problem*> ps(probs, probs + count);
+    for (int i = 0; i < count; ++i) T2S2_CHECK(ps[i] && f[i] && x_out[i], "NULL problem, f or x_out entry");
+    {
+      std::vector<t2s2_problem*> sorted = ps;
+      std::sort(sorted.begin(), sorted.end());
+      T2S2_CHECK(std::adjacent_find(sorted.begin(), sorted.end()) == sorted.end(),
+                 "each instance needs its own t2s2_problem");
     }
-    t2s2::DTT xd;
-    xd.d = fd.d;
-    xd.n = fd.n;
-    xd.r.assign(fd.d + 1, 1);
-    xd.c.assign(x_out->cores, x_out->cores + fd.d);
-    t2s2::DTT x0d;
-    const t2s2::DTT* x0p = nullptr;
-    if (x0) {
-      x0d = to_dtt(x0);
-      x0p = &x0d;
+    const int nw = std::min(count, workers > 0 ? workers : 16);
+    // longest first: cost ~ sum_l m_l * log10(10 / eps) (more unknowns per
+    // core and thinner layers need more rank)
+    std::vector<int> order(count);
+    std::vector<double> cost(count);
+    for (int i = 0; i < count; ++i) {
+      order[i] = i;
+      double sm = 0.0;
+      for (int m : ps[i]->P->m) sm += m;
+      cost[i] = sm * std::log10(10.0 / ps[i]->P->eps);
     }
-    t2s2::Ctx c = ctx_for(p, stream);
-    t2s2::SolveReport r;
-    const int st = t2s2::solve(*p->P, c, fd, x0p, o, xd, r);
-    for (int l = 0; l <= fd.d; ++l) x_out->ranks[l] = xd.r[l];
-    if (rep) {
-      std::memset(rep, 0, sizeof(*rep));
-      rep->status = st == 0 ? T2S2_OK : T2S2_ENOTCONV;
-      rep->sweeps = r.sweeps;
-      rep->max_rank = r.max_rank;
-      for (int l = 0; l <= fd.d && l <= T2S2_MAX_DIM; ++l) rep->ranks[l] = r.ranks[l];
-      rep->residual = r.residual;
-      rep->time_ms = r.time_ms;
-      const int h = std::min<int>((int)r.hist_res.size(), T2S2_MAX_HISTORY);
-      rep->history_len = h;
-      for (int i = 0; i < h; ++i) {
-        rep->history_residual[i] = r.hist_res[i];
-        rep->history_local[i] = r.hist_local[i];
-        rep->history_max_rank[i] = r.hist_rank[i];
-        rep->history_time_ms[i] = r.hist_time[i];
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    int device = 0;
+    T2S2_HIP(hipGetDevice(&device));
+    // every worker stream starts after the work already queued on stream
+    hipEvent_t ready;
+    T2S2_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    T2S2_HIP(hipEventRecord(ready, static_cast<hipStream_t>(stream)));
+    std::vector<int> codes(count, T2S2_OK);
+    std::vector<std::string> msgs(count);
+    std::atomic<int> next{0};
+    auto work = [&]() {
+      hipStream_t s = nullptr;
+      std::string fail;
+      if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
+          hipStreamWaitEvent(s, ready, 0) != hipSuccess)
+        fail = "worker stream set-up failed";
+      for (int k = next++; k < count; k = next++) {
+        const int i = order[k];
+        if (!fail.empty()) {
+          codes[i] = T2S2_EHIP;
+          msgs[i] = fail;
+          continue;
+        }
+        codes[i] = guarded([&] {
+          return solve_one(ps[i], f[i], x0 ? x0[i] : nullptr, opts, x_out[i], reps ? &reps[i] : nullptr, s);
+        });
+        if (codes[i] != T2S2_OK) msgs[i] = t2s2_last_error();
       }
-    }
-    if (st != 0) t2s2::set_last_error("tolerance not met within max_sweeps");
-    return st == 0 ? T2S2_OK : T2S2_ENOTCONV;
+      if (s) (void)hipStreamDestroy(s);
+    };
+    std::vector<std::thread> pool;
+    pool.reserve(nw);
+    for (int w = 0; w < nw; ++w) pool.emplace_back(work);
+    for (auto& t : pool) t.join();
+    (void)hipEventDestroy(ready);
+    // a hard error outranks "not converged"; report the first of the worst
+    int worst = T2S2_OK;
+    std::string first;
+    for (int pass = 0; pass < 2 && worst == T2S2_OK; ++pass)
+      for (int i = 0; i < count; ++i) {
+        const bool hard = codes[i] != T2S2_OK && codes[i] != T2S2_ENOTCONV;
+        if ((pass == 0 && hard) || (pass == 1 && codes[i] == T2S2_ENOTCONV)) {
+          worst = codes[i];
+          first = "instance " + std::to_string(i) + ": " + msgs[i];
+          break;
+        }
+      }
+    if (worst != T2S2_OK) t2s2::set_last_error(first);
+    return worst;
   });
 }
 

@@ -79,6 +79,36 @@ __device__ inline double2 cdiv(double2 a, double2 b) {
   const double r = b.x / b.y, den = b.x * r + b.y;
   return make_double2((a.x * r + a.y) / den, (a.y * r - a.x) / den);
 }
+// ---- complex single as float2 (the FP32 factorisations of mixed precision)
+__host__ __device__ inline float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__host__ __device__ inline float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__host__ __device__ inline float cabs2(float2 a) { return a.x * a.x + a.y * a.y; }
+__device__ inline float cabs(float2 a) { return hypotf(a.x, a.y); }
+__device__ inline float2 cdiv(float2 a, float2 b) {
+  if (fabsf(b.x) >= fabsf(b.y)) {
+    const float r = b.y / b.x, den = b.x + b.y * r;
+    return make_float2((a.x + a.y * r) / den, (a.y - a.x * r) / den);
+  }
+  const float r = b.x / b.y, den = b.x * r + b.y;
+  return make_float2((a.x * r + a.y) / den, (a.y * r - a.x) / den);
+}
+
+// complex type of a real type, and its constructor
+template <class R> struct CxOf;
+template <> struct CxOf<double> {
+  using type = double2;
+  __host__ __device__ static double2 make(double re, double im) { return make_double2(re, im); }
+};
+template <> struct CxOf<float> {
+  using type = float2;
+  __host__ __device__ static float2 make(float re, float im) { return make_float2(re, im); }
+};
+
 __device__ inline double2 csqrt(double2 z) {
   const double r = hypot(z.x, z.y);
   if (r == 0.0) return make_double2(0.0, 0.0);

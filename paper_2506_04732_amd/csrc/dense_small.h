@@ -10,6 +10,7 @@ void chol_skip(hipStream_t s, int n, const double* G, double* R, int* mask, int*
 // Inverse of a nonsingular upper-triangular n x n matrix.
 void trtri_upper(hipStream_t s, int n, const double* R, double* Rinv);
 void trtri_upper(hipStream_t s, int n, const double2* R, double2* Rinv);
+void trtri_upper(hipStream_t s, int n, const float2* R, float2* Rinv);
 // B (k x c) = U Wt, U (k x k) orthogonal, rows of Wt orthogonal and sorted by
 // decreasing norm sigma.  B and JT (k x k) are overwritten as workspace;
 // info needs k + 1 ints (info[0] = sweeps used).
@@ -17,17 +18,22 @@ void jacobi_rows(hipStream_t s, int k, int c, double* B, double* JT, double* U, 
                  int* info, int max_sweeps = 60);
 // A (n x n) <- H = Q^T A Q upper Hessenberg, QT <- Q^T; work >= 2n doubles.
 void hessenberg(hipStream_t s, int n, double* A, double* QT, double* work);
+void hessenberg(hipStream_t s, int n, float* A, float* QT, float* work);
 // Real Schur form of a real upper Hessenberg H (n x n, n <= 512) by the
 // Francis double-shift QR iteration: H = Z T Z^T, T quasi upper triangular
 // (1 x 1 and 2 x 2 diagonal blocks).  ZT (n x n) holds an initial Z^T on input
 // and receives (Z_in Z)^T; Hwork: n*n doubles (used when H exceeds LDS);
 // info[0] = Francis steps (negative if the iteration cap was hit).
 void schur_francis(hipStream_t s, int n, const double* H, double* Hwork, double* ZT, double* T, int* info);
+void schur_francis(hipStream_t s, int n, const float* H, float* Hwork, float* ZT, float* T, int* info);
 // Real Schur form -> complex Schur form: Tc = P^H T P upper triangular and
 // ZTc = (Z P)^T with P block diagonal unitary; bstart: n ints, U: 2n complex.
 void rsf2csf(hipStream_t s, int n, const double* T, const double* ZT, double2* Tc, double2* ZTc, int* bstart,
              double2* U);
+void rsf2csf(hipStream_t s, int n, const float* T, const float* ZT, float2* Tc, float2* ZTc, int* bstart,
+             float2* U);
 // Unit upper-triangular Y with T Y = Y diag(T).
 void trevec(hipStream_t s, int n, const double2* T, double2* Y);
+void trevec(hipStream_t s, int n, const float2* T, float2* Y);
 
 }  // namespace t2s2

@@ -18,6 +18,14 @@ namespace {
 
 constexpr int kNT = 1024;          // threads of the single workgroup
 constexpr long kLdsDoubles = 20000;  // LDS budget of these kernels (160000 B)
+constexpr long kLdsBytes = 160000;
+
+template <class R> struct TinyOf;   // a safe "negligible" magnitude
+template <> struct TinyOf<double> { static constexpr double value = 1e-290; };
+template <> struct TinyOf<float> { static constexpr float value = 1e-35f; };
+template <class R> struct EpsOf;    // unit roundoff
+template <> struct EpsOf<double> { static constexpr double value = DBL_EPSILON; };
+template <> struct EpsOf<float> { static constexpr float value = FLT_EPSILON; };
 
 __device__ inline double block_max(double v, double* red) {
   // all threads participate; red holds kNT/64 doubles
@@ -111,6 +119,15 @@ struct TriOps<double2> {
   __device__ static double2 fma(double2 a, double2 b, double2 c) { return cadd(cmul(a, b), c); }
   __device__ static double2 div(double2 a, double2 b) { return cdiv(a, b); }
   __device__ static double2 neg(double2 a) { return make_double2(-a.x, -a.y); }
+};
+
+template <>
+struct TriOps<float2> {
+  __device__ static float2 zero() { return make_float2(0.0f, 0.0f); }
+  __device__ static float2 one() { return make_float2(1.0f, 0.0f); }
+  __device__ static float2 fma(float2 a, float2 b, float2 c) { return cadd(cmul(a, b), c); }
+  __device__ static float2 div(float2 a, float2 b) { return cdiv(a, b); }
+  __device__ static float2 neg(float2 a) { return make_float2(-a.x, -a.y); }
 };
 
 template <class T>
@@ -252,17 +269,18 @@ __global__ void __launch_bounds__(kNT) jacobi_rows_kernel(int k, int c, double* 
 // ------------------------------------------------- Hessenberg reduction
 // A (n x n, real, row-major) -> H = Q^T A Q upper Hessenberg, by Householder
 // reflectors on columns 0..n-3.  QT receives Q^T.
-template <bool LDS>
-__global__ void __launch_bounds__(kNT) hessenberg_kernel(int n, double* __restrict__ A, double* __restrict__ QT,
-                                                         double* __restrict__ work) {
-  extern __shared__ double lds[];
-  __shared__ double red[kNT / 64];
-  __shared__ double s_alpha, s_vnorm2;
+template <bool LDS, class R>
+__global__ void __launch_bounds__(kNT) hessenberg_kernel(int n, R* __restrict__ A, R* __restrict__ QT,
+                                                         R* __restrict__ work) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  R* lds = reinterpret_cast<R*>(lds_raw);
+  __shared__ R red[kNT / 64];
+  __shared__ R s_alpha, s_vnorm2;
   const long nn = (long)n * n;
   constexpr bool in_lds = LDS;
-  double* H;
-  double* v;  // reflector (n)
-  double* w;  // products (n)
+  R* H;
+  R* v;  // reflector (n)
+  R* w;  // products (n)
   if constexpr (LDS) {
     H = lds;
     v = lds + nn;
@@ -274,13 +292,13 @@ __global__ void __launch_bounds__(kNT) hessenberg_kernel(int n, double* __restri
   }
   if (in_lds)
     for (long e = threadIdx.x; e < nn; e += blockDim.x) H[e] = A[e];
-  for (long e = threadIdx.x; e < nn; e += blockDim.x) QT[e] = ((e / n) == (e % n)) ? 1.0 : 0.0;
+  for (long e = threadIdx.x; e < nn; e += blockDim.x) QT[e] = ((e / n) == (e % n)) ? R(1.0) : R(0.0);
   __syncthreads();
   for (int k = 0; k < n - 2; ++k) {
     // x = H[k+1:, k]
-    double s = 0.0;
+    R s = R(0.0);
     for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) {
-      const double x = H[(long)i * n + k];
+      const R x = H[(long)i * n + k];
       v[i] = x;
       s = fma(x, x, s);
     }
@@ -290,26 +308,26 @@ __global__ void __launch_bounds__(kNT) hessenberg_kernel(int n, double* __restri
     if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = s;
     __syncthreads();
     if (threadIdx.x == 0) {
-      double tot = 0.0;
+      R tot = R(0.0);
       for (int i = 0; i < (int)(blockDim.x / 64); ++i) tot += red[i];
-      const double x0 = v[k + 1];
-      const double tail = tot - x0 * x0;
-      if (tail <= 1e-300 * fmax(1.0, tot)) {
-        s_vnorm2 = 0.0;  // already in Hessenberg form for this column
+      const R x0 = v[k + 1];
+      const R tail = tot - x0 * x0;
+      if (tail <= TinyOf<R>::value * fmax(R(1.0), tot)) {
+        s_vnorm2 = R(0.0);  // already in Hessenberg form for this column
       } else {
-        const double alpha = (x0 >= 0.0) ? -sqrt(tot) : sqrt(tot);
+        const R alpha = (x0 >= R(0.0)) ? -sqrt(tot) : sqrt(tot);
         s_alpha = alpha;
         v[k + 1] = x0 - alpha;
         s_vnorm2 = tail + (x0 - alpha) * (x0 - alpha);
       }
     }
     __syncthreads();
-    const double vn2 = s_vnorm2;
-    if (vn2 == 0.0) continue;
-    const double beta = 2.0 / vn2;
+    const R vn2 = s_vnorm2;
+    if (vn2 == R(0.0)) continue;
+    const R beta = R(2.0) / vn2;
     // left: H[k+1:, :] -= beta v (v^T H[k+1:, :]) ; columns k..n-1 suffice
     for (int j = k + threadIdx.x; j < n; j += blockDim.x) {
-      double d = 0.0;
+      R d = R(0.0);
       for (int i = k + 1; i < n; ++i) d = fma(v[i], H[(long)i * n + j], d);
       w[j] = beta * d;
     }
@@ -325,7 +343,7 @@ __global__ void __launch_bounds__(kNT) hessenberg_kernel(int n, double* __restri
     __syncthreads();
     // right: H[:, k+1:] -= beta (H[:, k+1:] v) v^T
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      double d = 0.0;
+      R d = R(0.0);
       for (int j = k + 1; j < n; ++j) d = fma(H[(long)i * n + j], v[j], d);
       w[i] = beta * d;
     }
@@ -341,7 +359,7 @@ __global__ void __launch_bounds__(kNT) hessenberg_kernel(int n, double* __restri
     __syncthreads();
     // QT = P QT (P symmetric): rows k+1.. of QT: QT[k+1:, :] -= beta v (v^T QT[k+1:, :])
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
-      double d = 0.0;
+      R d = R(0.0);
       for (int i = k + 1; i < n; ++i) d = fma(v[i], QT[(long)i * n + j], d);
       w[j] = beta * d;
     }
@@ -356,7 +374,7 @@ __global__ void __launch_bounds__(kNT) hessenberg_kernel(int n, double* __restri
     }
     __syncthreads();
     // exact zeros below the subdiagonal of column k
-    for (int i = k + 2 + threadIdx.x; i < n; i += blockDim.x) H[(long)i * n + k] = 0.0;
+    for (int i = k + 2 + threadIdx.x; i < n; i += blockDim.x) H[(long)i * n + k] = R(0.0);
     __syncthreads();
   }
   if (in_lds)
@@ -368,28 +386,29 @@ __global__ void __launch_bounds__(kNT) hessenberg_kernel(int n, double* __restri
 // (T[:k,:k] - t_kk I) y = -T[:k, k].  Rows are produced bottom-up for all
 // columns at once.  Denominators below smin = max(ulp |t_kk|, tiny) are
 // replaced by smin (as in standard eigenvector codes).
-__global__ void __launch_bounds__(kNT) trevec_kernel(int n, const double2* __restrict__ T, double2* __restrict__ Y) {
+template <class R>
+__global__ void __launch_bounds__(kNT) trevec_kernel(int n, const typename CxOf<R>::type* __restrict__ T,
+                                                     typename CxOf<R>::type* __restrict__ Y) {
+  using CX = CxOf<R>;
   const long nn = (long)n * n;
   for (long e = threadIdx.x; e < nn; e += blockDim.x) {
     const int i = (int)(e / n), j = (int)(e % n);
-    Y[e] = (i == j) ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0);
+    Y[e] = (i == j) ? CX::make(R(1.0), R(0.0)) : CX::make(R(0.0), R(0.0));
   }
   __syncthreads();
-  double tnorm = 0.0;
   for (int i = n - 1; i >= 0; --i) {
-    const double2 tii = T[(long)i * n + i];
+    const auto tii = T[(long)i * n + i];
     for (int k = i + 1 + threadIdx.x; k < n; k += blockDim.x) {
-      double2 s = T[(long)i * n + k];  // times y_k = 1
+      auto s = T[(long)i * n + k];  // times y_k = 1
       for (int t = i + 1; t < k; ++t) s = cadd(s, cmul(T[(long)i * n + t], Y[(long)t * n + k]));
-      const double2 tkk = T[(long)k * n + k];
-      double2 den = csub(tii, tkk);
-      const double smin = fmax(DBL_EPSILON * cabs(tkk), 1e-290);
-      if (cabs(den) < smin) den = make_double2(smin, 0.0);
-      Y[(long)i * n + k] = cdiv(make_double2(-s.x, -s.y), den);
+      const auto tkk = T[(long)k * n + k];
+      auto den = csub(tii, tkk);
+      const R smin = fmax(EpsOf<R>::value * cabs(tkk), TinyOf<R>::value);
+      if (cabs(den) < smin) den = CX::make(smin, R(0.0));
+      Y[(long)i * n + k] = cdiv(CX::make(-s.x, -s.y), den);
     }
     __syncthreads();
   }
-  (void)tnorm;
 }
 
 }  // namespace
@@ -420,6 +439,12 @@ void trtri_upper(hipStream_t s, int n, const double2* R, double2* Rinv) {
   T2S2_LAUNCH_CHECK();
 }
 
+void trtri_upper(hipStream_t s, int n, const float2* R, float2* Rinv) {
+  TimedScope ts(s, KC_TRTRI, 8.0 * n * n, 4.0 * n * n * n / 3.0);
+  hipLaunchKernelGGL(trtri_upper_kernel<float2>, dim3(1), dim3(kNT), 0, s, n, R, Rinv);
+  T2S2_LAUNCH_CHECK();
+}
+
 void jacobi_rows(hipStream_t s, int k, int c, double* B, double* JT, double* U, double* Wt, double* sigma,
                  int* info, int max_sweeps) {
   T2S2_CHECK(k >= 1 && c >= 1, "jacobi_rows: bad size");
@@ -439,20 +464,26 @@ void jacobi_rows(hipStream_t s, int k, int c, double* B, double* JT, double* U, 
   T2S2_LAUNCH_CHECK();
 }
 
-void hessenberg(hipStream_t s, int n, double* A, double* QT, double* work) {
-  const long need = (long)n * n + 2L * n;
-  TimedScope ts(s, KC_HESS, 8.0 * 3.0 * n * n, 14.0 * n * n * n / 3.0);
-  if (need <= kLdsDoubles)
-    hipLaunchKernelGGL(hessenberg_kernel<true>, dim3(1), dim3(kNT), lds_bytes(need), s, n, A, QT, work);
+template <class R>
+static void hessenberg_t(hipStream_t s, int n, R* A, R* QT, R* work) {
+  const long need = ((long)n * n + 2L * n) * (long)sizeof(R);
+  TimedScope ts(s, KC_HESS, sizeof(R) * 3.0 * n * n, 14.0 * n * n * n / 3.0);
+  if (need <= kLdsBytes)
+    hipLaunchKernelGGL((hessenberg_kernel<true, R>), dim3(1), dim3(kNT), (size_t)need, s, n, A, QT, work);
   else
-    hipLaunchKernelGGL(hessenberg_kernel<false>, dim3(1), dim3(kNT), 0, s, n, A, QT, work);
+    hipLaunchKernelGGL((hessenberg_kernel<false, R>), dim3(1), dim3(kNT), 0, s, n, A, QT, work);
   T2S2_LAUNCH_CHECK();
 }
+void hessenberg(hipStream_t s, int n, double* A, double* QT, double* work) { hessenberg_t<double>(s, n, A, QT, work); }
+void hessenberg(hipStream_t s, int n, float* A, float* QT, float* work) { hessenberg_t<float>(s, n, A, QT, work); }
 
-void trevec(hipStream_t s, int n, const double2* T, double2* Y) {
-  TimedScope ts(s, KC_TREVEC, 16.0 * 2.0 * n * n, 8.0 * n * n * n / 6.0);
-  hipLaunchKernelGGL(trevec_kernel, dim3(1), dim3(kNT), 0, s, n, T, Y);
+template <class R>
+static void trevec_t(hipStream_t s, int n, const typename CxOf<R>::type* T, typename CxOf<R>::type* Y) {
+  TimedScope ts(s, KC_TREVEC, 2.0 * sizeof(R) * 2.0 * n * n, 8.0 * n * n * n / 6.0);
+  hipLaunchKernelGGL(trevec_kernel<R>, dim3(1), dim3(kNT), 0, s, n, T, Y);
   T2S2_LAUNCH_CHECK();
 }
+void trevec(hipStream_t s, int n, const double2* T, double2* Y) { trevec_t<double>(s, n, T, Y); }
+void trevec(hipStream_t s, int n, const float2* T, float2* Y) { trevec_t<float>(s, n, T, Y); }
 
 }  // namespace t2s2

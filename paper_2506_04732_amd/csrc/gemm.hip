@@ -179,7 +179,9 @@ struct SplitWork {
     if (p) (void)hipFree(p);
   }
 };
-SplitWork g_split;
+// one workspace per host thread: concurrent solves (batched mode) drive
+// their own streams from their own threads
+thread_local SplitWork g_split;
 
 template <class T>
 T* split_workspace(size_t count) {

@@ -86,6 +86,8 @@ int trunc_svd(const Ctx& c, int M, int n, const double* A, long lda, double delt
 // form by shifted QR, triangular eigenvectors.  Outputs complex n x n V, Vinv
 // and n eigenvalues.
 void eig_nonsym(const Ctx& c, int n, const double* A, double2* lam, double2* V, double2* Vinv);
+// The same factorisation computed in FP32 from A rounded to FP32.
+void eig_nonsym(const Ctx& c, int n, const double* A, float2* lam, float2* V, float2* Vinv);
 
 // A (n x n real) = Z T Z^H; outputs ZT = Z^T and upper-triangular T.
 void schur_real(const Ctx& c, int n, const double* A, double2* ZT, double2* T);

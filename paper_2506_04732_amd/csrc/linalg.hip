@@ -53,6 +53,8 @@ template <>
 double one_v<double>() { return 1.0; }
 template <>
 double2 one_v<double2>() { return make_double2(1.0, 0.0); }
+template <>
+float2 one_v<float2>() { return make_float2(1.0f, 0.0f); }
 
 template <class T>
 void mode1(const Ctx& c, int rA, int r0, int m, int r1, const T* A, const T* X, T* Y, T beta, Op opA) {
@@ -79,6 +81,9 @@ template void mode3<double>(const Ctx&, int, int, int, int, const double*, const
 template void mode3<double2>(const Ctx&, int, int, int, int, const double2*, const double2*, double2*, double2, Op);
 template void mode2<double>(const Ctx&, int, int, int, int, const double*, const double*, double*, double, Op);
 template void mode2<double2>(const Ctx&, int, int, int, int, const double2*, const double2*, double2*, double2, Op);
+template void mode1<float2>(const Ctx&, int, int, int, int, const float2*, const float2*, float2*, float2, Op);
+template void mode3<float2>(const Ctx&, int, int, int, int, const float2*, const float2*, float2*, float2, Op);
+template void mode2<float2>(const Ctx&, int, int, int, int, const float2*, const float2*, float2*, float2, Op);
 
 // ------------------------------------------------------------ dcholqr
 int dcholqr(const Ctx& c, int M, int n, const double* A, long lda, double* Qout, double* Rout, double drop) {
@@ -244,6 +249,32 @@ void eig_nonsym(const Ctx& c, int n, const double* A, double2* lam, double2* V, 
   const double2 one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0);
   gemm<double2>(c.s, OpT, OpN, n, n, n, one, ZT, n, 0, Y, n, 0, zero, V, n, 0, 1);
   gemm<double2>(c.s, OpN, OpR, n, n, n, one, Yi, n, 0, ZT, n, 0, zero, Vinv, n, 0, 1);
+  diag_complex(c.s, n, T, n, lam);
+}
+
+void eig_nonsym(const Ctx& c, int n, const double* A, float2* lam, float2* V, float2* Vinv) {
+  Scratch& S = *c.sc;
+  float* H = S.get<float>("eig32.H", (size_t)n * n);
+  float* QT = S.get<float>("eig32.QT", (size_t)n * n);
+  float* work = S.get<float>("eig32.work", 2 * (size_t)n);
+  float* Hw = S.get<float>("eig32.Hw", (size_t)n * n);
+  float* Tr = S.get<float>("eig32.Tr", (size_t)n * n);
+  int* info = S.get<int>("eig32.info", 1);
+  int* bstart = S.get<int>("eig32.bstart", n);
+  float2* U = S.get<float2>("eig32.U2", 2 * (size_t)n);
+  float2* ZT = S.get<float2>("eig32.ZT", (size_t)n * n);
+  float2* T = S.get<float2>("eig32.T", (size_t)n * n);
+  float2* Y = S.get<float2>("eig32.Y", (size_t)n * n);
+  float2* Yi = S.get<float2>("eig32.Yi", (size_t)n * n);
+  to_float(c.s, A, H, (long)n * n);
+  hessenberg(c.s, n, H, QT, work);
+  schur_francis(c.s, n, H, Hw, QT, Tr, info);
+  rsf2csf(c.s, n, Tr, QT, T, ZT, bstart, U);
+  trevec(c.s, n, T, Y);
+  trtri_upper(c.s, n, Y, Yi);
+  const float2 one = make_float2(1.0f, 0.0f), zero = make_float2(0.0f, 0.0f);
+  gemm<float2>(c.s, OpT, OpN, n, n, n, one, ZT, n, 0, Y, n, 0, zero, V, n, 0, 1);
+  gemm<float2>(c.s, OpN, OpR, n, n, n, one, Yi, n, 0, ZT, n, 0, zero, Vinv, n, 0, 1);
   diag_complex(c.s, n, T, n, lam);
 }
 

@@ -4,7 +4,8 @@
 //
 // One workgroup.  The Hessenberg matrix lives in LDS in packed row form (row
 // i keeps columns max(0, i-3) .. n-1: the 3 x 3 bulge reaches three below the
-// diagonal) whenever it fits (n <= ~190 in FP64), else in global memory.  The
+// diagonal) whenever it fits (n <= ~195 in FP64, ~275 in FP32), else in
+// global memory.  Both precisions share one template.  The
 // Schur vectors (rows of Z^T) are updated lazily: the reflectors of up to kFB
 // consecutive bulge-chase steps are multiplied into a small (kFB+3)^2 matrix
 // in LDS and applied to the affected rows of Z^T in one pass, so the chase
@@ -20,31 +21,33 @@ namespace {
 constexpr int kFqThreads = 256;
 constexpr int kFB = 16;          // reflectors per Z batch
 constexpr int kFG = kFB + 3;     // rows covered by one batch
-constexpr long kFqLds = 20000 - kFG * kFG - 600;  // doubles of dynamic LDS for H
+// bytes of dynamic LDS for the packed H: 160 KB less the static arrays
+template <class R>
+constexpr long kFqLdsBytes = 160000 - (long)(kFG * kFG) * sizeof(R) - 514 * 4 - 256;
 
 __host__ __device__ inline int row_start(int i) { return i > 3 ? i - 3 : 0; }
 
-template <bool LDS>
+template <bool LDS, class R>
 struct HStore {
-  double* base;
+  R* base;
   const int* rowoff;  // LDS: offset of row i in the packed array
   int n;
-  __device__ double& at(int i, int j) const {
+  __device__ R& at(int i, int j) const {
     if constexpr (LDS) return base[rowoff[i] + (j - row_start(i))];
     else return base[(long)i * n + j];
   }
 };
 
-template <bool LDS>
-__global__ void __launch_bounds__(kFqThreads) francis_kernel(int n, const double* __restrict__ Hin,
-                                                             double* __restrict__ Hg, double* __restrict__ ZT,
-                                                             double* __restrict__ Tout, int* __restrict__ info,
-                                                             int max_iter) {
-  extern __shared__ double lds[];
-  __shared__ double G[kFG * kFG];
+template <bool LDS, class R>
+__global__ void __launch_bounds__(kFqThreads) francis_kernel(int n, const R* __restrict__ Hin, R* __restrict__ Hg,
+                                                             R* __restrict__ ZT, R* __restrict__ Tout,
+                                                             int* __restrict__ info, int max_iter) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  R* lds = reinterpret_cast<R*>(lds_raw);
+  __shared__ R G[kFG * kFG];
   __shared__ int rowoff[513];
   __shared__ int s_l, s_hi, s_it, s_done, s_zk0, s_zcnt, s_zlast;
-  __shared__ double s_shift[2];
+  __shared__ R s_shift[2];
   if constexpr (LDS) {
     if (threadIdx.x == 0) {
       int o = 0;
@@ -56,10 +59,10 @@ __global__ void __launch_bounds__(kFqThreads) francis_kernel(int n, const double
     }
   }
   __syncthreads();
-  HStore<LDS> H{LDS ? lds : Hg, rowoff, n};
+  HStore<LDS, R> H{LDS ? lds : Hg, rowoff, n};
   for (long e = threadIdx.x; e < (long)n * n; e += blockDim.x) {
     const int i = (int)(e / n), j = (int)(e % n);
-    if (j >= row_start(i)) H.at(i, j) = (j >= i - 1) ? Hin[e] : 0.0;
+    if (j >= row_start(i)) H.at(i, j) = (j >= i - 1) ? Hin[e] : R(0.0);
   }
   if (threadIdx.x == 0) {
     s_hi = n - 1;
@@ -77,13 +80,13 @@ __global__ void __launch_bounds__(kFqThreads) francis_kernel(int n, const double
     if (cnt > 0) {
       const int rows = min(kFG, n - k0);
       for (int col = threadIdx.x; col < n; col += blockDim.x) {
-        double old[kFG];
+        R old[kFG];
 #pragma unroll
-        for (int b = 0; b < kFG; ++b) old[b] = (b < rows) ? ZT[(long)(k0 + b) * n + col] : 0.0;
+        for (int b = 0; b < kFG; ++b) old[b] = (b < rows) ? ZT[(long)(k0 + b) * n + col] : R(0.0);
 #pragma unroll
         for (int a = 0; a < kFG; ++a) {
           if (a >= rows) break;
-          double acc = 0.0;
+          R acc = R(0.0);
 #pragma unroll
           for (int b = 0; b < kFG; ++b) acc = fma(G[a * kFG + b], old[b], acc);
           ZT[(long)(k0 + a) * n + col] = acc;
@@ -99,7 +102,7 @@ __global__ void __launch_bounds__(kFqThreads) francis_kernel(int n, const double
   auto batch_open = [&](int a, int w) {
     if (s_zcnt > 0 && (a < s_zlast || a + w - 1 > s_zk0 + kFG - 1)) flush();
     if (s_zcnt == 0) {
-      for (int e = threadIdx.x; e < kFG * kFG; e += blockDim.x) G[e] = ((e / kFG) == (e % kFG)) ? 1.0 : 0.0;
+      for (int e = threadIdx.x; e < kFG * kFG; e += blockDim.x) G[e] = ((e / kFG) == (e % kFG)) ? R(1.0) : R(0.0);
       __syncthreads();
       if (threadIdx.x == 0) s_zk0 = a;
       __syncthreads();
@@ -108,16 +111,16 @@ __global__ void __launch_bounds__(kFqThreads) francis_kernel(int n, const double
 
   // apply the reflector P = I - tau v v^T (rows a..a+w-1) to H (rows from
   // column c0, columns up to row r1) and to the batch matrix G
-  auto reflect = [&](int a, int w, double v0, double v1, double v2, double tau, int c0, int r1, int zero_col) {
+  auto reflect = [&](int a, int w, R v0, R v1, R v2, R tau, int c0, int r1, int zero_col) {
     batch_open(a, w);
     const int ga = a - s_zk0;
     for (int j = c0 + threadIdx.x; j < n; j += blockDim.x) {
-      const double h0 = H.at(a, j), h1 = H.at(a + 1, j), h2 = (w == 3) ? H.at(a + 2, j) : 0.0;
-      const double s = tau * (v0 * h0 + v1 * h1 + v2 * h2);
+      const R h0 = H.at(a, j), h1 = H.at(a + 1, j), h2 = (w == 3) ? H.at(a + 2, j) : R(0.0);
+      const R s = tau * (v0 * h0 + v1 * h1 + v2 * h2);
       if (j == zero_col) {
         H.at(a, j) = h0 - s * v0;
-        H.at(a + 1, j) = 0.0;
-        if (w == 3) H.at(a + 2, j) = 0.0;
+        H.at(a + 1, j) = R(0.0);
+        if (w == 3) H.at(a + 2, j) = R(0.0);
       } else {
         H.at(a, j) = h0 - s * v0;
         H.at(a + 1, j) = h1 - s * v1;
@@ -125,16 +128,16 @@ __global__ void __launch_bounds__(kFqThreads) francis_kernel(int n, const double
       }
     }
     for (int c = threadIdx.x; c < kFG; c += blockDim.x) {
-      const double g0 = G[ga * kFG + c], g1 = G[(ga + 1) * kFG + c], g2 = (w == 3) ? G[(ga + 2) * kFG + c] : 0.0;
-      const double s = tau * (v0 * g0 + v1 * g1 + v2 * g2);
+      const R g0 = G[ga * kFG + c], g1 = G[(ga + 1) * kFG + c], g2 = (w == 3) ? G[(ga + 2) * kFG + c] : R(0.0);
+      const R s = tau * (v0 * g0 + v1 * g1 + v2 * g2);
       G[ga * kFG + c] = g0 - s * v0;
       G[(ga + 1) * kFG + c] = g1 - s * v1;
       if (w == 3) G[(ga + 2) * kFG + c] = g2 - s * v2;
     }
     __syncthreads();
     for (int i = threadIdx.x; i <= r1; i += blockDim.x) {
-      const double h0 = H.at(i, a), h1 = H.at(i, a + 1), h2 = (w == 3) ? H.at(i, a + 2) : 0.0;
-      const double s = tau * (h0 * v0 + h1 * v1 + h2 * v2);
+      const R h0 = H.at(i, a), h1 = H.at(i, a + 1), h2 = (w == 3) ? H.at(i, a + 2) : R(0.0);
+      const R s = tau * (h0 * v0 + h1 * v1 + h2 * v2);
       H.at(i, a) = h0 - s * v0;
       H.at(i, a + 1) = h1 - s * v1;
       if (w == 3) H.at(i, a + 2) = h2 - s * v2;
@@ -147,9 +150,9 @@ __global__ void __launch_bounds__(kFqThreads) francis_kernel(int n, const double
   };
 
   // deflation threshold: the factorisation only feeds the exact-solve
-  // preconditioner inside FP64 refinement, so subdiagonals below 1e-13 of
-  // their neighbours are dropped (a relative perturbation of that size)
-  const double ulp = 1e-13;
+  // preconditioner inside FP64 refinement, so subdiagonals below 1e-13 (FP64)
+  // or one FP32 ulp of their neighbours are dropped
+  const R ulp = sizeof(R) == 8 ? (R)1e-13 : (R)FLT_EPSILON;
   int total = 0;
   while (true) {
     // ---- deflation: largest l <= hi with a negligible subdiagonal
@@ -157,14 +160,14 @@ __global__ void __launch_bounds__(kFqThreads) francis_kernel(int n, const double
     __syncthreads();
     int hi = s_hi;
     for (int i = 1 + threadIdx.x; i <= hi; i += blockDim.x) {
-      double sc = fabs(H.at(i - 1, i - 1)) + fabs(H.at(i, i));
-      if (sc == 0.0) sc = 1.0;
+      R sc = fabs(H.at(i - 1, i - 1)) + fabs(H.at(i, i));
+      if (sc == R(0.0)) sc = R(1.0);
       if (fabs(H.at(i, i - 1)) <= ulp * sc) atomicMax(&s_l, i);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
       const int l = s_l;
-      if (l >= 1 && l <= hi) H.at(l, l - 1) = 0.0;
+      if (l >= 1 && l <= hi) H.at(l, l - 1) = R(0.0);
       if (hi < 0) {
         s_done = 1;
       } else if (l >= hi - 1) {
@@ -173,11 +176,11 @@ __global__ void __launch_bounds__(kFqThreads) francis_kernel(int n, const double
         s_l = -1;
         if (l - 1 < 0) s_done = 1;
       } else {
-        const double a = H.at(hi - 1, hi - 1), b = H.at(hi - 1, hi), c = H.at(hi, hi - 1), d = H.at(hi, hi);
-        double sum = a + d, prod = a * d - b * c;
+        const R a = H.at(hi - 1, hi - 1), b = H.at(hi - 1, hi), c = H.at(hi, hi - 1), d = H.at(hi, hi);
+        R sum = a + d, prod = a * d - b * c;
         if (s_it > 0 && s_it % 10 == 0) {
-          const double e = fabs(c) + fabs(H.at(hi - 1, hi - 2));
-          sum = 1.5 * e;
+          const R e = fabs(c) + fabs(H.at(hi - 1, hi - 2));
+          sum = R(1.5) * e;
           prod = e * e;
         }
         s_shift[0] = sum;
@@ -191,44 +194,44 @@ __global__ void __launch_bounds__(kFqThreads) francis_kernel(int n, const double
     hi = s_hi;
     if (l < 0) continue;
     ++total;
-    // ---- one Francis double-shift step on [l, hi]
-    const double sum = s_shift[0], prod = s_shift[1];
+    // ---- one Francis R-shift step on [l, hi]
+    const R sum = s_shift[0], prod = s_shift[1];
     const int p = hi - l + 1;
-    double x, y, z;
+    R x, y, z;
     {
-      const double h00 = H.at(l, l), h01 = H.at(l, l + 1), h10 = H.at(l + 1, l), h11 = H.at(l + 1, l + 1);
-      const double h21 = H.at(l + 2, l + 1);
+      const R h00 = H.at(l, l), h01 = H.at(l, l + 1), h10 = H.at(l + 1, l), h11 = H.at(l + 1, l + 1);
+      const R h21 = H.at(l + 2, l + 1);
       x = h00 * h00 + h01 * h10 - sum * h00 + prod;
       y = h10 * (h00 + h11 - sum);
       z = h10 * h21;
     }
     for (int k = 0; k <= p - 3; ++k) {
       const int a = l + k;
-      const double sg = sqrt(x * x + y * y + z * z);
-      if (sg > 0.0 && (y != 0.0 || z != 0.0)) {
-        const double v0 = x + (x >= 0.0 ? sg : -sg);
-        const double tau = 2.0 / (v0 * v0 + y * y + z * z);
+      const R sg = sqrt(x * x + y * y + z * z);
+      if (sg > R(0.0) && (y != R(0.0) || z != R(0.0))) {
+        const R v0 = x + (x >= R(0.0) ? sg : -sg);
+        const R tau = R(2.0) / (v0 * v0 + y * y + z * z);
         const int c0 = l + (k > 0 ? k - 1 : 0);
         const int r1 = l + min(k + 3, p - 1);
         reflect(a, 3, v0, y, z, tau, c0, r1, k > 0 ? a - 1 : -1);
       }
       x = H.at(a + 1, a);
       y = H.at(a + 2, a);
-      z = (k < p - 3) ? H.at(a + 3, a) : 0.0;
+      z = (k < p - 3) ? H.at(a + 3, a) : R(0.0);
     }
     {
-      const double sg = sqrt(x * x + y * y);
-      if (sg > 0.0 && y != 0.0) {
-        const double v0 = x + (x >= 0.0 ? sg : -sg);
-        const double tau = 2.0 / (v0 * v0 + y * y);
-        reflect(hi - 1, 2, v0, y, 0.0, tau, hi - 2, hi, hi - 2);
+      const R sg = sqrt(x * x + y * y);
+      if (sg > R(0.0) && y != R(0.0)) {
+        const R v0 = x + (x >= R(0.0) ? sg : -sg);
+        const R tau = R(2.0) / (v0 * v0 + y * y);
+        reflect(hi - 1, 2, v0, y, R(0.0), tau, hi - 2, hi, hi - 2);
       }
     }
   }
   flush();
   for (long e = threadIdx.x; e < (long)n * n; e += blockDim.x) {
     const int i = (int)(e / n), j = (int)(e % n);
-    Tout[e] = (j >= i - 1 && j >= row_start(i)) ? H.at(i, j) : 0.0;
+    Tout[e] = (j >= i - 1 && j >= row_start(i)) ? H.at(i, j) : R(0.0);
   }
   if (threadIdx.x == 0) info[0] = s_done ? total : -total;
 }
@@ -237,41 +240,44 @@ __global__ void __launch_bounds__(kFqThreads) francis_kernel(int n, const double
 // complex upper-triangular Tc = P^H T P and Z'^T = (Z P)^T, with P block
 // diagonal: for each 2 x 2 block B, the unitary [v, w], v a unit eigenvector
 // of B, makes P^H B P upper triangular.
-__global__ void __launch_bounds__(256) rsf2csf_kernel(int n, const double* __restrict__ T,
-                                                      const double* __restrict__ ZT, double2* __restrict__ Tc,
-                                                      double2* __restrict__ ZTc, int* __restrict__ bstart,
-                                                      double2* __restrict__ U) {
+template <class R>
+__global__ void __launch_bounds__(256) rsf2csf_kernel(int n, const R* __restrict__ T, const R* __restrict__ ZT,
+                                                      typename CxOf<R>::type* __restrict__ Tc,
+                                                      typename CxOf<R>::type* __restrict__ ZTc,
+                                                      int* __restrict__ bstart, typename CxOf<R>::type* __restrict__ U) {
+  using C = typename CxOf<R>::type;
+  using CX = CxOf<R>;
   if (threadIdx.x == 0) {
     int k = 0;
     while (k < n) {
-      if (k + 1 < n && T[(long)(k + 1) * n + k] != 0.0) {
-        const double a = T[(long)k * n + k], b = T[(long)k * n + k + 1];
-        const double c = T[(long)(k + 1) * n + k], d = T[(long)(k + 1) * n + k + 1];
-        const double hm = 0.5 * (a - d);
-        const double disc = hm * hm + b * c;
-        double2 lam;
-        if (disc >= 0.0) {
-          const double sq = sqrt(disc);
-          lam = make_double2(0.5 * (a + d) + (hm >= 0.0 ? sq : -sq), 0.0);
+      if (k + 1 < n && T[(long)(k + 1) * n + k] != R(0.0)) {
+        const R a = T[(long)k * n + k], b = T[(long)k * n + k + 1];
+        const R c = T[(long)(k + 1) * n + k], d = T[(long)(k + 1) * n + k + 1];
+        const R hm = R(0.5) * (a - d);
+        const R disc = hm * hm + b * c;
+        C lam;
+        if (disc >= R(0.0)) {
+          const R sq = sqrt(disc);
+          lam = CX::make(R(0.5) * (a + d) + (hm >= R(0.0) ? sq : -sq), R(0.0));
         } else {
-          lam = make_double2(0.5 * (a + d), sqrt(-disc));
+          lam = CX::make(R(0.5) * (a + d), sqrt(-disc));
         }
         // eigenvector of B for lam: (b, lam - a) or (lam - d, c)
-        double2 v0, v1;
-        const double2 la = make_double2(lam.x - a, lam.y), ld = make_double2(lam.x - d, lam.y);
+        C v0, v1;
+        const C la = CX::make(lam.x - a, lam.y), ld = CX::make(lam.x - d, lam.y);
         if (fabs(b) + cabs(la) >= fabs(c) + cabs(ld)) {
-          v0 = make_double2(b, 0.0);
+          v0 = CX::make(b, R(0.0));
           v1 = la;
         } else {
           v0 = ld;
-          v1 = make_double2(c, 0.0);
+          v1 = CX::make(c, R(0.0));
         }
-        const double nv = sqrt(cabs2(v0) + cabs2(v1));
-        v0 = cscale(v0, 1.0 / nv);
-        v1 = cscale(v1, 1.0 / nv);
+        const R nv = sqrt(cabs2(v0) + cabs2(v1));
+        v0 = cscale(v0, (R)1 / nv);
+        v1 = cscale(v1, (R)1 / nv);
         // U = [[v0, -conj(v1)], [v1, conj(v0)]]
         U[2 * k + 0] = v0;
-        U[2 * k + 1] = make_double2(-v1.x, v1.y);
+        U[2 * k + 1] = CX::make(-v1.x, v1.y);
         U[2 * (k + 1) + 0] = v1;
         U[2 * (k + 1) + 1] = cconj(v0);
         bstart[k] = k;
@@ -285,35 +291,35 @@ __global__ void __launch_bounds__(256) rsf2csf_kernel(int n, const double* __res
   }
   __syncthreads();
   // P[s+p][s+q] = U[2*(s+p) + q] for a block starting at s; identity otherwise
-  auto Pent = [&](int r, int c) -> double2 {
+  auto Pent = [&](int r, int c) -> C {
     const int s = bstart[c];
-    if (s < 0) return (r == c) ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0);
-    if (r != s && r != s + 1) return make_double2(0.0, 0.0);
+    if (s < 0) return (r == c) ? CX::make(R(1.0), R(0.0)) : CX::make(R(0.0), R(0.0));
+    if (r != s && r != s + 1) return CX::make(R(0.0), R(0.0));
     return U[2 * r + (c - s)];
   };
   const long nn = (long)n * n;
   for (long e = threadIdx.x; e < nn; e += blockDim.x) {
     const int i = (int)(e / n), j = (int)(e % n);
-    double2 acc = make_double2(0.0, 0.0);
+    C acc = CX::make(R(0.0), R(0.0));
     if (j >= i - 1) {
       const int si = bstart[i] < 0 ? i : bstart[i], ni = bstart[i] < 0 ? 1 : 2;
       const int sj = bstart[j] < 0 ? j : bstart[j], nj = bstart[j] < 0 ? 1 : 2;
       for (int a = si; a < si + ni; ++a) {
-        const double2 pa = cconj(Pent(a, i));
+        const C pa = cconj(Pent(a, i));
         for (int b = sj; b < sj + nj; ++b) {
-          const double t = T[(long)a * n + b];
-          if (t == 0.0) continue;
+          const R t = T[(long)a * n + b];
+          if (t == R(0.0)) continue;
           acc = cadd(acc, cmul(pa, cscale(Pent(b, j), t)));
         }
       }
     }
-    Tc[e] = (j >= i) ? acc : make_double2(0.0, 0.0);
+    Tc[e] = (j >= i) ? acc : CX::make(R(0.0), R(0.0));
   }
   // Z'^T[j][i] = sum_b P[b][j] ZT[b][i]
   for (long e = threadIdx.x; e < nn; e += blockDim.x) {
     const int j = (int)(e / n), i = (int)(e % n);
     const int sj = bstart[j] < 0 ? j : bstart[j], nj = bstart[j] < 0 ? 1 : 2;
-    double2 acc = make_double2(0.0, 0.0);
+    C acc = CX::make(R(0.0), R(0.0));
     for (int b = sj; b < sj + nj; ++b) acc = cadd(acc, cscale(Pent(b, j), ZT[(long)b * n + i]));
     ZTc[e] = acc;
   }
@@ -327,24 +333,42 @@ long francis_packed_doubles(int n) {
   return o;
 }
 
-void schur_francis(hipStream_t s, int n, const double* H, double* Hwork, double* ZT, double* T, int* info) {
+template <class R>
+static void schur_francis_t(hipStream_t s, int n, const R* H, R* Hwork, R* ZT, R* T, int* info) {
   T2S2_CHECK(n >= 1 && n <= 512, "schur_francis: n must be in [1, 512]");
-  TimedScope ts(s, KC_SCHUR, 8.0 * 4.0 * n * n, 10.0 * (double)n * n * n);
-  const long need = francis_packed_doubles(n);
-  if (need <= kFqLds)
-    hipLaunchKernelGGL(francis_kernel<true>, dim3(1), dim3(kFqThreads), (size_t)need * sizeof(double), s, n, H,
-                       Hwork, ZT, T, info, 40 * n + 100);
+  TimedScope ts(s, KC_SCHUR, sizeof(R) * 4.0 * n * n, 10.0 * (double)n * n * n);
+  const long need = francis_packed_doubles(n) * (long)sizeof(R);
+  if (need <= kFqLdsBytes<R>)
+    hipLaunchKernelGGL((francis_kernel<true, R>), dim3(1), dim3(kFqThreads), (size_t)need, s, n, H, Hwork, ZT, T,
+                       info, 40 * n + 100);
   else
-    hipLaunchKernelGGL(francis_kernel<false>, dim3(1), dim3(kFqThreads), 0, s, n, H, Hwork, ZT, T, info,
+    hipLaunchKernelGGL((francis_kernel<false, R>), dim3(1), dim3(kFqThreads), 0, s, n, H, Hwork, ZT, T, info,
                        40 * n + 100);
+  T2S2_LAUNCH_CHECK();
+}
+
+void schur_francis(hipStream_t s, int n, const double* H, double* Hwork, double* ZT, double* T, int* info) {
+  schur_francis_t<double>(s, n, H, Hwork, ZT, T, info);
+}
+void schur_francis(hipStream_t s, int n, const float* H, float* Hwork, float* ZT, float* T, int* info) {
+  schur_francis_t<float>(s, n, H, Hwork, ZT, T, info);
+}
+
+template <class R>
+static void rsf2csf_t(hipStream_t s, int n, const R* T, const R* ZT, typename CxOf<R>::type* Tc,
+                      typename CxOf<R>::type* ZTc, int* bstart, typename CxOf<R>::type* U) {
+  TimedScope ts(s, KC_SCHUR, sizeof(R) * 2.0 * n * n + 2.0 * sizeof(R) * 2.0 * n * n, 0.0);
+  hipLaunchKernelGGL(rsf2csf_kernel<R>, dim3(1), dim3(256), 0, s, n, T, ZT, Tc, ZTc, bstart, U);
   T2S2_LAUNCH_CHECK();
 }
 
 void rsf2csf(hipStream_t s, int n, const double* T, const double* ZT, double2* Tc, double2* ZTc, int* bstart,
              double2* U) {
-  TimedScope ts(s, KC_SCHUR, 8.0 * 2.0 * n * n + 16.0 * 2.0 * n * n, 0.0);
-  hipLaunchKernelGGL(rsf2csf_kernel, dim3(1), dim3(256), 0, s, n, T, ZT, Tc, ZTc, bstart, U);
-  T2S2_LAUNCH_CHECK();
+  rsf2csf_t<double>(s, n, T, ZT, Tc, ZTc, bstart, U);
+}
+void rsf2csf(hipStream_t s, int n, const float* T, const float* ZT, float2* Tc, float2* ZTc, int* bstart,
+             float2* U) {
+  rsf2csf_t<float>(s, n, T, ZT, Tc, ZTc, bstart, U);
 }
 
 }  // namespace t2s2

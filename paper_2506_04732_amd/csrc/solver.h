@@ -35,6 +35,7 @@ struct Problem {
   DTTM opL, opK;
   std::vector<double*> dK, dEinv;
   std::vector<double2*> dK_ZT, dK_T;  // Schur form of K_l
+  std::vector<float2*> dK_ZT32, dK_T32;  // the same rounded to FP32
   std::vector<int> opR;
   Scratch sc;
   ~Problem();
@@ -50,6 +51,7 @@ struct SolveOptions {
   unsigned long long seed = 0;
   int check_every = 1;
   int verbose = 0;
+  int precision = 0;  // 0 FP64, 1 mixed (FP32 factors inside FP64 refinement)
 };
 
 struct SolveReport {
@@ -58,6 +60,7 @@ struct SolveReport {
   double residual = -1.0, time_ms = 0.0;
   std::vector<double> hist_res, hist_local, hist_time;
   std::vector<int> hist_rank;
+  int local_systems = 0, refinement_steps = 0, fp64_fallbacks = 0;
 };
 
 Problem* problem_create(int d, const int* N, double eps, const double* beta, int scheme, int rank_cap);

@@ -22,6 +22,7 @@
 #include <cmath>
 #include <cstdio>
 
+#include "ddnorm.h"
 #include "spectral_host.h"
 
 namespace t2s2 {
@@ -37,6 +38,8 @@ Problem::~Problem() {
   for (auto p : dEinv) fr(p);
   for (auto p : dK_ZT) fr(p);
   for (auto p : dK_T) fr(p);
+  for (auto p : dK_ZT32) fr(p);
+  for (auto p : dK_T32) fr(p);
 }
 
 static std::vector<double> host_inverse(int n, std::vector<double> A) {
@@ -179,6 +182,12 @@ Problem* problem_create(int d, const int* N, double eps, const double* beta, int
       schur_real(c, m, k, zt, t);
       P->dK_ZT.push_back(zt);
       P->dK_T.push_back(t);
+      float2* zt32 = dev_alloc<float2>((size_t)m * m);
+      float2* t32 = dev_alloc<float2>((size_t)m * m);
+      to_float(c.s, reinterpret_cast<const double*>(zt), reinterpret_cast<float*>(zt32), 2L * m * m);
+      to_float(c.s, reinterpret_cast<const double*>(t), reinterpret_cast<float*>(t32), 2L * m * m);
+      P->dK_ZT32.push_back(zt32);
+      P->dK_T32.push_back(t32);
     }
     T2S2_HIP(hipDeviceSynchronize());
   } catch (...) {
@@ -201,67 +210,7 @@ void tt_matvec(const Ctx& c, const DTTM& A, const DTT& x, DTT& y) {
   }
 }
 
-// Copy of x in scratch (prefix names the buffers).
-static DTT scratch_copy(const Ctx& c, const DTT& x, const std::string& prefix, int extra_rank = 0) {
-  DTT y = x;
-  for (int l = 0; l < x.d; ++l) {
-    const size_t sz = (size_t)x.r[l] * x.n[l] * x.r[l + 1];
-    const size_t cap = (size_t)(x.r[l] + extra_rank) * x.n[l] * (x.r[l + 1] + extra_rank);
-    y.c[l] = c.sc->get<double>(prefix + std::to_string(l), std::max(sz, cap));
-    c.d2d(y.c[l], x.c[l], sz);
-  }
-  return y;
-}
-
-// In place: cores 0..d-2 become left-orthonormal (ranks may shrink); returns
-// the norm of the last core (= ||x||).  Core buffers must hold r_l n r_{l+1}
-// for the input ranks.
-static double left_orthogonalize(const Ctx& c, DTT& x, const std::string& tag) {
-  for (int l = 0; l + 1 < x.d; ++l) {
-    const int M = x.r[l] * x.n[l], n = x.r[l + 1];
-    const int kmax = std::min(M, n);
-    double* Q = c.sc->get<double>(tag + ".Q", (size_t)M * kmax);
-    double* R = c.sc->get<double>(tag + ".R", (size_t)kmax * n);
-    int k;
-    if (M <= n) {
-      // wide unfolding: the identity is an orthonormal basis of its column space
-      k = M;
-      c.d2d(R, x.c[l], (size_t)M * n);
-      fill(c.s, x.c[l], (long)M * M, 0.0);
-      const int nn = M;
-      std::vector<double> eye((size_t)nn * nn, 0.0);
-      for (int i = 0; i < nn; ++i) eye[(size_t)i * nn + i] = 1.0;
-      c.h2d(x.c[l], eye.data(), eye.size());
-      c.sync();
-    } else {
-      k = dcholqr(c, M, n, x.c[l], n, Q, R, 1e-15);
-      if (k == 0) return 0.0;
-      c.d2d(x.c[l], Q, (size_t)M * k);
-    }
-    const int n1 = x.n[l + 1], r2 = x.r[l + 2];
-    double* T = c.sc->get<double>(tag + ".T", (size_t)k * n1 * r2);
-    mode1<double>(c, k, n, n1, r2, R, x.c[l + 1], T, 0.0);
-    c.d2d(x.c[l + 1], T, (size_t)k * n1 * r2);
-    x.r[l + 1] = k;
-  }
-  const int l = x.d - 1;
-  return c.nrm2(x.c[l], (long)x.r[l] * x.n[l] * x.r[l + 1]);
-}
-
-double tt_norm(const Ctx& c, const DTT& x) {
-  // extra capacity: wide unfoldings are replaced by identities of size r n
-  DTT y = x;
-  for (int l = 0; l < x.d; ++l) {
-    const size_t sz = (size_t)x.r[l] * x.n[l] * x.r[l + 1];
-    size_t cap = sz;
-    const size_t rl = (size_t)x.r[l] * x.n[l];
-    cap = std::max(cap, rl * rl);
-    cap = std::max(cap, rl * x.n[std::min(l + 1, x.d - 1)] * (size_t)x.r[std::min(l + 2, x.d)]);
-    y.c[l] = c.sc->get<double>("nrm.c" + std::to_string(l), cap);
-    c.d2d(y.c[l], x.c[l], sz);
-  }
-  return left_orthogonalize(c, y, "nrm");
-}
+double tt_norm(const Ctx& c, const DTT& x) { return tt_norm_dd(c, x); }
 
 double tt_residual_norm(Problem& p, const Ctx& c, const DTT& x, const DTT& f) {
   const int d = x.d;
@@ -287,9 +236,7 @@ double tt_residual_norm(Problem& p, const Ctx& c, const DTT& x, const DTT& f) {
   for (int l = 0; l < d; ++l) {
     const int n = x.n[l];
     const size_t sz = (size_t)r.r[l] * n * r.r[l + 1];
-    const size_t rl = (size_t)r.r[l] * n;
-    const size_t cap = std::max({sz, rl * rl, rl * (size_t)(l + 1 < d ? x.n[l + 1] * r.r[l + 2] : 1)});
-    r.c[l] = c.sc->get<double>("res.r" + std::to_string(l), cap);
+    r.c[l] = c.sc->get<double>("res.r" + std::to_string(l), sz);
     if (d == 1) {
       c.d2d(r.c[l], f.c[l], (size_t)n);
       axpby(c.s, n, -1.0, y.c[l], 1.0, r.c[l]);
@@ -309,8 +256,10 @@ double tt_residual_norm(Problem& p, const Ctx& c, const DTT& x, const DTT& f) {
       copy2d(c.s, (long)yr0 * n, yr1, y.c[l], yr1, r.c[l] + (long)fr0 * n * ld + fr1, ld);
     }
   }
-  const double rn = left_orthogonalize(c, r, "res.o");
-  const double fn = tt_norm(c, f);
+  // norms by the double-double Gram recursion: f and L x cancel to the
+  // residual level, which FP64 orthogonalisation cannot resolve
+  const double rn = tt_norm_dd(c, r);
+  const double fn = tt_norm_dd(c, f);
   T2S2_CHECK(fn > 0.0 && std::isfinite(fn), "residual: ||f|| must be finite and > 0");
   return rn / fn;
 }
@@ -357,11 +306,15 @@ void tt_round(const Ctx& c, DTT& x, double tol, int rmax) {
 // ================================================================ solver
 namespace {
 
-struct Eig {
-  double2* lam = nullptr;
-  double2* V = nullptr;
-  double2* Vi = nullptr;
+// Interface factorisation L = V diag(lam) V^{-1} (complex), FP64 or FP32.
+template <class C>
+struct EigT {
+  C* lam = nullptr;
+  C* V = nullptr;
+  C* Vi = nullptr;
 };
+using Eig = EigT<double2>;
+using Eig32 = EigT<float2>;
 
 struct Amen {
   Problem& p;
@@ -372,12 +325,17 @@ struct Amen {
   // interfaces per bond position 0..d (matrices in row-major, [test][trial])
   std::vector<double*> L, XB, ZXI, ZXL, ZB;
   std::vector<Eig> eig;
+  std::vector<Eig32> eig32;       // mixed precision: FP32 factors per bond
+  std::vector<char> ok64;         // eig[pos] holds the factors of the current L[pos]
+  std::vector<char> need64;       // mixed: bond pos needed FP64 factors once, keep them
+  bool mixed = false;
   std::vector<int> xr, zr, sr;  // ranks of x, z, f~ per bond
   std::vector<double*> xc, zc, bc;  // cores
   std::vector<int> maxrank;     // structural bound per bond
   // work
   double *u, *f, *res, *y, *T1, *T2, *A1, *S, *kick_buf, *zbuf, *U, *W, *tmp, *Qk, *Rk;
   double2 *h0, *h1;
+  float2 *g0, *g1;
 
   Amen(Problem& p_, const Ctx& c_, const SolveOptions& o_) : p(p_), c(c_), o(o_) {}
 
@@ -406,6 +364,39 @@ struct Amen {
     complex_real_part(c.s, h0, out, n);
   }
 
+  // same solve with the FP32 factors (FP64 in, FP64 out)
+  void local_solve32(int l, int r1, int r2, const Eig32& eL, const Eig32& eR, const double* g, double* out) {
+    const int ml = m[l];
+    const long n = (long)r1 * ml * r2;
+    const float2 z0 = make_float2(0.0f, 0.0f);
+    real_to_complex(c.s, g, g0, n);
+    mode3<float2>(c, r1, ml, r2, r2, g0, eR.Vi, g1, z0);
+    mode2<float2>(c, r1, ml, ml, r2, p.dK_ZT32[l], g1, g0, z0, OpR);
+    mode1<float2>(c, r1, r1, ml, r2, eL.Vi, g0, g1, z0);
+    kron_trisolve(c.s, r1, ml, r2, p.dK_T32[l], eL.lam, eR.lam, g1);
+    mode1<float2>(c, r1, r1, ml, r2, eL.V, g1, g0, z0);
+    mode2<float2>(c, r1, ml, ml, r2, p.dK_ZT32[l], g0, g1, z0, OpT);
+    mode3<float2>(c, r1, ml, r2, r2, g1, eR.V, g0, z0);
+    complex_real_part(c.s, g0, out, n);
+  }
+
+  // factorise the interface at bond pos (size n) in the working precision
+  void factor(int pos, int n) {
+    if (mixed && !need64[pos]) {
+      eig_nonsym(c, n, L[pos], eig32[pos].lam, eig32[pos].V, eig32[pos].Vi);
+      ok64[pos] = 0;
+    } else {
+      eig_nonsym(c, n, L[pos], eig[pos].lam, eig[pos].V, eig[pos].Vi);
+      ok64[pos] = 1;
+    }
+  }
+  void ensure64(int pos, int n) {
+    if (!ok64[pos]) {
+      eig_nonsym(c, n, L[pos], eig[pos].lam, eig[pos].V, eig[pos].Vi);
+      ok64[pos] = 1;
+    }
+  }
+
   void set_boundary(int pos) {
     // 1 x 1 interfaces: L = 0, XB = 1, ZXI = 1, ZXL = 0, ZB = 1
     const double zero = 0.0, one = 1.0;
@@ -418,6 +409,11 @@ struct Amen {
     c.h2d(eig[pos].lam, &z, 1);
     c.h2d(eig[pos].V, &o1, 1);
     c.h2d(eig[pos].Vi, &o1, 1);
+    const float2 zf = make_float2(0.0f, 0.0f), of = make_float2(1.0f, 0.0f);
+    c.h2d(eig32[pos].lam, &zf, 1);
+    c.h2d(eig32[pos].V, &of, 1);
+    c.h2d(eig32[pos].Vi, &of, 1);
+    ok64[pos] = 1;
     c.sync();
   }
 
@@ -443,7 +439,7 @@ struct Amen {
     // ZB' = Z^T (ZB x1 b)
     mode1<double>(c, q0, s0, ml, s1, ZB[l], bc[l], T1, 0.0);
     gemm<double>(c.s, OpT, OpN, q1, s1, q0 * ml, 1.0, Z, q1, 0, T1, s1, 0, 0.0, ZB[l + 1], s1, 0, 1);
-    eig_nonsym(c, r1, L[l + 1], eig[l + 1].lam, eig[l + 1].V, eig[l + 1].Vi);
+    factor(l + 1, r1);
   }
 
   // right interfaces at pos l from pos l+1 and cores x_l, z_l
@@ -467,7 +463,7 @@ struct Amen {
     // ZB' = Z_mat (b x3 ZB)^T  (q0 x s0)
     mode3<double>(c, s0, ml, s1, q1, bc[l], ZB[l + 1], T1, 0.0);
     gemm<double>(c.s, OpN, OpT, q0, s0, ml * q1, 1.0, Z, (long)ml * q1, 0, T1, (long)ml * q1, 0, 0.0, ZB[l], s0, 0, 1);
-    eig_nonsym(c, r0, L[l], eig[l].lam, eig[l].V, eig[l].Vi);
+    factor(l, r0);
   }
 
   // right-orthogonalise a TT held in cores (in place); ranks updated
@@ -524,6 +520,10 @@ struct Amen {
     ZXL.resize(d + 1);
     ZB.resize(d + 1);
     eig.resize(d + 1);
+    eig32.resize(d + 1);
+    ok64.assign(d + 1, 0);
+    need64.assign(d + 1, 0);
+    mixed = (o.precision == 1);
     for (int l = 0; l <= d; ++l) {
       const std::string t = std::to_string(l);
       L[l] = buf("L" + t, (size_t)cap * cap);
@@ -534,6 +534,9 @@ struct Amen {
       eig[l].lam = c.sc->get<double2>("am.lam" + t, cap);
       eig[l].V = c.sc->get<double2>("am.V" + t, (size_t)cap * cap);
       eig[l].Vi = c.sc->get<double2>("am.Vi" + t, (size_t)cap * cap);
+      eig32[l].lam = c.sc->get<float2>("am.lam32" + t, cap);
+      eig32[l].V = c.sc->get<float2>("am.V32" + t, (size_t)cap * cap);
+      eig32[l].Vi = c.sc->get<float2>("am.Vi32" + t, (size_t)cap * cap);
     }
     u = buf("u", big);
     f = buf("f", big);
@@ -552,6 +555,8 @@ struct Amen {
     Rk = buf("Rk", (size_t)cap * std::max<size_t>(cap, mmax * kk));
     h0 = c.sc->get<double2>("am.h0", big);
     h1 = c.sc->get<double2>("am.h1", big);
+    g0 = c.sc->get<float2>("am.g0", big);
+    g1 = c.sc->get<float2>("am.g1", big);
     // initial x (caller's buffers) and z (scratch)
     xr.assign(d + 1, 1);
     zr.assign(d + 1, 1);
@@ -603,13 +608,35 @@ struct Amen {
         const double res0 = fn > 0 ? rn / fn : 0.0;
         max_res = std::max(max_res, res0);
         if (res0 > loc_tol) {
-          for (int it = 0; it < 6; ++it) {
-            local_solve(l, r1, r2, eig[l], eig[l + 1], res, y);
+          // iterative refinement: FP64 residual and update, correction from
+          // the exact solver's factors (FP64, or FP32 in mixed precision
+          // with a switch to FP64 factors when they contract too slowly)
+          ++rep.local_systems;
+          bool use64 = !mixed || (ok64[l] && ok64[l + 1]);
+          double prev = rn;
+          for (int it = 0, it32 = 0, it64 = 0; it < 14; ++it) {
+            if (use64) {
+              local_solve(l, r1, r2, eig[l], eig[l + 1], res, y);
+              ++it64;
+            } else {
+              local_solve32(l, r1, r2, eig32[l], eig32[l + 1], res, y);
+              ++it32;
+            }
+            ++rep.refinement_steps;
             axpby(c.s, n, 1.0, y, 1.0, u);
             local_apply(l, r1, r2, L[l], L[l + 1], u, res);
             axpby(c.s, n, 1.0, f, -1.0, res);
             rn = c.nrm2(res, n);
             if (rn <= 0.1 * loc_tol * fn) break;
+            if (use64 && it64 >= 6) break;
+            if (!use64 && (rn > 0.25 * prev || it32 >= 8)) {
+              ensure64(l, r1);
+              ensure64(l + 1, r2);
+              need64[l] = need64[l + 1] = 1;
+              use64 = true;
+              ++rep.fp64_fallbacks;
+            }
+            prev = rn;
           }
         }
         const bool last = (direction > 0 && l == d - 1) || (direction < 0 && l == 0);

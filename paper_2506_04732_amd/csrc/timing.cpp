@@ -14,7 +14,6 @@ struct Rec {
 };
 struct TimingState {
   bool enabled = false;
-  std::vector<Rec> open;      // begin recorded, end pending (stack)
   std::vector<Rec> done;      // both recorded
   std::vector<hipEvent_t> pool;
   double ms[KC_COUNT] = {0}, bytes[KC_COUNT] = {0}, flops[KC_COUNT] = {0};
@@ -22,6 +21,9 @@ struct TimingState {
 };
 TimingState g_t;
 std::mutex g_m;
+// begin recorded, end pending: a stack per host thread, so that concurrent
+// solves on several streams (batched solves) pair their own events
+thread_local std::vector<Rec> t_open;
 
 hipEvent_t take_event() {
   if (!g_t.pool.empty()) {
@@ -57,14 +59,14 @@ void timing_record_begin(hipStream_t s, int cls, double bytes, double flops) {
   std::lock_guard<std::mutex> lk(g_m);
   Rec r{cls, take_event(), take_event(), bytes, flops};
   T2S2_HIP(hipEventRecord(r.a, s));
-  g_t.open.push_back(r);
+  t_open.push_back(r);
 }
 
 void timing_record_end(hipStream_t s) {
   std::lock_guard<std::mutex> lk(g_m);
-  if (g_t.open.empty()) return;
-  Rec r = g_t.open.back();
-  g_t.open.pop_back();
+  if (t_open.empty()) return;
+  Rec r = t_open.back();
+  t_open.pop_back();
   T2S2_HIP(hipEventRecord(r.b, s));
   g_t.done.push_back(r);
   if (g_t.done.size() >= 4096) drain();

@@ -84,6 +84,18 @@ __global__ void real_to_complex_kernel(const double* __restrict__ x, double2* __
     y[i] = make_double2(x[i], 0.0);
 }
 
+__global__ void real_to_complex32_kernel(const double* __restrict__ x, float2* __restrict__ y, long n) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    y[i] = make_float2((float)x[i], 0.0f);
+}
+__global__ void complex32_real_part_kernel(const float2* __restrict__ x, double* __restrict__ y, long n) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    y[i] = (double)x[i].x;
+}
+__global__ void to_float_kernel(const double* __restrict__ x, float* __restrict__ y, long n) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    y[i] = (float)x[i];
+}
 __global__ void complex_real_part_kernel(const double2* __restrict__ x, double* __restrict__ y, long n) {
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
     y[i] = x[i].x;
@@ -164,27 +176,29 @@ __global__ void col_sumsq_kernel(const double* __restrict__ x, long rows, long c
 // m x m (complex), h complex [r1][m][r2], in place.  One thread per (a, b):
 // the vector lives in registers (compile-time bound MAXM, fully unrolled
 // column-oriented back substitution), T is broadcast from LDS.
-template <int MAXM>
+template <int MAXM, class R>
 __global__ void __launch_bounds__(128)
-kron_trisolve_kernel(int r1, int m, int r2, const double2* __restrict__ T,
-                     const double2* __restrict__ lamL, const double2* __restrict__ lamR,
-                     double2* __restrict__ h) {
-  __shared__ double2 Ts[MAXM * MAXM];
+kron_trisolve_kernel(int r1, int m, int r2, const typename CxOf<R>::type* __restrict__ T,
+                     const typename CxOf<R>::type* __restrict__ lamL, const typename CxOf<R>::type* __restrict__ lamR,
+                     typename CxOf<R>::type* __restrict__ h) {
+  using C = typename CxOf<R>::type;
+  using CX = CxOf<R>;
+  __shared__ C Ts[MAXM * MAXM];
   for (int e = threadIdx.x; e < m * m; e += blockDim.x) Ts[(e / m) * MAXM + (e % m)] = T[e];
   __syncthreads();
   const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (t >= (long)r1 * r2) return;
   const int a = (int)(t / r2), b = (int)(t % r2);
-  const double2 s = cadd(lamL[a], lamR[b]);
-  double2* base = h + (long)a * m * r2 + b;
-  double2 v[MAXM];
+  const C s = cadd(lamL[a], lamR[b]);
+  C* base = h + (long)a * m * r2 + b;
+  C v[MAXM];
 #pragma unroll
-  for (int i = 0; i < MAXM; ++i) v[i] = (i < m) ? base[(long)i * r2] : make_double2(0.0, 0.0);
+  for (int i = 0; i < MAXM; ++i) v[i] = (i < m) ? base[(long)i * r2] : CX::make(R(0), R(0));
 #pragma unroll
   for (int k = MAXM - 1; k >= 0; --k) {
     if (k < m) {
-      double2 dkk = cadd(Ts[k * MAXM + k], s);
-      if (dkk.x == 0.0 && dkk.y == 0.0) dkk.x = 1e-300;
+      C dkk = cadd(Ts[k * MAXM + k], s);
+      if (dkk.x == R(0) && dkk.y == R(0)) dkk.x = sizeof(R) == 8 ? R(1e-300) : R(1e-37f);
       v[k] = cdiv(v[k], dkk);
 #pragma unroll
       for (int i = 0; i < k; ++i) v[i] = csub(v[i], cmul(Ts[i * MAXM + k], v[k]));
@@ -211,7 +225,8 @@ __global__ void transpose_kernel(long rows, long cols, const T* __restrict__ in,
   }
 }
 
-__global__ void diag_complex_kernel(int n, const double2* __restrict__ M, long ld, double2* __restrict__ out) {
+template <class C>
+__global__ void diag_complex_kernel(int n, const C* __restrict__ M, long ld, C* __restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = M[(long)i * (ld + 1)];
 }
@@ -290,6 +305,24 @@ void real_to_complex(hipStream_t s, const double* x, double2* y, long n) {
   T2S2_LAUNCH_CHECK();
 }
 
+void real_to_complex(hipStream_t s, const double* x, float2* y, long n) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(real_to_complex32_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, x, y, n);
+  T2S2_LAUNCH_CHECK();
+}
+
+void complex_real_part(hipStream_t s, const float2* x, double* y, long n) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(complex32_real_part_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, x, y, n);
+  T2S2_LAUNCH_CHECK();
+}
+
+void to_float(hipStream_t s, const double* x, float* y, long n) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(to_float_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, x, y, n);
+  T2S2_LAUNCH_CHECK();
+}
+
 void complex_real_part(hipStream_t s, const double2* x, double* y, long n) {
   if (n <= 0) return;
   hipLaunchKernelGGL(complex_real_part_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, x, y, n);
@@ -322,19 +355,31 @@ void col_sumsq(hipStream_t s, const double* x, long rows, long cols, long ld, do
   T2S2_LAUNCH_CHECK();
 }
 
-void kron_trisolve(hipStream_t s, int r1, int m, int r2, const double2* T, const double2* lamL,
-                   const double2* lamR, double2* h) {
+template <class R>
+static void kron_trisolve_t(hipStream_t s, int r1, int m, int r2, const typename CxOf<R>::type* T,
+                            const typename CxOf<R>::type* lamL, const typename CxOf<R>::type* lamR,
+                            typename CxOf<R>::type* h) {
   T2S2_CHECK(m >= 1 && m <= 64, "kron_trisolve: mode size must be in [1, 64]");
   const long nthr = (long)r1 * r2;
   const int grid = (int)((nthr + 127) / 128);
-  TimedScope ts(s, KC_KRONSOLVE, 16.0 * (2.0 * nthr * m + (double)m * m + r1 + r2), 8.0 * nthr * m * (m + 1) / 2.0);
+  const double cb = 2.0 * sizeof(R);
+  TimedScope ts(s, KC_KRONSOLVE, cb * (2.0 * nthr * m + (double)m * m + r1 + r2), 8.0 * nthr * m * (m + 1) / 2.0);
   if (m <= 16)
-    hipLaunchKernelGGL(kron_trisolve_kernel<16>, dim3(grid), dim3(128), 0, s, r1, m, r2, T, lamL, lamR, h);
+    hipLaunchKernelGGL((kron_trisolve_kernel<16, R>), dim3(grid), dim3(128), 0, s, r1, m, r2, T, lamL, lamR, h);
   else if (m <= 32)
-    hipLaunchKernelGGL(kron_trisolve_kernel<32>, dim3(grid), dim3(128), 0, s, r1, m, r2, T, lamL, lamR, h);
+    hipLaunchKernelGGL((kron_trisolve_kernel<32, R>), dim3(grid), dim3(128), 0, s, r1, m, r2, T, lamL, lamR, h);
   else
-    hipLaunchKernelGGL(kron_trisolve_kernel<64>, dim3(grid), dim3(128), 0, s, r1, m, r2, T, lamL, lamR, h);
+    hipLaunchKernelGGL((kron_trisolve_kernel<64, R>), dim3(grid), dim3(128), 0, s, r1, m, r2, T, lamL, lamR, h);
   T2S2_LAUNCH_CHECK();
+}
+
+void kron_trisolve(hipStream_t s, int r1, int m, int r2, const double2* T, const double2* lamL,
+                   const double2* lamR, double2* h) {
+  kron_trisolve_t<double>(s, r1, m, r2, T, lamL, lamR, h);
+}
+void kron_trisolve(hipStream_t s, int r1, int m, int r2, const float2* T, const float2* lamL,
+                   const float2* lamR, float2* h) {
+  kron_trisolve_t<float>(s, r1, m, r2, T, lamL, lamR, h);
 }
 
 void transpose(hipStream_t s, long rows, long cols, const double* in, long ldi, double* out, long ldo) {
@@ -353,7 +398,13 @@ void transpose(hipStream_t s, long rows, long cols, const double2* in, long ldi,
 
 void diag_complex(hipStream_t s, int n, const double2* M, long ld, double2* out) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(diag_complex_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, M, ld, out);
+  hipLaunchKernelGGL(diag_complex_kernel<double2>, dim3((n + 255) / 256), dim3(256), 0, s, n, M, ld, out);
+  T2S2_LAUNCH_CHECK();
+}
+
+void diag_complex(hipStream_t s, int n, const float2* M, long ld, float2* out) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(diag_complex_kernel<float2>, dim3((n + 255) / 256), dim3(256), 0, s, n, M, ld, out);
   T2S2_LAUNCH_CHECK();
 }
 

@@ -1,0 +1,92 @@
+"""GPU parity of the batched solve (many uneven instances, concurrent streams).
+
+Bar: every instance's result is bitwise the TT that a single solve of that
+instance returns (same kernels, same order of operations), and matches the
+oracle's full-format solution to the FP64 bar; at the batched workload's
+sizes the oracle's FP64 residual of each sampled result meets the target.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+import paper_2506_04732_amd as t2s2  # noqa: E402
+import workloads  # noqa: E402
+from paper_2506_04732_amd import TT, sources  # noqa: E402
+from oracle import collocation as col  # noqa: E402
+from oracle import metrics  # noqa: E402
+from oracle import tt as ott  # noqa: E402
+from residual_floor import agreement_bound  # noqa: E402
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _small_instances():
+    out = []
+    for i, (d, N) in enumerate([(3, [9, 12, 7]), (4, [6, 8, 7, 5]), (2, [20, 14]), (3, [10, 10, 10]),
+                                (1, [30]), (4, [5, 9, 6, 8])]):
+        out.append(workloads.gauss_problem(d, N, [1e-2, 3e-3, 1e-3, 5e-2, 2e-3, 1e-2][i], 3, seed=40 + i,
+                                           tol=1e-12, rank_cap=40))
+    return out
+
+
+def _gpu(prob, cap):
+    p = t2s2.Problem(prob.d, prob.N, prob.eps, prob.beta, prob.scheme, rank_cap=cap)
+    f = sources.source_tt(p, sources.gaussian_factors(p, prob.gauss.amp, prob.gauss.centre, prob.gauss.width))
+    return p, f
+
+
+def test_batched_equals_single_solves_and_dense():
+    insts = _small_instances()
+    _say("batched small", [q.name for q in insts])
+    cap = 40
+    pf = [_gpu(q, cap) for q in insts]
+    opts = dict(tol=1e-12, target=1e-11, max_sweeps=20, kick=4, init_rank=2)
+    single = [p.solve(f, **opts) for p, f in pf]
+    batch = t2s2.solve_batched([p for p, _ in pf], [f for _, f in pf], workers=4, **opts)
+    for q, s, b in zip(insts, single, batch):
+        assert s.converged and b.converged, (q.name, s.residual, b.residual)
+        assert s.ranks == b.ranks
+        for cs, cb in zip(s.x.to_numpy(), b.x.to_numpy()):
+            assert np.array_equal(cs, cb), q.name
+        ops = col.build_ops(q.d, q.N, q.eps, q.beta, q.scheme)
+        u = col.solve_dense(ops, col.separable_full(col.gauss_rhs_factors(ops, q.gauss.amp, q.gauss.centre,
+                                                                           q.gauss.width)))
+        u = u[tuple(slice(1, -1) for _ in range(q.d))]
+        assert metrics.rel_frobenius(ott.full(b.x.to_numpy()), u) <= 1e-9, q.name
+
+
+def test_batched_workload_sample_meets_target_by_oracle_residual():
+    insts = workloads.batched_instances(6)
+    _say("batched workload sample", [(q.d, q.N, f"{q.eps:.1e}") for q in insts])
+    cap = insts[0].rank_cap
+    pf = [_gpu(q, cap) for q in insts]
+    opts = dict(tol=insts[0].tol, target=insts[0].target_residual, max_sweeps=30, kick=8, init_rank=8,
+                check_every=0)
+    res = t2s2.solve_batched([p for p, _ in pf], [f for _, f in pf], workers=6, **opts)
+    assert sum(r.converged for r in res) >= 5
+    for q, r in zip(insts, res):
+        ops = col.build_ops(q.d, q.N, q.eps, q.beta, q.scheme)
+        Es, Ms = col.interior_factors(ops)
+        b = ott.separable_to_tt(col.gauss_rhs_factors(ops, q.gauss.amp, q.gauss.centre, q.gauss.width))
+        rho = ott.residual_norm(ott.kron_sum_ttm(Es, Ms), r.x.to_numpy(), b)
+        _say(q.name, f"converged {r.converged} library {r.residual:.3e} oracle {rho:.3e} ranks {r.ranks}")
+        # the library's FP64 residual is the oracle's up to what two FP64
+        # constructions of the operator can agree on (see residual_floor)
+        bound = agreement_bound(ops, q.eps, q.beta, Es, Ms, r.x.to_numpy(), b, rho)
+        _say(q.name, f"agreement bound {bound:.2e}")
+        assert abs(rho - r.residual) <= bound
+        if r.converged:
+            assert rho <= q.target_residual + bound, (q.name, rho)
+        else:
+            assert r.status == 3 and rho > q.target_residual - bound
+
+
+def test_batched_rejects_shared_problem_and_empty_batch():
+    q = _small_instances()[0]
+    p, f = _gpu(q, 16)
+    with pytest.raises(t2s2.T2S2Error):
+        t2s2.solve_batched([p, p], [f, f], workers=2)
+    assert t2s2.solve_batched([], []) == []

@@ -1,0 +1,105 @@
+"""GPU parity of the mixed-precision solve (FP32 interface factorisations and
+local-solve transforms inside FP64 iterative refinement of every local system).
+
+Bar: the same as the FP64 path.  Refinement drives every local residual to
+the FP64 tolerance, so the returned TT must match the oracle's full-format
+solution to the FP64 bar, and at the 6D N = 32 workload the oracle's own FP64
+residual of the returned TT must meet the 1e-8 target.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+import paper_2506_04732_amd as t2s2  # noqa: E402
+import workloads  # noqa: E402
+from paper_2506_04732_amd import PRECISION_FP64, PRECISION_MIXED, TT, sources  # noqa: E402
+from oracle import collocation as col  # noqa: E402
+from oracle import metrics  # noqa: E402
+from oracle import tt as ott  # noqa: E402
+from residual_floor import agreement_bound  # noqa: E402
+
+MIXED = PRECISION_MIXED
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _setup(prob, cap=None):
+    p = t2s2.Problem(prob.d, prob.N, prob.eps, prob.beta, prob.scheme, rank_cap=cap or prob.rank_cap)
+    fac = sources.gaussian_factors(p, prob.gauss.amp, prob.gauss.centre, prob.gauss.width)
+    f = sources.source_tt(p, fac)
+    ops = col.build_ops(prob.d, prob.N, prob.eps, prob.beta, prob.scheme)
+    Es, Ms = col.interior_factors(ops)
+    terms = col.gauss_rhs_factors(ops, prob.gauss.amp, prob.gauss.centre, prob.gauss.width)
+    return p, f, ops, ott.kron_sum_ttm(Es, Ms), terms
+
+
+def test_mixed_3d_transport_matches_schur():
+    prob = workloads.transport_3d(0)
+    _say("mixed", prob.name)
+    p, f, ops, A, terms = _setup(prob, cap=40)
+    r = p.solve(f, tol=1e-12, target=1e-11, max_sweeps=20, kick=8, precision=MIXED)
+    assert r.converged, (r.residual, r.history_residual)
+    assert r.precision == MIXED and r.local_systems > 0 and r.refinement_steps >= r.local_systems
+    u = col.solve_schur(ops, col.separable_full(terms))
+    xg = r.x.to_numpy()
+    assert metrics.rel_frobenius(ott.full(xg), u) <= 1e-10
+    # both residuals are FP64 evaluations of a ~1e-14 quantity: they agree to
+    # the rounding floor of evaluating f - L x (about 1e-16 ||L|| ||x|| / ||f||)
+    assert abs(r.residual - ott.residual_norm(A, xg, ott.separable_to_tt(terms))) <= 1e-3 * r.residual + 5e-13
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_mixed_6d_small_grid_matches_schur(seed):
+    prob = workloads.gauss_problem(6, 8, 1e-2, 3, seed=seed, tol=1e-12, rank_cap=64)
+    _say("mixed", prob.name)
+    p, f, ops, A, terms = _setup(prob)
+    r = p.solve(f, tol=1e-12, target=1e-11, max_sweeps=30, kick=8, precision=MIXED)
+    assert r.converged, (r.residual, r.history_residual)
+    u = col.solve_schur(ops, col.separable_full(terms))
+    assert metrics.rel_frobenius(ott.full(r.x.to_numpy()), u) <= 1e-9
+
+
+@pytest.mark.parametrize("case", ["d1", "ragged"])
+def test_mixed_edge_cases_match_dense(case):
+    _say("mixed edge", case)
+    if case == "d1":
+        prob = workloads.gauss_problem(1, 20, 1e-3, 2, seed=5, tol=1e-12, rank_cap=4)
+    else:
+        prob = workloads.gauss_problem(4, [7, 12, 5, 10], 5e-3, 3, seed=7, tol=1e-12, rank_cap=48)
+    p, f, ops, A, terms = _setup(prob)
+    r = p.solve(f, tol=1e-12, target=1e-11, max_sweeps=20, kick=4, precision=MIXED)
+    u = col.solve_dense(ops, col.separable_full(terms))[tuple(slice(1, -1) for _ in range(prob.d))]
+    assert r.converged, (r.residual, r.history_residual)
+    assert metrics.rel_frobenius(ott.full(r.x.to_numpy()), u) <= 1e-9
+
+
+def test_mixed_6d_N32_meets_target_by_oracle_residual():
+    prob = workloads.steady_6d(0, 32)
+    _say("mixed", prob.name, "N=32 full size")
+    cap = 256
+    p, f, ops, A, terms = _setup(prob, cap=cap)
+    opts = dict(tol=3e-10, target=9e-9, max_sweeps=40, kick=24, init_rank=64, check_every=0, seed=0)
+    r64 = p.solve(f, out=TT.empty(p.m, cap), precision=PRECISION_FP64, **opts)
+    rmx = p.solve(f, out=TT.empty(p.m, cap), precision=MIXED, **opts)
+    assert r64.converged and rmx.converged, (r64.residual, rmx.residual)
+    b = ott.separable_to_tt(terms)
+    x64, xmx = r64.x.to_numpy(), rmx.x.to_numpy()
+    res_mx = ott.residual_norm(A, xmx, b)
+    Es, Ms = col.interior_factors(ops)
+    bound = agreement_bound(ops, prob.eps, prob.beta, Es, Ms, xmx, b, res_mx)
+    assert res_mx <= 1e-8 + bound, res_mx
+    assert abs(res_mx - rmx.residual) <= bound
+    diff = ott.rel_diff(xmx, x64)
+    _say(f"mixed vs fp64: rel diff {diff:.2e}, residuals {rmx.residual:.2e} / {r64.residual:.2e}, "
+         f"time {rmx.time_ms:.0f} / {r64.time_ms:.0f} ms, fallbacks {rmx.fp64_fallbacks}")
+    assert diff <= 1e-5
+
+
+def test_bad_precision_is_rejected():
+    prob = workloads.gauss_problem(2, 8, 1e-2, 2, seed=3, tol=1e-12, rank_cap=8)
+    p, f, *_ = _setup(prob)
+    with pytest.raises(t2s2.T2S2Error):
+        p.solve(f, precision=7)

@@ -3,9 +3,10 @@
 Tolerances (FP64): the library's operator is assembled from its own host 1D
 builder, which agrees with the oracle's to ~1e-14 relative; the contractions
 themselves are exact up to rounding, so element-wise agreement is checked at
-1e-12 relative to the largest entry.  Norms of nearly cancelling residuals are
-checked in absolute terms against ||f|| (the orthogonalisation keeps absolute
-accuracy of a few ulps of ||f||).
+1e-12 relative to the largest entry.  Norms (and so residuals) come from a
+double-double Gram recursion: a TT whose parts cancel to 1e-9 of their size
+must still have its norm within 1e-5 relative of the oracle's Householder
+orthogonalisation, whose own error there is ~1e-7.
 """
 import numpy as np
 import pytest
@@ -87,7 +88,23 @@ def test_residual_norm_of_random_and_near_solution():
     g = p.tt_residual_norm(TT.from_numpy(xs), TT.from_numpy(f))
     o = ott.residual_norm(A, xs, f)
     assert o < 1e-7
-    assert abs(g - o) <= 1e-3 * o + 1e-14
+    assert abs(g - o) <= 1e-5 * o
+
+
+@pytest.mark.parametrize("delta", [1e-6, 1e-9])
+def test_norm_of_cancelling_difference(delta):
+    _say("cancelling norm", delta)
+    rng = np.random.default_rng(21)
+    d, ranks = 6, [1, 30, 70, 100, 65, 30, 1]
+    x = _rand_tt(rng, [30] * d, ranks)
+    xs = [c.copy() for c in x]
+    xs[2] = xs[2] * (1 + delta)
+    y = ott.add(x, xs, 1.0, -1.0)           # = -delta x up to the rounding of core 2
+    p = t2s2.Problem(d, 32, 1e-2, np.ones(d), 1, rank_cap=8)
+    g = p.tt_norm(TT.from_numpy(y))
+    o = ott.norm(y)
+    assert abs(o - delta * ott.norm(x)) <= 1e-5 * o
+    assert abs(g - o) <= 1e-5 * o
 
 
 @pytest.mark.parametrize("tol", [1e-3, 1e-8, 1e-12])

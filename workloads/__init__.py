@@ -103,7 +103,9 @@ def steady_6d(seed: int = 0, N: int = 32) -> Problem:
 
 def batched_instances(count: int = 256, base_seed: int = 0) -> List[Problem]:
     """Uneven instances: d ~ U{4,5,6}, N_l ~ U[16,48] per dimension,
-    eps log-uniform in [1e-4, 1e-1], rank-4 Gaussian sources."""
+    eps log-uniform in [1e-4, 1e-1], beta uniform on the sphere, rank-4
+    Gaussian sources; solved to residual 1e-8 (TT tolerance 1e-10) under a
+    rank cap of 128."""
     out = []
     for i in range(count):
         rng = np.random.default_rng(base_seed + i)
@@ -113,6 +115,6 @@ def batched_instances(count: int = 256, base_seed: int = 0) -> List[Problem]:
         beta = unit_vector(rng, d)
         gm = gaussian_mixture(rng, d, 4)
         out.append(Problem(name=f"batch_{i}", d=d, N=N, eps=eps, beta=beta, scheme=1,
-                           tol=1e-6, rank_cap=64, source="gauss", gauss=gm,
-                           target_residual=1e-5, seed=base_seed + i))
+                           tol=1e-10, rank_cap=128, source="gauss", gauss=gm,
+                           target_residual=1e-8, seed=base_seed + i))
     return out
