@@ -23,6 +23,10 @@ against the paper:
                       enrichment ("swaps"; Results, Fig. 6).
 * ``metrics``      -- relative Frobenius error, oscillation count,
                       compression ratio (Results).
+* ``mlp``          -- FP64 network, gauge-invariant TT fitting loss and
+                      Adam step of the learned warm start (a systems
+                      addition; the paper trains nothing), with gradients
+                      pinned by finite differences.
 
 Parity status of every function is listed in its module header.
 """

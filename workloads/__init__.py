@@ -118,3 +118,40 @@ def batched_instances(count: int = 256, base_seed: int = 0) -> List[Problem]:
                            tol=1e-10, rank_cap=128, source="gauss", gauss=gm,
                            target_residual=1e-8, seed=base_seed + i))
     return out
+
+
+# ---------------------------------------------------------------- learned warm start
+WARM_D, WARM_N, WARM_SOURCES = 7, 24, 4
+WARM_DIRECTION_SEED = 7_000_003
+
+
+def warm_directions() -> np.ndarray:
+    """The 4 fixed unit directions u_m in R^7 along which the Gaussian centres move."""
+    rng = np.random.default_rng(WARM_DIRECTION_SEED)
+    return np.stack([unit_vector(rng, WARM_D) for _ in range(WARM_SOURCES)])
+
+
+def warm_params(seed: int) -> dict:
+    """Parameters of one learned-warm-start instance: beta on the unit sphere
+    of R^7, eps log-uniform in [1e-4, 1e-2], and 12 source parameters: per
+    Gaussian m an amplitude a_m ~ U[0.5, 1.5], a width s_m ~ U[0.2, 0.5] and a
+    signed offset t_m ~ U[-0.5, 0.5] of its centre t_m u_m along the fixed
+    direction u_m."""
+    rng = np.random.default_rng(seed)
+    beta = unit_vector(rng, WARM_D)
+    eps = float(10.0 ** rng.uniform(-4, -2))
+    amp = rng.uniform(0.5, 1.5, size=WARM_SOURCES)
+    width = rng.uniform(0.2, 0.5, size=WARM_SOURCES)
+    offset = rng.uniform(-0.5, 0.5, size=WARM_SOURCES)
+    return {"beta": beta, "eps": eps, "amp": amp, "width": width, "offset": offset}
+
+
+def warm_instance(seed: int) -> Problem:
+    """7D, N = 24, the instance of warm_params(seed) as a Problem (solved to
+    residual 1e-8, TT tolerance 1e-10, rank cap 128)."""
+    q = warm_params(seed)
+    centre = q["offset"][:, None] * warm_directions()
+    gm = GaussianMixture(amp=q["amp"], centre=centre, width=q["width"])
+    return Problem(name=f"warm7d_{seed}", d=WARM_D, N=[WARM_N] * WARM_D, eps=q["eps"], beta=q["beta"], scheme=1,
+                   tol=1e-10, rank_cap=128, source="gauss", gauss=gm, target_residual=1e-8, seed=seed,
+                   meta={"offset": q["offset"]})
