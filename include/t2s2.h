@@ -108,6 +108,9 @@ typedef struct {
                           the largest local residual is <= 10 * target      */
   int verbose;         /* 1: print one line per sweep on stderr              */
   int precision;       /* T2S2_PRECISION_FP64 or T2S2_PRECISION_MIXED        */
+  int warm_judge;      /* 1: keep x0 only if its FP64 residual ||f - L x0|| /
+                          ||f|| is below that of the seeded random start of a
+                          cold solve, else start cold; 0: always use x0     */
 } t2s2_options;
 
 /* Per-solve report (host struct filled by t2s2_solve). */
@@ -128,6 +131,11 @@ typedef struct {
   int refinement_steps;                         /* preconditioned FP64 steps */
   int fp64_fallbacks;                           /* MIXED: FP32 factors too
                                                    weak, FP64 ones used     */
+  int warm_start_used;                          /* x0 given and kept        */
+  double warm_residual;                         /* residual of x0 when judged,
+                                                   else -1                  */
+  double cold_residual;                         /* residual of the cold start
+                                                   when judged, else -1     */
 } t2s2_report;
 
 /* Message of the last failing call on this thread ("" if none). */
@@ -231,6 +239,75 @@ int t2s2_solve_batched(int count, t2s2_problem* const* probs,
                        const t2s2_tt* const* f, const t2s2_tt* const* x0,
                        const t2s2_options* opts, t2s2_tt* const* x_out,
                        t2s2_report* reps, int workers, void* stream);
+
+/* -------------------------------------------------- learned warm start ---
+ * A systems addition (the paper trains nothing): a multilayer perceptron
+ * maps an instance's parameters to TT cores that start the sweeps.  Widths
+ * w_0 .. w_L; hidden layers tanh(W h + b), output linear.  Parameters are one
+ * flat FP32 device vector: per layer W_k (w_{k+1} x w_k, row-major), then b_k.
+ * The network owns its parameters, gradient, Adam moments, a BF16 copy and
+ * scratch (device memory of the current device), released by destroy.
+ * All arrays below are FP32 device arrays, batch-major (row b = sample b).
+ * Calls on one network must not run concurrently. */
+typedef struct t2s2_mlp t2s2_mlp;
+
+/* Glorot-uniform weights (seeded), zero biases.  1 <= n_layers <= 15,
+ * widths has n_layers + 1 entries in [1, 65536].  EINVAL on bad sizes. */
+int t2s2_mlp_create(int n_layers, const int* widths, unsigned long long seed,
+                    t2s2_mlp** out);
+void t2s2_mlp_destroy(t2s2_mlp* net);
+int t2s2_mlp_param_count(const t2s2_mlp* net, long long* count);
+/* Copy the parameters (which = 0) or the last gradient (which = 1) into dst
+ * (param_count floats, device); set_params copies src in and resets Adam. */
+int t2s2_mlp_get_params(t2s2_mlp* net, float* dst, int which, void* stream);
+int t2s2_mlp_set_params(t2s2_mlp* net, const float* src, void* stream);
+/* y (batch x w_L) = net(x (batch x w_0)) in FP32; keeps the activations. */
+int t2s2_mlp_forward(t2s2_mlp* net, int batch, const float* x, float* y,
+                     void* stream);
+/* Gradient of sum(dy * y) for the forward pass just made on the same x and
+ * batch (EINVAL otherwise) into the network's gradient buffer. */
+int t2s2_mlp_backward(t2s2_mlp* net, int batch, const float* x,
+                      const float* dy, void* stream);
+/* One Adam step (Kingma and Ba) with that gradient. */
+int t2s2_mlp_adam_step(t2s2_mlp* net, float lr, float beta1, float beta2,
+                       float eps, void* stream);
+/* Inference with weights and biases rounded to BF16 (round to nearest
+ * even), FP32 activations and accumulation. */
+int t2s2_mlp_infer_bf16(t2s2_mlp* net, int batch, const float* x, float* y,
+                        void* stream);
+/* Flat TT layout: cores of uniform interior rank r (boundary ranks 1) one
+ * after another, core l [r_{l-1}][n_l][r_l] C-contiguous; 1 <= d <= 16,
+ * n_l <= 64, r <= 16.
+ * Gauge-invariant fitting loss per sample, loss[b] = ||P - T||^2 / ||T||^2
+ * of the TTs held in pred and target (Methods: the TT representation is not
+ * unique, so cores are never compared directly), and dpred = d loss / d pred,
+ * by left/right contractions of the TT format. */
+int t2s2_tt_fit_loss(int batch, int d, const int* n, int rank,
+                     const float* pred, const float* target, float* loss,
+                     float* dpred, void* stream);
+/* Training: epochs of shuffled (seeded) mini-batches of the mean fitting
+ * loss, backward, Adam (betas 0.9, 0.999, eps 1e-8).  x: count x w_0,
+ * targets: count x w_L flat TTs, w_L must equal the flat size of (d, n,
+ * rank).  epoch_loss (host, optional, epochs floats) receives the mean
+ * training loss of each epoch.  On a network that has taken no Adam step
+ * yet, the output bias is first set to the mean target and the output
+ * weights are scaled by 0.1 (the start is then a typical TT, whose
+ * multilinear gradients do not vanish).  Synchronises stream. */
+int t2s2_mlp_train(t2s2_mlp* net, int count, const float* x,
+                   const float* targets, int d, const int* n, int rank,
+                   int epochs, int batch, float lr, unsigned long long seed,
+                   float* epoch_loss, void* stream);
+/* TT (FP64 cores, ranks <= rank) -> flat FP32 vector, zero-padded to rank.
+ * canonical = 1 also fixes the sign of each rank column of cores 0..d-2 so
+ * that its largest-magnitude entry is positive (undone in the next core, so
+ * the tensor is unchanged): for a left-orthonormal TT from rounding this
+ * makes the packed vector a function of the tensor alone. */
+int t2s2_tt_pack(const t2s2_tt* x, int rank, int canonical, float* out,
+                 void* stream);
+/* Flat FP32 vector -> TT with FP64 cores of ranks (1, rank, .., rank, 1);
+ * x_out->cores must hold them; x_out->ranks is written. */
+int t2s2_tt_unpack(int d, const int* n, int rank, const float* in,
+                   t2s2_tt* x_out, void* stream);
 
 /* --------------------------------------------------------- diagnostics ---
  * Kernel-class timing for benchmarks.  While enabled, every library kernel

@@ -150,6 +150,9 @@ class SolveResult:
     local_systems: int = 0
     refinement_steps: int = 0
     fp64_fallbacks: int = 0
+    warm_start_used: int = 0
+    warm_residual: float = -1.0
+    cold_residual: float = -1.0
 
     @property
     def converged(self) -> bool:
@@ -228,10 +231,11 @@ class Problem:
     def solve(self, f: TT, x0: Optional[TT] = None, *, tol: float = 1e-10, target: float = 1e-8,
               max_sweeps: int = 40, kick: int = 8, rank_cap: Optional[int] = None, init_rank: int = 2,
               seed: int = 0, check_every: int = 1, verbose: bool = False, out: Optional[TT] = None,
-              precision: int = PRECISION_FP64) -> SolveResult:
+              precision: int = PRECISION_FP64, warm_judge: bool = False) -> SolveResult:
         cap = int(rank_cap or self.rank_cap)
         x = out if out is not None else TT.empty(self.m, cap)
         o = _options(tol, target, max_sweeps, kick, cap, init_rank, seed, check_every, verbose, precision)
+        o.warm_judge = int(bool(warm_judge))
         rep = _lib.Report()
         fs, xs = f._struct(), x._struct()
         x0s = x0._struct() if x0 is not None else None
@@ -261,7 +265,8 @@ def _result(x: TT, code: int, rep, d: int) -> SolveResult:
                        history_max_rank=list(rep.history_max_rank[:h]),
                        history_time_ms=list(rep.history_time_ms[:h]), precision=rep.precision,
                        local_systems=rep.local_systems, refinement_steps=rep.refinement_steps,
-                       fp64_fallbacks=rep.fp64_fallbacks)
+                       fp64_fallbacks=rep.fp64_fallbacks, warm_start_used=rep.warm_start_used,
+                       warm_residual=rep.warm_residual, cold_residual=rep.cold_residual)
 
 
 def solve_batched(problems: Sequence["Problem"], fs: Sequence[TT], *, x0s: Optional[Sequence[Optional[TT]]] = None,

@@ -17,6 +17,9 @@ EXPORTED = [
     "t2s2_problem_operator", "t2s2_problem_colloc", "t2s2_tt_matvec", "t2s2_tt_norm",
     "t2s2_tt_residual_norm", "t2s2_tt_round", "t2s2_solve", "t2s2_solve_batched", "t2s2_default_options",
     "t2s2_timing_enable", "t2s2_timing_read", "t2s2_timing_class_name",
+    "t2s2_mlp_create", "t2s2_mlp_destroy", "t2s2_mlp_param_count", "t2s2_mlp_get_params", "t2s2_mlp_set_params",
+    "t2s2_mlp_forward", "t2s2_mlp_backward", "t2s2_mlp_adam_step", "t2s2_mlp_infer_bf16", "t2s2_mlp_train",
+    "t2s2_tt_fit_loss", "t2s2_tt_pack", "t2s2_tt_unpack",
 ]
 TIMING_CLASSES = ["gemm_f64", "gemm_c128", "ttm_matvec", "schur_qr", "hessenberg", "jacobi_svd", "cholesky",
                   "trtri", "trevec", "kron_trisolve", "other"]
@@ -35,7 +38,8 @@ class TTMStruct(C.Structure):
 class Options(C.Structure):
     _fields_ = [("tol", C.c_double), ("target", C.c_double), ("max_sweeps", C.c_int), ("kick", C.c_int),
                 ("rank_cap", C.c_int), ("init_rank", C.c_int), ("seed", C.c_ulonglong),
-                ("check_every", C.c_int), ("verbose", C.c_int), ("precision", C.c_int)]
+                ("check_every", C.c_int), ("verbose", C.c_int), ("precision", C.c_int),
+                ("warm_judge", C.c_int)]
 
 
 class Report(C.Structure):
@@ -44,7 +48,9 @@ class Report(C.Structure):
                 ("history_len", C.c_int), ("history_residual", C.c_double * MAX_HISTORY),
                 ("history_local", C.c_double * MAX_HISTORY), ("history_max_rank", C.c_int * MAX_HISTORY),
                 ("history_time_ms", C.c_double * MAX_HISTORY), ("precision", C.c_int),
-                ("local_systems", C.c_int), ("refinement_steps", C.c_int), ("fp64_fallbacks", C.c_int)]
+                ("local_systems", C.c_int), ("refinement_steps", C.c_int), ("fp64_fallbacks", C.c_int),
+                ("warm_start_used", C.c_int), ("warm_residual", C.c_double),
+                ("cold_residual", C.c_double)]
 
 
 class LibraryMissing(RuntimeError):
@@ -83,6 +89,21 @@ def lib() -> C.CDLL:
     ttp = C.POINTER(TTStruct)
     L.t2s2_solve_batched.argtypes = [C.c_int, C.POINTER(vp), C.POINTER(ttp), C.POINTER(ttp), C.POINTER(Options),
                                      C.POINTER(ttp), C.POINTER(Report), C.c_int, vp]
+    fp, u64 = C.POINTER(C.c_float), C.c_ulonglong
+    L.t2s2_mlp_create.argtypes = [C.c_int, ip, u64, C.POINTER(vp)]
+    L.t2s2_mlp_destroy.argtypes = [vp]
+    L.t2s2_mlp_destroy.restype = None
+    L.t2s2_mlp_param_count.argtypes = [vp, C.POINTER(C.c_longlong)]
+    L.t2s2_mlp_get_params.argtypes = [vp, vp, C.c_int, vp]
+    L.t2s2_mlp_set_params.argtypes = [vp, vp, vp]
+    L.t2s2_mlp_forward.argtypes = [vp, C.c_int, vp, vp, vp]
+    L.t2s2_mlp_backward.argtypes = [vp, C.c_int, vp, vp, vp]
+    L.t2s2_mlp_adam_step.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float, vp]
+    L.t2s2_mlp_infer_bf16.argtypes = [vp, C.c_int, vp, vp, vp]
+    L.t2s2_mlp_train.argtypes = [vp, C.c_int, vp, vp, C.c_int, ip, C.c_int, C.c_int, C.c_int, C.c_float, u64, fp, vp]
+    L.t2s2_tt_fit_loss.argtypes = [C.c_int, C.c_int, ip, C.c_int, vp, vp, vp, vp, vp]
+    L.t2s2_tt_pack.argtypes = [C.POINTER(TTStruct), C.c_int, C.c_int, vp, vp]
+    L.t2s2_tt_unpack.argtypes = [C.c_int, ip, C.c_int, vp, C.POINTER(TTStruct), vp]
     L.t2s2_default_options.argtypes = [C.POINTER(Options)]
     L.t2s2_default_options.restype = None
     L.t2s2_timing_enable.argtypes = [C.c_int]
@@ -90,7 +111,7 @@ def lib() -> C.CDLL:
     L.t2s2_timing_class_name.argtypes = [C.c_int]
     L.t2s2_timing_class_name.restype = C.c_char_p
     for name in EXPORTED:
-        if name not in ("t2s2_last_error", "t2s2_default_options", "t2s2_timing_class_name"):
+        if name not in ("t2s2_last_error", "t2s2_default_options", "t2s2_timing_class_name", "t2s2_mlp_destroy"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L

@@ -11,8 +11,13 @@
 #include <thread>
 #include <vector>
 
+#include "mlp.h"
 #include "solver.h"
 #include "spectral_host.h"
+
+struct t2s2_mlp {
+  t2s2::Mlp* N = nullptr;
+};
 
 struct t2s2_problem {
   t2s2::Problem* P = nullptr;
@@ -93,6 +98,7 @@ int solve_one(t2s2_problem* p, const t2s2_tt* f, const t2s2_tt* x0, const t2s2_o
     T2S2_CHECK(opts->precision == T2S2_PRECISION_FP64 || opts->precision == T2S2_PRECISION_MIXED,
                "precision must be T2S2_PRECISION_FP64 or T2S2_PRECISION_MIXED");
     o.precision = opts->precision;
+    o.warm_judge = opts->warm_judge;
   }
   t2s2::DTT xd;
   xd.d = fd.d;
@@ -123,6 +129,9 @@ int solve_one(t2s2_problem* p, const t2s2_tt* f, const t2s2_tt* x0, const t2s2_o
     rep->local_systems = r.local_systems;
     rep->refinement_steps = r.refinement_steps;
     rep->fp64_fallbacks = r.fp64_fallbacks;
+    rep->warm_start_used = r.warm_start_used;
+    rep->warm_residual = r.warm_residual;
+    rep->cold_residual = r.cold_residual;
     for (int i = 0; i < h; ++i) {
       rep->history_residual[i] = r.hist_res[i];
       rep->history_local[i] = r.hist_local[i];
@@ -309,6 +318,7 @@ void t2s2_default_options(t2s2_options* o) {
   o->check_every = 1;
   o->verbose = 0;
   o->precision = T2S2_PRECISION_FP64;
+  o->warm_judge = 0;
 }
 
 int t2s2_solve(t2s2_problem* p, const t2s2_tt* f, const t2s2_tt* x0, const t2s2_options* opts, t2s2_tt* x_out,
@@ -392,6 +402,136 @@ int t2s2_solve_batched(int count, t2s2_problem* const* probs, const t2s2_tt* con
       }
     if (worst != T2S2_OK) t2s2::set_last_error(first);
     return worst;
+  });
+}
+
+// ------------------------------------------------------- learned warm start
+int t2s2_mlp_create(int n_layers, const int* widths, unsigned long long seed, t2s2_mlp** out) {
+  return guarded([&] {
+    T2S2_CHECK(out && widths && n_layers >= 1 && n_layers <= 15, "mlp_create: bad arguments");
+    *out = nullptr;
+    std::vector<int> w(widths, widths + n_layers + 1);
+    auto* h = new t2s2_mlp();
+    try {
+      h->N = t2s2::mlp_create(w, seed);
+    } catch (...) {
+      delete h;
+      throw;
+    }
+    *out = h;
+    return T2S2_OK;
+  });
+}
+
+void t2s2_mlp_destroy(t2s2_mlp* net) {
+  if (!net) return;
+  delete net->N;
+  delete net;
+}
+
+int t2s2_mlp_param_count(const t2s2_mlp* net, long long* count) {
+  return guarded([&] {
+    T2S2_CHECK(net && count, "NULL argument");
+    *count = net->N->nparam;
+    return T2S2_OK;
+  });
+}
+
+int t2s2_mlp_get_params(t2s2_mlp* net, float* dst, int which, void* stream) {
+  return guarded([&] {
+    T2S2_CHECK(net && dst && (which == 0 || which == 1), "mlp_get_params: bad arguments");
+    const float* src = which == 0 ? net->N->params : net->N->grad;
+    T2S2_HIP(hipMemcpyAsync(dst, src, sizeof(float) * net->N->nparam, hipMemcpyDeviceToDevice,
+                            static_cast<hipStream_t>(stream)));
+    return T2S2_OK;
+  });
+}
+
+int t2s2_mlp_set_params(t2s2_mlp* net, const float* src, void* stream) {
+  return guarded([&] {
+    T2S2_CHECK(net && src, "NULL argument");
+    t2s2::Mlp& N = *net->N;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    T2S2_HIP(hipMemcpyAsync(N.params, src, sizeof(float) * N.nparam, hipMemcpyDeviceToDevice, s));
+    T2S2_HIP(hipMemsetAsync(N.m, 0, sizeof(float) * N.nparam, s));
+    T2S2_HIP(hipMemsetAsync(N.v, 0, sizeof(float) * N.nparam, s));
+    N.t = 0;
+    N.bf16_valid = false;
+    return T2S2_OK;
+  });
+}
+
+int t2s2_mlp_forward(t2s2_mlp* net, int batch, const float* x, float* y, void* stream) {
+  return guarded([&] {
+    T2S2_CHECK(net && x && y && batch >= 1, "mlp_forward: bad arguments");
+    t2s2::mlp_forward(*net->N, static_cast<hipStream_t>(stream), batch, x, y);
+    return T2S2_OK;
+  });
+}
+
+int t2s2_mlp_backward(t2s2_mlp* net, int batch, const float* x, const float* dy, void* stream) {
+  return guarded([&] {
+    T2S2_CHECK(net && x && dy && batch >= 1, "mlp_backward: bad arguments");
+    t2s2::mlp_backward(*net->N, static_cast<hipStream_t>(stream), batch, x, dy);
+    return T2S2_OK;
+  });
+}
+
+int t2s2_mlp_adam_step(t2s2_mlp* net, float lr, float beta1, float beta2, float eps, void* stream) {
+  return guarded([&] {
+    T2S2_CHECK(net && std::isfinite(lr) && beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps >= 0.f,
+               "mlp_adam_step: bad arguments");
+    t2s2::mlp_adam(*net->N, static_cast<hipStream_t>(stream), lr, beta1, beta2, eps);
+    return T2S2_OK;
+  });
+}
+
+int t2s2_mlp_infer_bf16(t2s2_mlp* net, int batch, const float* x, float* y, void* stream) {
+  return guarded([&] {
+    T2S2_CHECK(net && x && y && batch >= 1, "mlp_infer_bf16: bad arguments");
+    t2s2::mlp_infer_bf16(*net->N, static_cast<hipStream_t>(stream), batch, x, y);
+    return T2S2_OK;
+  });
+}
+
+int t2s2_mlp_train(t2s2_mlp* net, int count, const float* x, const float* targets, int d, const int* n, int rank,
+                   int epochs, int batch, float lr, unsigned long long seed, float* epoch_loss, void* stream) {
+  return guarded([&] {
+    T2S2_CHECK(net && x && targets && n && count >= 1 && epochs >= 0 && batch >= 1 && lr > 0.f,
+               "mlp_train: bad arguments");
+    const auto h = t2s2::mlp_train(*net->N, static_cast<hipStream_t>(stream), count, x, targets, d, n, rank, epochs,
+                                   batch, lr, seed);
+    if (epoch_loss) std::copy(h.begin(), h.end(), epoch_loss);
+    return T2S2_OK;
+  });
+}
+
+int t2s2_tt_fit_loss(int batch, int d, const int* n, int rank, const float* pred, const float* target, float* loss,
+                     float* dpred, void* stream) {
+  return guarded([&] {
+    T2S2_CHECK(n && pred && target && loss && dpred && batch >= 0, "tt_fit_loss: bad arguments");
+    t2s2::tt_fit_loss(static_cast<hipStream_t>(stream), batch, d, n, rank, pred, target, loss, dpred, 1.0f);
+    return T2S2_OK;
+  });
+}
+
+int t2s2_tt_pack(const t2s2_tt* x, int rank, int canonical, float* out, void* stream) {
+  return guarded([&] {
+    T2S2_CHECK(out, "NULL argument");
+    const t2s2::DTT xd = to_dtt(x);
+    t2s2::tt_pack(static_cast<hipStream_t>(stream), xd, rank, canonical ? 1 : 0, out);
+    return T2S2_OK;
+  });
+}
+
+int t2s2_tt_unpack(int d, const int* n, int rank, const float* in, t2s2_tt* x_out, void* stream) {
+  return guarded([&] {
+    T2S2_CHECK(n && in && x_out && x_out->d == d && x_out->cores && x_out->ranks, "tt_unpack: bad arguments");
+    t2s2::DTT xd;
+    xd.c.assign(x_out->cores, x_out->cores + d);
+    t2s2::tt_unpack(static_cast<hipStream_t>(stream), d, n, rank, in, xd);
+    for (int l = 0; l <= d; ++l) x_out->ranks[l] = xd.r[l];
+    return T2S2_OK;
   });
 }
 

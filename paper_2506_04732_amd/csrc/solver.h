@@ -52,6 +52,7 @@ struct SolveOptions {
   int check_every = 1;
   int verbose = 0;
   int precision = 0;  // 0 FP64, 1 mixed (FP32 factors inside FP64 refinement)
+  int warm_judge = 0;  // 1: use x0 only if its FP64 residual beats the seeded cold start's
 };
 
 struct SolveReport {
@@ -61,6 +62,8 @@ struct SolveReport {
   std::vector<double> hist_res, hist_local, hist_time;
   std::vector<int> hist_rank;
   int local_systems = 0, refinement_steps = 0, fp64_fallbacks = 0;
+  int warm_start_used = 0;
+  double warm_residual = -1.0, cold_residual = -1.0;
 };
 
 Problem* problem_create(int d, const int* N, double eps, const double* beta, int scheme, int rank_cap);

@@ -557,6 +557,25 @@ struct Amen {
     h1 = c.sc->get<double2>("am.h1", big);
     g0 = c.sc->get<float2>("am.g0", big);
     g1 = c.sc->get<float2>("am.g1", big);
+    if (x0 && o.warm_judge) {
+      // the given start is kept only if its FP64 residual beats that of the
+      // seeded random start a cold solve would use (the fallback)
+      rep.warm_residual = tt_residual_norm(p, c, *x0, fin);
+      DTT cold;
+      cold.d = d;
+      cold.n = m;
+      cold.r.assign(d + 1, 1);
+      cold.c.resize(d);
+      for (int l = 1; l < d; ++l) cold.r[l] = std::min(std::max(1, o.init_rank), maxrank[l]);
+      for (int l = 0; l < d; ++l) {
+        const long sz = (long)cold.r[l] * m[l] * cold.r[l + 1];
+        cold.c[l] = buf("cold" + std::to_string(l), (size_t)sz);
+        fill_random(c.s, cold.c[l], sz, o.seed * 1315423911ULL + 17ULL * l + 1ULL);
+      }
+      rep.cold_residual = tt_residual_norm(p, c, cold, fin);
+      if (!(rep.warm_residual < rep.cold_residual)) x0 = nullptr;
+    }
+    rep.warm_start_used = x0 ? 1 : 0;
     // initial x (caller's buffers) and z (scratch)
     xr.assign(d + 1, 1);
     zr.assign(d + 1, 1);

@@ -125,20 +125,20 @@ WARM_D, WARM_N, WARM_SOURCES = 7, 24, 4
 WARM_DIRECTION_SEED = 7_000_003
 
 
-def warm_directions() -> np.ndarray:
-    """The 4 fixed unit directions u_m in R^7 along which the Gaussian centres move."""
-    rng = np.random.default_rng(WARM_DIRECTION_SEED)
-    return np.stack([unit_vector(rng, WARM_D) for _ in range(WARM_SOURCES)])
+def warm_directions(d: int = WARM_D) -> np.ndarray:
+    """The 4 fixed unit directions u_m in R^d along which the Gaussian centres move."""
+    rng = np.random.default_rng(WARM_DIRECTION_SEED + d)
+    return np.stack([unit_vector(rng, d) for _ in range(WARM_SOURCES)])
 
 
-def warm_params(seed: int) -> dict:
+def warm_params(seed: int, d: int = WARM_D) -> dict:
     """Parameters of one learned-warm-start instance: beta on the unit sphere
-    of R^7, eps log-uniform in [1e-4, 1e-2], and 12 source parameters: per
-    Gaussian m an amplitude a_m ~ U[0.5, 1.5], a width s_m ~ U[0.2, 0.5] and a
-    signed offset t_m ~ U[-0.5, 0.5] of its centre t_m u_m along the fixed
-    direction u_m."""
+    of R^d (d = 7), eps log-uniform in [1e-4, 1e-2], and 12 source
+    parameters: per Gaussian m an amplitude a_m ~ U[0.5, 1.5], a width
+    s_m ~ U[0.2, 0.5] and a signed offset t_m ~ U[-0.5, 0.5] of its centre
+    t_m u_m along the fixed direction u_m."""
     rng = np.random.default_rng(seed)
-    beta = unit_vector(rng, WARM_D)
+    beta = unit_vector(rng, d)
     eps = float(10.0 ** rng.uniform(-4, -2))
     amp = rng.uniform(0.5, 1.5, size=WARM_SOURCES)
     width = rng.uniform(0.2, 0.5, size=WARM_SOURCES)
@@ -146,12 +146,13 @@ def warm_params(seed: int) -> dict:
     return {"beta": beta, "eps": eps, "amp": amp, "width": width, "offset": offset}
 
 
-def warm_instance(seed: int) -> Problem:
-    """7D, N = 24, the instance of warm_params(seed) as a Problem (solved to
-    residual 1e-8, TT tolerance 1e-10, rank cap 128)."""
-    q = warm_params(seed)
-    centre = q["offset"][:, None] * warm_directions()
+def warm_instance(seed: int, d: int = WARM_D, N: int = WARM_N) -> Problem:
+    """The instance of warm_params(seed, d) as a Problem on N nodes per
+    dimension (7D, N = 24 for the learned warm start), solved to residual
+    1e-8 with TT tolerance 1e-10 under rank cap 128."""
+    q = warm_params(seed, d)
+    centre = q["offset"][:, None] * warm_directions(d)
     gm = GaussianMixture(amp=q["amp"], centre=centre, width=q["width"])
-    return Problem(name=f"warm7d_{seed}", d=WARM_D, N=[WARM_N] * WARM_D, eps=q["eps"], beta=q["beta"], scheme=1,
+    return Problem(name=f"warm{d}d_N{N}_{seed}", d=d, N=[N] * d, eps=q["eps"], beta=q["beta"], scheme=1,
                    tol=1e-10, rank_cap=128, source="gauss", gauss=gm, target_residual=1e-8, seed=seed,
-                   meta={"offset": q["offset"]})
+                   meta={"params": q})
