@@ -161,6 +161,89 @@ def bench_batched(args, rank: int):
         print(json.dumps(out), flush=True)
 
 
+WARM_OPTS = dict(tol=1e-10, target=1e-8, max_sweeps=30, kick=8, init_rank=8, check_every=0, seed=0)
+
+
+def bench_warm(args, rank: int):
+    """Learned warm start, 7D N=24: solve train + test instances (batched),
+    train the 3x256 network on the training solutions (rank-8 targets), then
+    solve each held-out instance cold and warm (BF16 inference, residual
+    judge).  value = mean seconds per held-out warm solve (inference incl.)."""
+    import numpy as np
+    import torch
+    import paper_2506_04732_amd as t2s2
+    import workloads
+    from paper_2506_04732_amd import sources, warmstart
+
+    d, N, r8, cap = 7, 24, 8, 128
+    ntr, nte = args.train, args.test
+    t0 = time.perf_counter()
+    insts = [workloads.warm_instance(10 ** 6 + i) for i in range(ntr + nte)]
+    probs = [t2s2.Problem(q.d, q.N, q.eps, q.beta, q.scheme, rank_cap=cap) for q in insts]
+    fs = [sources.source_tt(p, sources.gaussian_factors(p, q.gauss.amp, q.gauss.centre, q.gauss.width))
+          for p, q in zip(probs, insts)]
+    res = []
+    for k in range(0, len(probs), 64):
+        res += t2s2.solve_batched(probs[k:k + 64], fs[k:k + 64], workers=args.workers, **WARM_OPTS)
+        print(f"warm7d: solved {len(res)} / {len(probs)} in {time.perf_counter() - t0:.0f} s", file=sys.stderr,
+              flush=True)
+    t_gen = time.perf_counter() - t0
+    m = [N - 2] * d
+    T = torch.stack([warmstart.solution_target(p, r.x, r8) for p, r in zip(probs, res)])
+    X = torch.from_numpy(warmstart.features([q.meta["params"] for q in insts])).cuda()
+    net = warmstart.Network([X.shape[1], 256, 256, 256, warmstart.flat_size(m, r8)], seed=0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    hist = net.train(X[:ntr].contiguous(), T[:ntr].contiguous(), m, r8, epochs=args.epochs, batch=32, lr=1e-3, seed=1)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    print(f"warm7d: trained {args.epochs} epochs in {t_train:.0f} s, loss {hist[0]:.3f} -> {hist[-1]:.3f}",
+          file=sys.stderr, flush=True)
+    Xte, Tte = X[ntr:].contiguous(), T[ntr:].contiguous()
+    held, _ = warmstart.fit_loss(net.infer_bf16(Xte).contiguous(), Tte, m, r8)
+    base, _ = warmstart.fit_loss(T[:ntr].mean(0, keepdim=True).expand(nte, -1).contiguous(), Tte, m, r8)
+    cold_s, warm_s, cold_sw, warm_sw, used, rho_w, rho_c, conv_w = [], [], [], [], [], [], [], []
+    for i in range(nte):
+        p, f = probs[ntr + i], fs[ntr + i]
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        rc = p.solve(f, **WARM_OPTS)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        y = net.infer_bf16(Xte[i:i + 1].contiguous())
+        x0 = warmstart.unpack(y[0].contiguous(), m, r8, cap=cap)
+        rw = p.solve(f, x0=x0, warm_judge=True, **WARM_OPTS)
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        cold_s.append(tb - ta)
+        warm_s.append(tc - tb)
+        cold_sw.append(rc.sweeps)
+        warm_sw.append(rw.sweeps)
+        used.append(rw.warm_start_used)
+        rho_w.append(rw.warm_residual)
+        rho_c.append(rw.cold_residual)
+        conv_w.append(rw.converged)
+    out = {
+        "metric": "learned warm start, 7D N=24: seconds per held-out solve to rel. resid 1e-8 (warm incl. BF16 "
+                  "inference)",
+        "value": float(np.mean(warm_s)), "unit": "s", "n_gpus": 1, "steps": nte, "warmup": 0,
+        "ms_per_step": float(np.mean(warm_s)) * 1e3, "higher_is_better": False, "scaling": "strong",
+        "vs_baseline": None, "dtype": "f64 solve, f32 train, bf16 infer", "data": "synthetic",
+        "config": {"workload": "warm7d_N24_eps1e-4-1e-2_gauss4x3", "train": ntr, "test": nte,
+                   "epochs": args.epochs, "rank": r8, "rank_cap": cap, **WARM_OPTS},
+        "cold_s_mean": float(np.mean(cold_s)), "warm_s_mean": float(np.mean(warm_s)),
+        "sweeps_cold_mean": float(np.mean(cold_sw)), "sweeps_warm_mean": float(np.mean(warm_sw)),
+        "sweeps_cold": cold_sw, "sweeps_warm": warm_sw, "warm_used": int(sum(used)),
+        "warm_converged": int(sum(conv_w)),
+        "heldout_fit_loss_median": float(held.median().item()), "mean_target_fit_loss_median": float(base.median().item()),
+        "warm_residual_median": float(np.median(rho_w)), "cold_residual_median": float(np.median(rho_c)),
+        "train_loss_first_last": [hist[0], hist[-1]], "generate_s": t_gen, "train_s": t_train,
+        "roofline": None, "cpu_baseline": None,
+    }
+    if rank == 0:
+        print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -169,8 +252,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=3)
     ap.add_argument("--no-oracle-check", action="store_true")
-    ap.add_argument("--workload", choices=["6d", "batched256"], default="6d",
-                    help="6d: the 6D N=32 solve (default); batched256: 256 uneven instances solved concurrently")
+    ap.add_argument("--workload", choices=["6d", "batched256", "warm7d"], default="6d",
+                    help="6d: the 6D N=32 solve (default); batched256: 256 uneven instances solved concurrently; "
+                         "warm7d: learned warm start on 7D N=24 (train on solver solutions, held-out cold vs warm)")
+    ap.add_argument("--train", type=int, default=1024, help="warm7d: training instances")
+    ap.add_argument("--test", type=int, default=32, help="warm7d: held-out instances")
+    ap.add_argument("--epochs", type=int, default=200, help="warm7d: training epochs")
     ap.add_argument("--workers", type=int, default=8, help="batched256: concurrent instances")
     ap.add_argument("--seq-baseline", action="store_true",
                     help="batched256: also time the 256 instances solved one after another")
@@ -194,6 +281,8 @@ def main():
     rank = int(os.environ.get("RANK", "0"))
     if args.workload == "batched256":
         return bench_batched(args, rank)
+    if args.workload == "warm7d":
+        return bench_warm(args, rank)
 
     import torch
     import paper_2506_04732_amd as t2s2
