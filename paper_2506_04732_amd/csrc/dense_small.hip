@@ -269,12 +269,37 @@ __global__ void __launch_bounds__(kNT) jacobi_rows_kernel(int k, int c, double* 
 // ------------------------------------------------- Hessenberg reduction
 // A (n x n, real, row-major) -> H = Q^T A Q upper Hessenberg, by Householder
 // reflectors on columns 0..n-3.  QT receives Q^T.
+// Column sums w[j] = beta sum_{i >= r0} v[i] X[i][j] for j in [c0, n): 16
+// row groups of 64 lanes each sum a strided share of the rows of 64
+// consecutive columns (coalesced), partial sums meet in LDS.
+template <class R>
+__device__ void hess_colsum(int n, int r0, int c0, const R* __restrict__ X, const R* v, R beta, R* w, R* part) {
+  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6, ngrp = blockDim.x >> 6;
+  for (int cb = c0; cb < n; cb += 64) {
+    const int j = cb + lane;
+    R acc = R(0.0);
+    if (j < n)
+      for (int i = r0 + grp; i < n; i += ngrp) acc = fma(v[i], X[(long)i * n + j], acc);
+    part[grp * 64 + lane] = acc;
+    __syncthreads();
+    if (grp == 0 && j < n) {
+      R t = R(0.0);
+      for (int g = 0; g < ngrp; ++g) t += part[g * 64 + lane];
+      w[j] = beta * t;
+    }
+    __syncthreads();
+  }
+}
+
+// A (n x n, real, row-major) -> H = Q^T A Q upper Hessenberg, by Householder
+// reflectors on columns 0..n-3.  QT receives Q^T.
 template <bool LDS, class R>
 __global__ void __launch_bounds__(kNT) hessenberg_kernel(int n, R* __restrict__ A, R* __restrict__ QT,
                                                          R* __restrict__ work) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   R* lds = reinterpret_cast<R*>(lds_raw);
   __shared__ R red[kNT / 64];
+  __shared__ R part[kNT];
   __shared__ R s_alpha, s_vnorm2;
   const long nn = (long)n * n;
   constexpr bool in_lds = LDS;
@@ -290,6 +315,7 @@ __global__ void __launch_bounds__(kNT) hessenberg_kernel(int n, R* __restrict__ 
     v = work;
     w = work + n;
   }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
   if (in_lds)
     for (long e = threadIdx.x; e < nn; e += blockDim.x) H[e] = A[e];
   for (long e = threadIdx.x; e < nn; e += blockDim.x) QT[e] = ((e / n) == (e % n)) ? R(1.0) : R(0.0);
@@ -302,14 +328,13 @@ __global__ void __launch_bounds__(kNT) hessenberg_kernel(int n, R* __restrict__ 
       v[i] = x;
       s = fma(x, x, s);
     }
-    // block sum (reuse block_max pattern with sums)
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
     __syncthreads();
-    if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = s;
+    if (lane == 0) red[wave] = s;
     __syncthreads();
     if (threadIdx.x == 0) {
       R tot = R(0.0);
-      for (int i = 0; i < (int)(blockDim.x / 64); ++i) tot += red[i];
+      for (int i = 0; i < nwave; ++i) tot += red[i];
       const R x0 = v[k + 1];
       const R tail = tot - x0 * x0;
       if (tail <= TinyOf<R>::value * fmax(R(1.0), tot)) {
@@ -325,13 +350,8 @@ __global__ void __launch_bounds__(kNT) hessenberg_kernel(int n, R* __restrict__ 
     const R vn2 = s_vnorm2;
     if (vn2 == R(0.0)) continue;
     const R beta = R(2.0) / vn2;
-    // left: H[k+1:, :] -= beta v (v^T H[k+1:, :]) ; columns k..n-1 suffice
-    for (int j = k + threadIdx.x; j < n; j += blockDim.x) {
-      R d = R(0.0);
-      for (int i = k + 1; i < n; ++i) d = fma(v[i], H[(long)i * n + j], d);
-      w[j] = beta * d;
-    }
-    __syncthreads();
+    // left: H[k+1:, :] -= v (beta v^T H[k+1:, :]) ; columns k..n-1 suffice
+    hess_colsum<R>(n, k + 1, k, H, v, beta, w, part);
     {
       const int rows = n - k - 1, cols = n - k;
       const long tot = (long)rows * cols;
@@ -341,11 +361,12 @@ __global__ void __launch_bounds__(kNT) hessenberg_kernel(int n, R* __restrict__ 
       }
     }
     __syncthreads();
-    // right: H[:, k+1:] -= beta (H[:, k+1:] v) v^T
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    // right: H[:, k+1:] -= (beta H[:, k+1:] v) v^T ; one wavefront per row
+    for (int i = wave; i < n; i += nwave) {
       R d = R(0.0);
-      for (int j = k + 1; j < n; ++j) d = fma(H[(long)i * n + j], v[j], d);
-      w[i] = beta * d;
+      for (int j = k + 1 + lane; j < n; j += 64) d = fma(H[(long)i * n + j], v[j], d);
+      for (int off = 32; off > 0; off >>= 1) d += __shfl_xor(d, off, 64);
+      if (lane == 0) w[i] = beta * d;
     }
     __syncthreads();
     {
@@ -357,13 +378,8 @@ __global__ void __launch_bounds__(kNT) hessenberg_kernel(int n, R* __restrict__ 
       }
     }
     __syncthreads();
-    // QT = P QT (P symmetric): rows k+1.. of QT: QT[k+1:, :] -= beta v (v^T QT[k+1:, :])
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
-      R d = R(0.0);
-      for (int i = k + 1; i < n; ++i) d = fma(v[i], QT[(long)i * n + j], d);
-      w[j] = beta * d;
-    }
-    __syncthreads();
+    // QT = P QT (P symmetric): QT[k+1:, :] -= v (beta v^T QT[k+1:, :])
+    hess_colsum<R>(n, k + 1, 0, QT, v, beta, w, part);
     {
       const int rows = n - k - 1;
       const long tot = (long)rows * n;
@@ -467,8 +483,10 @@ void jacobi_rows(hipStream_t s, int k, int c, double* B, double* JT, double* U, 
 template <class R>
 static void hessenberg_t(hipStream_t s, int n, R* A, R* QT, R* work) {
   const long need = ((long)n * n + 2L * n) * (long)sizeof(R);
+  // static LDS of the kernel: partial sums (kNT) and the reduction slots
+  const long static_bytes = (long)sizeof(R) * (kNT + kNT / 64 + 2);
   TimedScope ts(s, KC_HESS, sizeof(R) * 3.0 * n * n, 14.0 * n * n * n / 3.0);
-  if (need <= kLdsBytes)
+  if (need <= kLdsBytes - static_bytes)
     hipLaunchKernelGGL((hessenberg_kernel<true, R>), dim3(1), dim3(kNT), (size_t)need, s, n, A, QT, work);
   else
     hipLaunchKernelGGL((hessenberg_kernel<false, R>), dim3(1), dim3(kNT), 0, s, n, A, QT, work);

@@ -6,8 +6,13 @@
 // mode 3 a GEMM with transposed right factor, mode 2 a GEMM batched over r0.
 //
 // Tile: 64 x 64 outputs per 256-thread workgroup, K staged through LDS in
-// steps of 16; each thread owns a 4 x 4 register block at stride 16 so that
-// both the LDS reads and the global writes of a wavefront are contiguous.
+// steps of 16 (the next step prefetched into registers during the current
+// one); each thread owns a 4 x 4 register block at stride 16 so that both
+// the LDS reads and the global writes of a wavefront are contiguous.  Most
+// calls of the solver have thin outputs and long reductions (projections
+// onto interfaces, Gram matrices): with fewer than 256 output tiles and
+// K >= 256 the reduction is split into ~128-long slabs summed in a fixed
+// order by a second kernel, so many short workgroups run at once.
 #include "gemm.h"
 
 #include <algorithm>
@@ -94,12 +99,16 @@ gemm_kernel(int opA, int opB, int M, int N, int K, T alpha,
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = AR::zero();
 
-  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+  // the next K tile is fetched into registers while the current one is
+  // multiplied from LDS, so a tile's global latency overlaps the arithmetic
+  constexpr int SA = (BM * BK) / NT, SB = (BN * BK) / NT;
+  const bool ta = (opA == 1 || opA == 2), tb = (opB == 1 || opB == 2);
+  T ra[SA], rb[SB];
+  auto fetch = [&](int k0) {
 #pragma unroll
-    for (int s = 0; s < (BM * BK) / NT; ++s) {
+    for (int s = 0; s < SA; ++s) {
       const int e = tid + NT * s;
       int i, k;
-      const bool ta = (opA == 1 || opA == 2);
       if (!ta) { i = e / BK; k = e % BK; } else { k = e / BM; i = e % BM; }
       const int gi = m0 + i, gk = k0 + k;
       T v = AR::zero();
@@ -107,13 +116,12 @@ gemm_kernel(int opA, int opB, int M, int N, int K, T alpha,
         v = !ta ? A[(long)gi * lda + gk] : A[(long)gk * lda + gi];
         if (opA >= 2) v = AR::conj(v);
       }
-      As[k][i] = v;
+      ra[s] = v;
     }
 #pragma unroll
-    for (int s = 0; s < (BN * BK) / NT; ++s) {
+    for (int s = 0; s < SB; ++s) {
       const int e = tid + NT * s;
       int j, k;
-      const bool tb = (opB == 1 || opB == 2);
       if (!tb) { k = e / BN; j = e % BN; } else { j = e / BK; k = e % BK; }
       const int gj = n0 + j, gk = k0 + k;
       T v = AR::zero();
@@ -121,9 +129,23 @@ gemm_kernel(int opA, int opB, int M, int N, int K, T alpha,
         v = !tb ? B[(long)gk * ldb + gj] : B[(long)gj * ldb + gk];
         if (opB >= 2) v = AR::conj(v);
       }
-      Bs[k][j] = v;
+      rb[s] = v;
+    }
+  };
+  if (kbeg < kend) fetch(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+#pragma unroll
+    for (int s = 0; s < SA; ++s) {
+      const int e = tid + NT * s;
+      if (!ta) As[e % BK][e / BK] = ra[s]; else As[e / BM][e % BM] = ra[s];
+    }
+#pragma unroll
+    for (int s = 0; s < SB; ++s) {
+      const int e = tid + NT * s;
+      if (!tb) Bs[e / BN][e % BN] = rb[s]; else Bs[e % BK][e / BK] = rb[s];
     }
     __syncthreads();
+    if (k0 + BK < kend) fetch(k0 + BK);
 #pragma unroll
     for (int k = 0; k < BK; ++k) {
       T a[4], b[4];
@@ -227,9 +249,10 @@ void gemm(hipStream_t s, Op opA, Op opB, int M, int N, int K, T alpha,
                 elem * ((double)M * K + (double)K * N + (double)M * N * (AR_beta_nonzero(beta) ? 2.0 : 1.0)) * batch,
                 (cplx ? 8.0 : 2.0) * (double)M * N * K * batch);
   const long tiles = (long)((N + BN - 1) / BN) * ((M + BM - 1) / BM);
-  if (batch == 1 && tiles < 96 && K >= 2048) {
-    // few output tiles, long reduction: split K over S workgroup slabs
-    int S = (int)std::min<long>((384 + tiles - 1) / tiles, K / 512);
+  if (batch == 1 && tiles < 256 && K >= 256) {
+    // few output tiles, long reduction: split K into slabs of ~128 (each
+    // workgroup runs a short loop, many run at once), at most ~1024 slabs
+    int S = (int)std::min<long>(K / 128, std::max<long>(2, 1024 / tiles));
     S = std::max(2, std::min(S, 256));
     int kchunk = (K + S - 1) / S;
     kchunk = ((kchunk + BK - 1) / BK) * BK;

@@ -327,6 +327,7 @@ struct Amen {
   std::vector<Eig> eig;
   std::vector<Eig32> eig32;       // mixed precision: FP32 factors per bond
   std::vector<char> ok64;         // eig[pos] holds the factors of the current L[pos]
+  std::vector<char> ok32;         // eig32[pos] holds the FP32 factors of the current L[pos]
   std::vector<char> need64;       // mixed: bond pos needed FP64 factors once, keep them
   bool mixed = false;
   std::vector<int> xr, zr, sr;  // ranks of x, z, f~ per bond
@@ -384,10 +385,12 @@ struct Amen {
   void factor(int pos, int n) {
     if (mixed && !need64[pos]) {
       eig_nonsym(c, n, L[pos], eig32[pos].lam, eig32[pos].V, eig32[pos].Vi);
+      ok32[pos] = 1;
       ok64[pos] = 0;
     } else {
       eig_nonsym(c, n, L[pos], eig[pos].lam, eig[pos].V, eig[pos].Vi);
       ok64[pos] = 1;
+      ok32[pos] = 0;
     }
   }
   void ensure64(int pos, int n) {
@@ -414,6 +417,7 @@ struct Amen {
     c.h2d(eig32[pos].V, &of, 1);
     c.h2d(eig32[pos].Vi, &of, 1);
     ok64[pos] = 1;
+    ok32[pos] = 1;
     c.sync();
   }
 
@@ -522,6 +526,7 @@ struct Amen {
     eig.resize(d + 1);
     eig32.resize(d + 1);
     ok64.assign(d + 1, 0);
+    ok32.assign(d + 1, 0);
     need64.assign(d + 1, 0);
     mixed = (o.precision == 1);
     for (int l = 0; l <= d; ++l) {
@@ -631,7 +636,13 @@ struct Amen {
           // the exact solver's factors (FP64, or FP32 in mixed precision
           // with a switch to FP64 factors when they contract too slowly)
           ++rep.local_systems;
-          bool use64 = !mixed || (ok64[l] && ok64[l + 1]);
+          // FP32 corrections need current FP32 factors on both sides; a bond
+          // that keeps FP64 factors makes its neighbours' systems FP64 too
+          bool use64 = !mixed || !(ok32[l] && ok32[l + 1]);
+          if (use64) {
+            ensure64(l, r1);
+            ensure64(l + 1, r2);
+          }
           double prev = rn;
           for (int it = 0, it32 = 0, it64 = 0; it < 14; ++it) {
             if (use64) {
