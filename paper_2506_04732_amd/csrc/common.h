@@ -24,7 +24,8 @@ bool timing_enabled();
 struct TimedScope {
   hipStream_t s;
   bool on;
-  TimedScope(hipStream_t s_, int cls, double bytes, double flops) : s(s_), on(timing_enabled()) {
+  TimedScope(hipStream_t s_, int cls, double bytes, double flops, bool enable = true)
+      : s(s_), on(enable && timing_enabled()) {
     if (on) timing_record_begin(s, cls, bytes, flops);
   }
   ~TimedScope() {

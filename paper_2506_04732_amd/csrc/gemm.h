@@ -12,6 +12,6 @@ enum Op { OpN = 0, OpT = 1, OpC = 2, OpR = 3 };  // R: conjugate, no transpose
 template <class T>
 void gemm(hipStream_t s, Op opA, Op opB, int M, int N, int K, T alpha,
           const T* A, long lda, long strideA, const T* B, long ldb, long strideB,
-          T beta, T* C, long ldc, long strideC, int batch);
+          T beta, T* C, long ldc, long strideC, int batch, bool timed = true);
 
 }  // namespace t2s2

@@ -237,7 +237,7 @@ template <> float2 zero_of<float2>() { return make_float2(0.0f, 0.0f); }
 template <class T>
 void gemm(hipStream_t s, Op opA, Op opB, int M, int N, int K, T alpha,
           const T* A, long lda, long strideA, const T* B, long ldb, long strideB,
-          T beta, T* C, long ldc, long strideC, int batch) {
+          T beta, T* C, long ldc, long strideC, int batch, bool timed) {
   if (M <= 0 || N <= 0 || batch <= 0) return;
   if (K <= 0) {
     // C = beta C; K = 0 never occurs in the solver, reject rather than guess
@@ -247,7 +247,7 @@ void gemm(hipStream_t s, Op opA, Op opB, int M, int N, int K, T alpha,
   const double elem = (double)sizeof(T);
   TimedScope ts(s, cplx ? KC_GEMM_C : KC_GEMM,
                 elem * ((double)M * K + (double)K * N + (double)M * N * (AR_beta_nonzero(beta) ? 2.0 : 1.0)) * batch,
-                (cplx ? 8.0 : 2.0) * (double)M * N * K * batch);
+                (cplx ? 8.0 : 2.0) * (double)M * N * K * batch, timed);
   const long tiles = (long)((N + BN - 1) / BN) * ((M + BM - 1) / BM);
   if (batch == 1 && tiles < 256 && K >= 256) {
     // few output tiles, long reduction: split K into slabs of ~128 (each
@@ -275,12 +275,12 @@ void gemm(hipStream_t s, Op opA, Op opB, int M, int N, int K, T alpha,
 }
 
 template void gemm<double>(hipStream_t, Op, Op, int, int, int, double, const double*, long, long,
-                           const double*, long, long, double, double*, long, long, int);
+                           const double*, long, long, double, double*, long, long, int, bool);
 template void gemm<double2>(hipStream_t, Op, Op, int, int, int, double2, const double2*, long, long,
-                            const double2*, long, long, double2, double2*, long, long, int);
+                            const double2*, long, long, double2, double2*, long, long, int, bool);
 template void gemm<float>(hipStream_t, Op, Op, int, int, int, float, const float*, long, long,
-                          const float*, long, long, float, float*, long, long, int);
+                          const float*, long, long, float, float*, long, long, int, bool);
 template void gemm<float2>(hipStream_t, Op, Op, int, int, int, float2, const float2*, long, long,
-                           const float2*, long, long, float2, float2*, long, long, int);
+                           const float2*, long, long, float2, float2*, long, long, int, bool);
 
 }  // namespace t2s2

@@ -198,6 +198,45 @@ Problem* problem_create(int d, const int* N, double eps, const double* beta, int
 }
 
 // =============================================================== TT ops
+// Device buffer for the permuted operator core (one per host thread, grown
+// on demand; the calls of one thread share its stream order).
+namespace {
+struct CoreWork {
+  double* p = nullptr;
+  size_t count = 0;
+  ~CoreWork() {
+    if (p) (void)hipFree(p);
+  }
+  double* get(size_t n) {
+    if (n > count) {
+      if (p) T2S2_HIP(hipFree(p));
+      p = nullptr;
+      count = 0;
+      T2S2_HIP(hipMalloc(&p, n * sizeof(double)));
+      count = n;
+    }
+    return p;
+  }
+};
+thread_local CoreWork g_core;
+}  // namespace
+
+// Core product Y[(a, p), i', (b, q)] = sum_i A[a, i', i, b] X[p, i, q] as, for
+// each a, a GEMM batched over p: Y_p[(i', b), q] = Ahat_a[(i', b), i] X_p[i, q]
+// (rows (i', b) of the output are contiguous with stride r1).
+static void core_product(const Ctx& c, int R0, int R1, int n, int r0, int r1, const double* A, const double* X,
+                         double* Y) {
+  const long asz = (long)R0 * n * n * R1;
+  TimedScope ts(c.s, KC_TTMV, 8.0 * ((double)r0 * n * r1 + (double)asz + (double)R0 * r0 * n * R1 * r1),
+                2.0 * (double)R0 * R1 * n * n * r0 * r1);
+  double* Ah = g_core.get((size_t)asz);
+  ttm_permute(c.s, R0, R1, n, A, Ah);
+  const long co = (long)R1 * r1;
+  for (int a = 0; a < R0; ++a)
+    gemm<double>(c.s, OpN, OpN, n * R1, r1, n, 1.0, Ah + (long)a * n * R1 * n, n, 0, X, r1, (long)n * r1, 0.0,
+                 Y + (long)a * r0 * n * co, r1, (long)n * co, r0, false);
+}
+
 void tt_matvec(const Ctx& c, const DTTM& A, const DTT& x, DTT& y) {
   T2S2_CHECK(A.d == x.d, "tt_matvec: dimension mismatch");
   y.d = x.d;
@@ -206,7 +245,7 @@ void tt_matvec(const Ctx& c, const DTTM& A, const DTT& x, DTT& y) {
   for (int l = 0; l <= x.d; ++l) y.r[l] = A.R[l] * x.r[l];
   for (int l = 0; l < x.d; ++l) {
     T2S2_CHECK(A.n[l] == x.n[l], "tt_matvec: mode size mismatch");
-    ttm_matvec_core(c.s, A.R[l], A.R[l + 1], x.n[l], x.r[l], x.r[l + 1], A.c[l], x.c[l], y.c[l]);
+    core_product(c, A.R[l], A.R[l + 1], x.n[l], x.r[l], x.r[l + 1], A.c[l], x.c[l], y.c[l]);
   }
 }
 

@@ -8,12 +8,9 @@ namespace t2s2 {
 
 constexpr int kDotBlocks = 512;  // partial-sum slots needed by dot_device
 
-// Core of y = A x for one TT core: Y[(a r0 + p), i', (b r1 + q)] =
-// sum_i A[a, i', i, b] X[p, i, q]; A is [R0][n][n][R1], X [r0][n][r1],
-// Y [R0 r0][n][R1 r1].  n <= 64.
-void ttm_matvec_core(hipStream_t s, int R0, int R1, int n, int r0, int r1,
-                     const double* A, const double* X, double* Y);
-
+// Ahat[a][(i' R1 + b) n + i] = A[a][i'][i][b] (operator core as R0 matrices
+// of (n R1) x n, row-major).
+void ttm_permute(hipStream_t s, int R0, int R1, int n, const double* A, double* Ahat);
 void fill(hipStream_t s, double* x, long n, double v);
 void fill(hipStream_t s, double2* x, long n, double2 v);
 // dst[r * ldd + c] = alpha src[r * lds + c], batched with strides ss / sd.

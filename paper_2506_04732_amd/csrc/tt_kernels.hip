@@ -14,48 +14,19 @@ inline int grid_for(long n, int per_block = kBlock, int cap = 8192) {
   return (int)g;
 }
 
-// ---------------------------------------------------------------- TT-matvec
-// Y[(a*r0 + p), i', (b*r1 + q)] = sum_i A[a, i', i, b] X[p, i, q].
-// One workgroup per (p, 64-wide tile of q): the X slab X[p, :, q-tile] is
-// read once (coalesced along q), the operator core sits in LDS, and every
-// output row Y[(a,p), i', (b, q-tile)] is written once, coalesced along q.
-constexpr int kMvQ = 64;
-constexpr int kMvGroups = 4;
-constexpr long kMvLdsA = 8192;  // doubles of operator core kept in LDS (64 KB)
-
-template <int MAXN>
-__global__ void __launch_bounds__(kMvQ * kMvGroups)
-ttm_matvec_kernel(int R0, int R1, int n, int r0, int r1,
-                  const double* __restrict__ A, const double* __restrict__ X,
-                  double* __restrict__ Y) {
-  extern __shared__ double As[];
-  const int p = blockIdx.y;
-  const int lane = threadIdx.x % kMvQ, grp = threadIdx.x / kMvQ;
-  const int q = blockIdx.x * kMvQ + lane;
-  const long asz = (long)R0 * n * n * R1;
-  const bool a_in_lds = asz <= kMvLdsA;
-  if (a_in_lds)
-    for (long e = threadIdx.x; e < asz; e += blockDim.x) As[e] = A[e];
-  __syncthreads();
-  if (q >= r1) return;
-  // the thread's column X[p, :, q] in registers (coalesced across lanes)
-  double x[MAXN];
-#pragma unroll
-  for (int i = 0; i < MAXN; ++i) x[i] = (i < n) ? X[((long)p * n + i) * r1 + q] : 0.0;
-  const double* Ab = a_in_lds ? As : A;
-  const long co = (long)R1 * r1;
-  for (int ip = grp; ip < n; ip += kMvGroups) {
-    for (int a = 0; a < R0; ++a) {
-      for (int b = 0; b < R1; ++b) {
-        // A[a, ip, i, b] at ((a*n + ip)*n + i)*R1 + b
-        const double* arow = Ab + ((long)(a * n + ip) * n) * R1 + b;
-        double acc = 0.0;
-#pragma unroll
-        for (int i = 0; i < MAXN; ++i)
-          if (i < n) acc = fma(arow[(long)i * R1], x[i], acc);
-        Y[((long)(a * r0 + p) * n + ip) * co + (long)b * r1 + q] = acc;
-      }
-    }
+// Ahat[a][(ip * R1 + b) * n + i] = A[a][ip][i][b]: the operator core as R0
+// row-major (n R1) x n matrices, the left factors of the GEMM form of the
+// core product
+__global__ void ttm_permute_kernel(int R0, int R1, int n, const double* __restrict__ A, double* __restrict__ Ah) {
+  const long tot = (long)R0 * n * n * R1;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
+    const int b = (int)(e % R1);
+    const long t = e / R1;
+    const int i = (int)(t % n);
+    const long t2 = t / n;
+    const int ip = (int)(t2 % n);
+    const int a = (int)(t2 / n);
+    Ah[(long)a * n * R1 * n + ((long)ip * R1 + b) * n + i] = A[e];
   }
 }
 
@@ -262,20 +233,9 @@ __global__ void fill_random_kernel(double* x, long n, unsigned long long seed) {
 }  // namespace
 
 // ======================================================== host launchers
-void ttm_matvec_core(hipStream_t s, int R0, int R1, int n, int r0, int r1,
-                     const double* A, const double* X, double* Y) {
-  T2S2_CHECK(n >= 1 && n <= 64, "ttm_matvec_core: mode size must be in [1, 64]");
-  T2S2_CHECK(r0 >= 1 && r1 >= 1 && R0 >= 1 && R1 >= 1, "ttm_matvec_core: ranks must be >= 1");
-  dim3 grid((r1 + kMvQ - 1) / kMvQ, r0);
-  const long asz = (long)R0 * n * n * R1;
-  // algorithmic traffic: read X and the operator core once, write Y once
-  TimedScope ts(s, KC_TTMV, 8.0 * ((double)r0 * n * r1 + (double)asz + (double)R0 * r0 * n * R1 * r1),
-                2.0 * (double)R0 * R1 * n * n * r0 * r1);
-  const size_t lds = asz <= kMvLdsA ? asz * sizeof(double) : 0;
-  if (n <= 32)
-    hipLaunchKernelGGL(ttm_matvec_kernel<32>, grid, dim3(kMvQ * kMvGroups), lds, s, R0, R1, n, r0, r1, A, X, Y);
-  else
-    hipLaunchKernelGGL(ttm_matvec_kernel<64>, grid, dim3(kMvQ * kMvGroups), lds, s, R0, R1, n, r0, r1, A, X, Y);
+void ttm_permute(hipStream_t s, int R0, int R1, int n, const double* A, double* Ahat) {
+  const long tot = (long)R0 * n * n * R1;
+  hipLaunchKernelGGL(ttm_permute_kernel, dim3(grid_for(tot)), dim3(kBlock), 0, s, R0, R1, n, A, Ahat);
   T2S2_LAUNCH_CHECK();
 }
 
