@@ -110,6 +110,10 @@ def bench_batched(args, rank: int):
     """256 uneven instances (d in {4,5,6}, N_l in [16,48], eps in [1e-4,1e-1]),
     each solved to residual 1e-8 under rank cap 128, `workers` at a time on
     concurrent streams.  value = seconds for the whole batch."""
+    # HIP maps a process's streams onto this many hardware queues (4 by
+    # default); concurrent instances need one each to overlap.  Set before
+    # the runtime starts (torch is imported below); 16 <= the 32 allowed.
+    os.environ["GPU_MAX_HW_QUEUES"] = str(min(32, max(4, args.workers)))
     import numpy as np
     import torch
     import paper_2506_04732_amd as t2s2
@@ -149,7 +153,8 @@ def bench_batched(args, rank: int):
         "ms_per_step": sec * 1e3, "higher_is_better": False, "scaling": "strong", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": "batched256_d4-6_N16-48_eps1e-4-1e-1_gauss4", "instances": len(insts),
-                   "workers": args.workers, "rank_cap": cap, **{k: v for k, v in BATCH_OPTS.items()}},
+                   "workers": args.workers, "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4")),
+                   "rank_cap": cap, **{k: v for k, v in BATCH_OPTS.items()}},
         "instances_per_s": len(insts) / sec,
         "converged": conv,
         "max_rank_p50": float(np.median([max(r.ranks) for r in res])),
@@ -258,7 +263,7 @@ def main():
     ap.add_argument("--train", type=int, default=1024, help="warm7d: training instances")
     ap.add_argument("--test", type=int, default=32, help="warm7d: held-out instances")
     ap.add_argument("--epochs", type=int, default=200, help="warm7d: training epochs")
-    ap.add_argument("--workers", type=int, default=8, help="batched256: concurrent instances")
+    ap.add_argument("--workers", type=int, default=16, help="batched256 / warm7d: concurrent instances")
     ap.add_argument("--seq-baseline", action="store_true",
                     help="batched256: also time the 256 instances solved one after another")
     ap.add_argument("--copy-probe", action="store_true",
