@@ -123,7 +123,7 @@ def bench_batched(args, rank: int):
     insts = workloads.batched_instances(256)
     cap = insts[0].rank_cap
     probs = [t2s2.Problem(q.d, q.N, q.eps, q.beta, q.scheme, rank_cap=cap) for q in insts]
-    fs = [sources.source_tt(p, sources.gaussian_factors(p, q.gauss.amp, q.gauss.centre, q.gauss.width))
+    fs = [sources.gaussians(p, q.gauss.amp, q.gauss.centre, q.gauss.width)
           for p, q in zip(probs, insts)]
     outs = [TT.empty(p.m, cap) for p in probs]
     for _ in range(args.warmup):
@@ -185,7 +185,7 @@ def bench_warm(args, rank: int):
     t0 = time.perf_counter()
     insts = [workloads.warm_instance(10 ** 6 + i) for i in range(ntr + nte)]
     probs = [t2s2.Problem(q.d, q.N, q.eps, q.beta, q.scheme, rank_cap=cap) for q in insts]
-    fs = [sources.source_tt(p, sources.gaussian_factors(p, q.gauss.amp, q.gauss.centre, q.gauss.width))
+    fs = [sources.gaussians(p, q.gauss.amp, q.gauss.centre, q.gauss.width)
           for p, q in zip(probs, insts)]
     res = []
     for k in range(0, len(probs), 64):
@@ -296,7 +296,7 @@ def main():
 
     prob = workloads.steady_6d(0, 32)
     p = t2s2.Problem(prob.d, prob.N, prob.eps, prob.beta, prob.scheme, rank_cap=RANK_CAP)
-    f = sources.source_tt(p, sources.gaussian_factors(p, prob.gauss.amp, prob.gauss.centre, prob.gauss.width))
+    f = sources.gaussians(p, prob.gauss.amp, prob.gauss.centre, prob.gauss.width)
     x = TT.empty(p.m, RANK_CAP)
     torch.cuda.synchronize()
     for _ in range(args.warmup):

@@ -202,6 +202,22 @@ int t2s2_tt_residual_norm(t2s2_problem* p, const t2s2_tt* x, const t2s2_tt* f,
  * Synchronises stream. */
 int t2s2_tt_round(t2s2_problem* p, t2s2_tt* x, double tol, int rmax, void* stream);
 
+/* ------------------------------------------------------------- sources ---
+ * Separable right-hand sides sampled on the problem's collocation grid
+ * (paper: the source enters the solve as a TT, Methods; a sum of s
+ * separable terms has exact TT rank s with block-diagonal cores).  f_out's
+ * cores are caller-owned device buffers for ranks (1, s, ..., s, 1) (d = 1:
+ * one core, the sum); its ranks are written.  Host parameter arrays.
+ * Synchronises stream. */
+/* f(x) = sum_{t<s} amp[t] prod_l exp(-(x_l - centre[t*d + l])^2 / (2 width[t]^2)).
+ * EINVAL: s outside [1, 1024], non-finite values, width <= 0. */
+int t2s2_source_gaussians(t2s2_problem* p, int s, const double* amp,
+                          const double* centre, const double* width,
+                          t2s2_tt* f_out, void* stream);
+/* The source of the manufactured solution u = prod_l sin(pi x_l) exp(x_l):
+ * f = sum_l (-eps u_l'' + beta_l u_l')(x_l) prod_{k != l} u_k(x_k), rank d. */
+int t2s2_source_manufactured(t2s2_problem* p, t2s2_tt* f_out, void* stream);
+
 /* ---------------------------------------------------------------- solve ---
  * Solve L x = f in TT format by alternating sweeps with exact local solves
  * and residual enrichment (the paper cites AMEn for this step).

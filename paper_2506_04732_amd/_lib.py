@@ -19,7 +19,7 @@ EXPORTED = [
     "t2s2_timing_enable", "t2s2_timing_read", "t2s2_timing_class_name",
     "t2s2_mlp_create", "t2s2_mlp_destroy", "t2s2_mlp_param_count", "t2s2_mlp_get_params", "t2s2_mlp_set_params",
     "t2s2_mlp_forward", "t2s2_mlp_backward", "t2s2_mlp_adam_step", "t2s2_mlp_infer_bf16", "t2s2_mlp_train",
-    "t2s2_tt_fit_loss", "t2s2_tt_pack", "t2s2_tt_unpack",
+    "t2s2_tt_fit_loss", "t2s2_tt_pack", "t2s2_tt_unpack", "t2s2_source_gaussians", "t2s2_source_manufactured",
 ]
 TIMING_CLASSES = ["gemm_f64", "gemm_c128", "ttm_matvec", "schur_qr", "hessenberg", "jacobi_svd", "cholesky",
                   "trtri", "trevec", "kron_trisolve", "other"]
@@ -104,6 +104,8 @@ def lib() -> C.CDLL:
     L.t2s2_tt_fit_loss.argtypes = [C.c_int, C.c_int, ip, C.c_int, vp, vp, vp, vp, vp]
     L.t2s2_tt_pack.argtypes = [C.POINTER(TTStruct), C.c_int, C.c_int, vp, vp]
     L.t2s2_tt_unpack.argtypes = [C.c_int, ip, C.c_int, vp, C.POINTER(TTStruct), vp]
+    L.t2s2_source_gaussians.argtypes = [vp, C.c_int, dp, dp, dp, C.POINTER(TTStruct), vp]
+    L.t2s2_source_manufactured.argtypes = [vp, C.POINTER(TTStruct), vp]
     L.t2s2_default_options.argtypes = [C.POINTER(Options)]
     L.t2s2_default_options.restype = None
     L.t2s2_timing_enable.argtypes = [C.c_int]

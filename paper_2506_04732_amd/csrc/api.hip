@@ -13,6 +13,7 @@
 
 #include "mlp.h"
 #include "solver.h"
+#include "sources.h"
 #include "spectral_host.h"
 
 struct t2s2_mlp {
@@ -402,6 +403,32 @@ int t2s2_solve_batched(int count, t2s2_problem* const* probs, const t2s2_tt* con
       }
     if (worst != T2S2_OK) t2s2::set_last_error(first);
     return worst;
+  });
+}
+
+// ------------------------------------------------------- sources
+static int source_common(t2s2_problem* p, int kind, int s, const double* amp, const double* centre,
+                         const double* width, t2s2_tt* f_out, void* stream) {
+  T2S2_CHECK(p && f_out && f_out->cores && f_out->ranks && f_out->d == p->P->d, "invalid problem or output TT");
+  if (kind == 0) T2S2_CHECK(amp && centre && width, "NULL parameter array");
+  t2s2::DTT fd;
+  fd.c.assign(f_out->cores, f_out->cores + f_out->d);
+  t2s2::Ctx c = ctx_for(p, stream);
+  t2s2::separable_source(*p->P, c, kind, s, amp, centre, width, fd);
+  for (int l = 0; l <= fd.d; ++l) f_out->ranks[l] = fd.r[l];
+  c.sync();
+  return T2S2_OK;
+}
+
+int t2s2_source_gaussians(t2s2_problem* p, int s, const double* amp, const double* centre, const double* width,
+                          t2s2_tt* f_out, void* stream) {
+  return guarded([&] { return source_common(p, 0, s, amp, centre, width, f_out, stream); });
+}
+
+int t2s2_source_manufactured(t2s2_problem* p, t2s2_tt* f_out, void* stream) {
+  return guarded([&] {
+    T2S2_CHECK(p, "NULL problem");
+    return source_common(p, 1, p->P->d, nullptr, nullptr, nullptr, f_out, stream);
   });
 }
 

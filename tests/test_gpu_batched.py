@@ -34,7 +34,7 @@ def _small_instances():
 
 def _gpu(prob, cap):
     p = t2s2.Problem(prob.d, prob.N, prob.eps, prob.beta, prob.scheme, rank_cap=cap)
-    f = sources.source_tt(p, sources.gaussian_factors(p, prob.gauss.amp, prob.gauss.centre, prob.gauss.width))
+    f = sources.gaussians(p, prob.gauss.amp, prob.gauss.centre, prob.gauss.width)
     return p, f
 
 

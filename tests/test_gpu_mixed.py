@@ -28,8 +28,7 @@ def _say(*a):
 
 def _setup(prob, cap=None):
     p = t2s2.Problem(prob.d, prob.N, prob.eps, prob.beta, prob.scheme, rank_cap=cap or prob.rank_cap)
-    fac = sources.gaussian_factors(p, prob.gauss.amp, prob.gauss.centre, prob.gauss.width)
-    f = sources.source_tt(p, fac)
+    f = sources.gaussians(p, prob.gauss.amp, prob.gauss.centre, prob.gauss.width)
     ops = col.build_ops(prob.d, prob.N, prob.eps, prob.beta, prob.scheme)
     Es, Ms = col.interior_factors(ops)
     terms = col.gauss_rhs_factors(ops, prob.gauss.amp, prob.gauss.centre, prob.gauss.width)

@@ -143,7 +143,7 @@ def test_warm_judge_rejects_bad_start_and_keeps_good_one():
     prob = workloads.gauss_problem(3, 12, 5e-3, 3, seed=9, tol=1e-12, rank_cap=24)
     _say("warm judge", prob.name)
     p = t2s2.Problem(prob.d, prob.N, prob.eps, prob.beta, prob.scheme, rank_cap=24)
-    f = sources.source_tt(p, sources.gaussian_factors(p, prob.gauss.amp, prob.gauss.centre, prob.gauss.width))
+    f = sources.gaussians(p, prob.gauss.amp, prob.gauss.centre, prob.gauss.width)
     cold = p.solve(f, tol=1e-12, target=1e-11, max_sweeps=20)
     assert cold.converged
     rng = np.random.default_rng(10)
@@ -169,7 +169,7 @@ def test_learned_warm_start_end_to_end_reduced():
     opts = dict(tol=1e-10, target=1e-8, max_sweeps=30, kick=8, init_rank=8, check_every=0)
     insts = [workloads.warm_instance(20000 + i, d=d, N=N) for i in range(ntr + nte)]
     probs = [t2s2.Problem(q.d, q.N, q.eps, q.beta, q.scheme, rank_cap=cap) for q in insts]
-    fs = [sources.source_tt(p, sources.gaussian_factors(p, q.gauss.amp, q.gauss.centre, q.gauss.width))
+    fs = [sources.gaussians(p, q.gauss.amp, q.gauss.centre, q.gauss.width)
           for p, q in zip(probs, insts)]
     _say("warm start e2e: solving", len(insts))
     res = []

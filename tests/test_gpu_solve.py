@@ -39,10 +39,8 @@ def _oracle_system(prob):
 
 def _gpu_source(p, prob):
     if prob.source == "sin_exp":
-        fac = sources.sin_exp_factors(p)
-    else:
-        fac = sources.gaussian_factors(p, prob.gauss.amp, prob.gauss.centre, prob.gauss.width)
-    return sources.source_tt(p, fac)
+        return sources.manufactured(p)
+    return sources.gaussians(p, prob.gauss.amp, prob.gauss.centre, prob.gauss.width)
 
 
 def test_2d_manufactured_matches_dense_lu():

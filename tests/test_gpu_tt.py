@@ -126,3 +126,22 @@ def test_round_matches_oracle(tol):
     # same ranks as the oracle's SVD rounding (ties aside) and the same tensor
     assert max(ott.ranks(gr)) <= max(ott.ranks(orr)) + 1
     assert np.linalg.norm(ott.full(gr) - ott.full(orr)) <= 2 * tol * np.linalg.norm(full_y) + 1e-12 * np.linalg.norm(full_y)
+
+
+@pytest.mark.parametrize("d,N", [(1, [20]), (3, [9, 5, 11]), (6, [32] * 6)])
+def test_sources_match_oracle(d, N):
+    """Device-sampled separable sources against the oracle's factors on its own grid."""
+    import workloads
+    from paper_2506_04732_amd import sources
+    _say("sources", d, N)
+    prob = workloads.gauss_problem(d, N, 3e-3, 4, seed=31, tol=1e-10, rank_cap=8)
+    p = t2s2.Problem(d, N, prob.eps, prob.beta, 1, rank_cap=8)
+    ops = col.build_ops(d, N, prob.eps, prob.beta, 1)
+    fg = sources.gaussians(p, prob.gauss.amp, prob.gauss.centre, prob.gauss.width).to_numpy()
+    fo = ott.separable_to_tt(col.gauss_rhs_factors(ops, prob.gauss.amp, prob.gauss.centre, prob.gauss.width))
+    assert ott.rel_diff(fg, fo) <= 1e-13
+    fm = sources.manufactured(p).to_numpy()
+    fmo = ott.separable_to_tt(col.manufactured_rhs_factors(ops, prob.eps, prob.beta))
+    assert ott.rel_diff(fm, fmo) <= 1e-13
+    with pytest.raises(t2s2.T2S2Error):
+        sources.gaussians(p, [1.0], [[0.0] * d], [0.0])
