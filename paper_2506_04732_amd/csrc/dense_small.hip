@@ -19,6 +19,7 @@ namespace {
 constexpr int kNT = 1024;          // threads of the single workgroup
 constexpr long kLdsDoubles = 20000;  // LDS budget of these kernels (160000 B)
 constexpr long kLdsBytes = 160000;
+constexpr int kJacG = 16;            // Jacobi: lanes per row pair
 
 template <class R> struct TinyOf;   // a safe "negligible" magnitude
 template <> struct TinyOf<double> { static constexpr double value = 1e-290; };
@@ -131,21 +132,46 @@ struct TriOps<float2> {
 };
 
 template <class T>
+__device__ inline T shfl_xor_t(T v, int off, int width);
+template <>
+__device__ inline double shfl_xor_t<double>(double v, int off, int width) { return __shfl_xor(v, off, width); }
+template <>
+__device__ inline double2 shfl_xor_t<double2>(double2 v, int off, int width) {
+  return make_double2(__shfl_xor(v.x, off, width), __shfl_xor(v.y, off, width));
+}
+template <>
+__device__ inline float2 shfl_xor_t<float2>(float2 v, int off, int width) {
+  return make_float2(__shfl_xor(v.x, off, width), __shfl_xor(v.y, off, width));
+}
+template <class T>
+__device__ inline T tadd(T a, T b);
+template <>
+__device__ inline double tadd<double>(double a, double b) { return a + b; }
+template <>
+__device__ inline double2 tadd<double2>(double2 a, double2 b) { return cadd(a, b); }
+template <>
+__device__ inline float2 tadd<float2>(float2 a, float2 b) { return cadd(a, b); }
+
+// Each entry's dot product is split over a group of kTriG lanes (strided
+// terms, shuffle reduction), so a row's dependent chain is ~n / kTriG long.
+constexpr int kTriG = 8;
+
+template <class T>
 __global__ void __launch_bounds__(kNT) trtri_upper_kernel(int n, const T* __restrict__ R, T* __restrict__ Rinv) {
   using O = TriOps<T>;
   const long nn = (long)n * n;
+  const int grp = threadIdx.x / kTriG, sub = threadIdx.x % kTriG, ngrp = blockDim.x / kTriG;
   for (long e = threadIdx.x; e < nn; e += blockDim.x) Rinv[e] = O::zero();
   __syncthreads();
   for (int i = n - 1; i >= 0; --i) {
     const T rii = R[(long)i * n + i];
-    for (int j = i + threadIdx.x; j < n; j += blockDim.x) {
-      if (j == i) {
-        Rinv[(long)i * n + i] = O::div(O::one(), rii);
-      } else {
-        T s = O::zero();
-        for (int t = i + 1; t <= j; ++t) s = O::fma(R[(long)i * n + t], Rinv[(long)t * n + j], s);
-        Rinv[(long)i * n + j] = O::div(O::neg(s), rii);
-      }
+    for (int j0 = i; j0 < n; j0 += ngrp) {
+      const int j = j0 + grp;
+      T s = O::zero();
+      if (j < n)
+        for (int t = i + 1 + sub; t <= j; t += kTriG) s = O::fma(R[(long)i * n + t], Rinv[(long)t * n + j], s);
+      for (int off = kTriG / 2; off > 0; off >>= 1) s = tadd<T>(s, shfl_xor_t<T>(s, off, kTriG));
+      if (j < n && sub == 0) Rinv[(long)i * n + j] = (j == i) ? O::div(O::one(), rii) : O::div(O::neg(s), rii);
     }
     __syncthreads();
   }
@@ -157,7 +183,8 @@ __global__ void __launch_bounds__(kNT) trtri_upper_kernel(int n, const T* __rest
 // (Hestenes' method applied to B^T), the rotations accumulate in U.  Rows are
 // then sorted by decreasing norm: sigma[i] = ||Wt[i, :]||, so B = U diag(sigma) V^T
 // with V^T the normalised rows of Wt.  Pairs are visited in round-robin
-// tournament order, k/2 disjoint pairs per round, one wavefront per pair.
+// tournament order, k/2 disjoint pairs per round, one group of kJacG lanes
+// per pair.
 template <int MODE>
 __global__ void __launch_bounds__(kNT) jacobi_rows_kernel(int k, int c, double* __restrict__ B,
                                                           double* __restrict__ JT, double* __restrict__ U,
@@ -175,7 +202,9 @@ __global__ void __launch_bounds__(kNT) jacobi_rows_kernel(int k, int c, double* 
   __syncthreads();
   const int K = k + (k & 1);  // even number of players (k odd: one bye)
   const int npairs = K / 2;
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, nwaves = blockDim.x / 64;
+  // one group of kJacG lanes per pair: a round's pairs are independent, so
+  // many of them are in flight at once
+  const int grp = threadIdx.x / kJacG, sub = threadIdx.x % kJacG, ngrp = blockDim.x / kJacG;
   // rows are rotated until their cosines fall below tol: the factorisation
   // B = U Wt is exact for any tol (U is a product of rotations), so tol only
   // decides how well the energy is compacted into the leading rows
@@ -185,7 +214,7 @@ __global__ void __launch_bounds__(kNT) jacobi_rows_kernel(int k, int c, double* 
     if (threadIdx.x == 0) s_rot = 0;
     __syncthreads();
     for (int round = 0; round < K - 1; ++round) {
-      for (int pi = wave; pi < npairs; pi += nwaves) {
+      for (int pi = grp; pi < npairs; pi += ngrp) {
         // slots pi and K-1-pi; slot 0 is fixed, the others rotate
         const int s1 = pi, s2 = K - 1 - pi;
         int p = (s1 == 0) ? 0 : ((s1 - 1 + round) % (K - 1)) + 1;
@@ -195,34 +224,34 @@ __global__ void __launch_bounds__(kNT) jacobi_rows_kernel(int k, int c, double* 
         double* bp = Bw + (long)p * c;
         double* bq = Bw + (long)q * c;
         double a = 0.0, b = 0.0, g = 0.0;
-        for (int e = lane; e < c; e += 64) {
+        for (int e = sub; e < c; e += kJacG) {
           const double x = bp[e], y = bq[e];
           a = fma(x, x, a);
           b = fma(y, y, b);
           g = fma(x, y, g);
         }
-        for (int off = 32; off > 0; off >>= 1) {
-          a += __shfl_xor(a, off, 64);
-          b += __shfl_xor(b, off, 64);
-          g += __shfl_xor(g, off, 64);
+        for (int off = kJacG / 2; off > 0; off >>= 1) {
+          a += __shfl_xor(a, off, kJacG);
+          b += __shfl_xor(b, off, kJacG);
+          g += __shfl_xor(g, off, kJacG);
         }
         if (g == 0.0 || fabs(g) <= tol * sqrt(a * b)) continue;
         const double zeta = (b - a) / (2.0 * g);
         const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-        for (int e = lane; e < c; e += 64) {
+        for (int e = sub; e < c; e += kJacG) {
           const double x = bp[e], y = bq[e];
           bp[e] = cs * x - sn * y;
           bq[e] = sn * x + cs * y;
         }
         double* jp = Jw + (long)p * k;
         double* jq = Jw + (long)q * k;
-        for (int e = lane; e < k; e += 64) {
+        for (int e = sub; e < k; e += kJacG) {
           const double x = jp[e], y = jq[e];
           jp[e] = cs * x - sn * y;
           jq[e] = sn * x + cs * y;
         }
-        if (lane == 0) atomicAdd(&s_rot, 1);
+        if (sub == 0) atomicAdd(&s_rot, 1);
       }
       __syncthreads();
     }
@@ -406,22 +435,30 @@ template <class R>
 __global__ void __launch_bounds__(kNT) trevec_kernel(int n, const typename CxOf<R>::type* __restrict__ T,
                                                      typename CxOf<R>::type* __restrict__ Y) {
   using CX = CxOf<R>;
+  using C = typename CxOf<R>::type;
   const long nn = (long)n * n;
+  const int grp = threadIdx.x / kTriG, sub = threadIdx.x % kTriG, ngrp = blockDim.x / kTriG;
   for (long e = threadIdx.x; e < nn; e += blockDim.x) {
     const int i = (int)(e / n), j = (int)(e % n);
     Y[e] = (i == j) ? CX::make(R(1.0), R(0.0)) : CX::make(R(0.0), R(0.0));
   }
   __syncthreads();
   for (int i = n - 1; i >= 0; --i) {
-    const auto tii = T[(long)i * n + i];
-    for (int k = i + 1 + threadIdx.x; k < n; k += blockDim.x) {
-      auto s = T[(long)i * n + k];  // times y_k = 1
-      for (int t = i + 1; t < k; ++t) s = cadd(s, cmul(T[(long)i * n + t], Y[(long)t * n + k]));
-      const auto tkk = T[(long)k * n + k];
-      auto den = csub(tii, tkk);
-      const R smin = fmax(EpsOf<R>::value * cabs(tkk), TinyOf<R>::value);
-      if (cabs(den) < smin) den = CX::make(smin, R(0.0));
-      Y[(long)i * n + k] = cdiv(CX::make(-s.x, -s.y), den);
+    const C tii = T[(long)i * n + i];
+    for (int k0 = i + 1; k0 < n; k0 += ngrp) {
+      const int k = k0 + grp;
+      C s = CX::make(R(0.0), R(0.0));
+      if (k < n)
+        for (int t = i + 1 + sub; t < k; t += kTriG) s = cadd(s, cmul(T[(long)i * n + t], Y[(long)t * n + k]));
+      for (int off = kTriG / 2; off > 0; off >>= 1) s = tadd<C>(s, shfl_xor_t<C>(s, off, kTriG));
+      if (k < n && sub == 0) {
+        s = cadd(s, T[(long)i * n + k]);  // times y_k = 1
+        const C tkk = T[(long)k * n + k];
+        C den = csub(tii, tkk);
+        const R smin = fmax(EpsOf<R>::value * cabs(tkk), TinyOf<R>::value);
+        if (cabs(den) < smin) den = CX::make(smin, R(0.0));
+        Y[(long)i * n + k] = cdiv(CX::make(-s.x, -s.y), den);
+      }
     }
     __syncthreads();
   }
