@@ -202,6 +202,27 @@ int t2s2_tt_residual_norm(t2s2_problem* p, const t2s2_tt* x, const t2s2_tt* f,
  * Synchronises stream. */
 int t2s2_tt_round(t2s2_problem* p, t2s2_tt* x, double tol, int rmax, void* stream);
 
+/* Local system of the alternating solver (paper: Results, stabilisation of
+ * convection-dominated problems -- AMEn solves one local problem per TT core,
+ * whose direct solution costs O((r_{l-1} n_l r_l)^3) when formed densely).
+ * For the Kronecker-sum operator the local matrix is itself a Kronecker sum
+ *   B = Lint (+) K (+) Rint,  (B u)[a,i,b] = sum_a' Lint[a][a'] u[a',i,b]
+ *        + sum_i' K[i][i'] u[a,i',b] + sum_b' Rint[b][b'] u[a,i,b'],
+ * on u of shape r1 x m x r2 (row-major), and this entry solves B u = g
+ * without forming B, as the solver's local solves do:
+ *   method 0: eigendecompositions of Lint and Rint, complex Schur form of K,
+ *             triangular solves along the mode index;
+ *   method 1: Hessenberg form of Lint, eigendecomposition of Rint, Schur form
+ *             of K, and per eigenvalue of Rint one Hessenberg-Schur chain
+ *             (requires r1 <= 256 and m * ceil(r1/64) * 1024 <= 160000).
+ * All arrays are FP64 device buffers owned by the caller, row-major: Lint
+ * (r1 x r1), K (m x m), Rint (r2 x r2), g and u (r1 * m * r2); u must not
+ * alias g.  One application in FP64, no refinement.  Sizes: r1, r2 <= 512,
+ * m <= 64.  Returns T2S2_EINVAL for bad sizes or method, and an error if a
+ * factorisation does not converge.  Synchronises stream. */
+int t2s2_local_solve(int r1, int m, int r2, const double* Lint, const double* K, const double* Rint,
+                     const double* g, double* u, int method, void* stream);
+
 /* ------------------------------------------------------------- sources ---
  * Separable right-hand sides sampled on the problem's collocation grid
  * (paper: the source enters the solve as a TT, Methods; a sum of s

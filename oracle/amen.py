@@ -95,6 +95,16 @@ def local_dense(PhiL, A, PhiR):
     return B.reshape(r0 * n * r1, r0 * n * r1)
 
 
+def kron_sum_dense(KL, K, KR):
+    """Dense Kronecker sum KL (+) K (+) KR on u[a, i, b] flattened row-major:
+    the local operator of the scaled (Kronecker-sum) system at one core, with
+    the left and right interfaces KL, KR (Results, stabilisation subsection:
+    one local problem per core).  Plain definition, for small sizes."""
+    r1, m, r2 = KL.shape[0], K.shape[0], KR.shape[0]
+    I1, Im, I2 = np.eye(r1), np.eye(m), np.eye(r2)
+    return np.kron(np.kron(KL, Im), I2) + np.kron(np.kron(I1, K), I2) + np.kron(np.kron(I1, Im), KR)
+
+
 def _split_interface_left(Phi):
     """(L-part, E-part) of a left x-A-x interface; the boundary interface is (0, 1)."""
     if Phi.shape[1] == 1:

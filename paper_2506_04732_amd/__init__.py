@@ -7,7 +7,7 @@ without the built library every entry point raises ``LibraryMissing``.
 
 Names follow the C ABI: ``nodes``, ``matrices_1d``, ``Problem`` (create /
 operator / colloc / tt_matvec / tt_norm / tt_residual_norm / tt_round /
-solve) and ``solve_batched``.
+solve), ``solve_batched`` and ``local_solve``.
 """
 from __future__ import annotations
 
@@ -21,7 +21,8 @@ from . import _lib
 from ._lib import (PRECISION_FP64, PRECISION_MIXED, SCHEME_PLAIN, SCHEME_SC, T2S2_ENOTCONV, LibraryMissing,
                    T2S2Error, check, lib)
 
-__all__ = ["nodes", "matrices_1d", "TT", "Problem", "SolveResult", "solve_batched", "SCHEME_PLAIN", "SCHEME_SC",
+__all__ = ["nodes", "matrices_1d", "TT", "Problem", "SolveResult", "solve_batched", "local_solve", "SCHEME_PLAIN",
+           "SCHEME_SC",
            "PRECISION_FP64", "PRECISION_MIXED",
            "LibraryMissing", "T2S2Error", "lib"]
 
@@ -304,3 +305,24 @@ def solve_batched(problems: Sequence["Problem"], fs: Sequence[TT], *, x0s: Optio
         x._read_ranks()
         out.append(_result(x, code, reps[i], problems[i].d))
     return out
+
+
+LOCAL_EIG, LOCAL_HESS = 0, 1
+
+
+def local_solve(Lint, K, Rint, g, method: int = LOCAL_HESS):
+    """t2s2_local_solve: u = (Lint (+) K (+) Rint)^{-1} g for g of shape
+    (r1, m, r2); all arguments float64 CUDA tensors.  Returns u (new tensor)."""
+    torch = _torch()
+    mats = [Lint, K, Rint, g]
+    for a in mats:
+        if not (isinstance(a, torch.Tensor) and a.is_cuda and a.dtype == torch.float64 and a.is_contiguous()):
+            raise TypeError("local_solve: arguments must be contiguous float64 CUDA tensors")
+    r1, m, r2 = g.shape
+    if Lint.shape != (r1, r1) or K.shape != (m, m) or Rint.shape != (r2, r2):
+        raise ValueError("local_solve: Lint (r1 x r1), K (m x m), Rint (r2 x r2) must match g (r1, m, r2)")
+    u = torch.empty_like(g)
+    check(lib().t2s2_local_solve(r1, m, r2, C.c_void_p(Lint.data_ptr()), C.c_void_p(K.data_ptr()),
+                                 C.c_void_p(Rint.data_ptr()), C.c_void_p(g.data_ptr()), C.c_void_p(u.data_ptr()),
+                                 int(method), _stream()))
+    return u

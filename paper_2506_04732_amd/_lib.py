@@ -15,14 +15,14 @@ MAX_DIM, MAX_HISTORY = 16, 128
 EXPORTED = [
     "t2s2_last_error", "t2s2_nodes", "t2s2_matrices_1d", "t2s2_problem_create", "t2s2_problem_destroy",
     "t2s2_problem_operator", "t2s2_problem_colloc", "t2s2_tt_matvec", "t2s2_tt_norm",
-    "t2s2_tt_residual_norm", "t2s2_tt_round", "t2s2_solve", "t2s2_solve_batched", "t2s2_default_options",
+    "t2s2_tt_residual_norm", "t2s2_tt_round", "t2s2_local_solve", "t2s2_solve", "t2s2_solve_batched", "t2s2_default_options",
     "t2s2_timing_enable", "t2s2_timing_read", "t2s2_timing_class_name",
     "t2s2_mlp_create", "t2s2_mlp_destroy", "t2s2_mlp_param_count", "t2s2_mlp_get_params", "t2s2_mlp_set_params",
     "t2s2_mlp_forward", "t2s2_mlp_backward", "t2s2_mlp_adam_step", "t2s2_mlp_infer_bf16", "t2s2_mlp_train",
     "t2s2_tt_fit_loss", "t2s2_tt_pack", "t2s2_tt_unpack", "t2s2_source_gaussians", "t2s2_source_manufactured",
 ]
 TIMING_CLASSES = ["gemm_f64", "gemm_c128", "ttm_matvec", "schur_qr", "hessenberg", "jacobi_svd", "cholesky",
-                  "trtri", "trevec", "kron_trisolve", "other"]
+                  "trtri", "trevec", "kron_trisolve", "hess_solve", "other"]
 
 
 class TTStruct(C.Structure):
@@ -84,6 +84,7 @@ def lib() -> C.CDLL:
     L.t2s2_tt_norm.argtypes = [vp, C.POINTER(TTStruct), dp, vp]
     L.t2s2_tt_residual_norm.argtypes = [vp, C.POINTER(TTStruct), C.POINTER(TTStruct), dp, vp]
     L.t2s2_tt_round.argtypes = [vp, C.POINTER(TTStruct), C.c_double, C.c_int, vp]
+    L.t2s2_local_solve.argtypes = [C.c_int, C.c_int, C.c_int, vp, vp, vp, vp, vp, C.c_int, vp]
     L.t2s2_solve.argtypes = [vp, C.POINTER(TTStruct), C.POINTER(TTStruct), C.POINTER(Options),
                              C.POINTER(TTStruct), C.POINTER(Report), vp]
     ttp = C.POINTER(TTStruct)

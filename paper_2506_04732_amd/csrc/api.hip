@@ -282,6 +282,19 @@ int t2s2_tt_round(t2s2_problem* p, t2s2_tt* x, double tol, int rmax, void* strea
   });
 }
 
+int t2s2_local_solve(int r1, int m, int r2, const double* Lint, const double* K, const double* Rint, const double* g,
+                     double* u, int method, void* stream) {
+  return guarded([&] {
+    T2S2_CHECK(Lint && K && Rint && g && u, "NULL argument");
+    t2s2::Scratch sc;
+    t2s2::Ctx c;
+    c.s = static_cast<hipStream_t>(stream);
+    c.sc = &sc;
+    t2s2::local_kron_solve(c, r1, m, r2, Lint, K, Rint, g, u, method);
+    return T2S2_OK;
+  });
+}
+
 int t2s2_timing_enable(int on) {
   return guarded([&] {
     t2s2::timing_set(on != 0);
@@ -302,7 +315,7 @@ int t2s2_timing_read(int cls, double* total_ms, long long* launches, double* byt
 
 const char* t2s2_timing_class_name(int cls) {
   static const char* names[] = {"gemm_f64", "gemm_c128", "ttm_matvec", "schur_qr", "hessenberg", "jacobi_svd",
-                                "cholesky", "trtri", "trevec", "kron_trisolve", "other"};
+                                "cholesky", "trtri", "trevec", "kron_trisolve", "hess_solve", "other"};
   if (cls < 0 || cls >= t2s2::KC_COUNT) return "";
   return names[cls];
 }

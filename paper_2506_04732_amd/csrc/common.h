@@ -12,7 +12,7 @@ namespace t2s2 {
 // Kernel classes timed by the optional event instrumentation.
 enum KernelClass {
   KC_GEMM = 0, KC_GEMM_C, KC_TTMV, KC_SCHUR, KC_HESS, KC_JACOBI, KC_CHOL, KC_TRTRI, KC_TREVEC, KC_KRONSOLVE,
-  KC_OTHER, KC_COUNT
+  KC_HESSSOLVE, KC_OTHER, KC_COUNT
 };
 
 // When enabled, every instrumented launch is bracketed by two HIP events on

@@ -76,6 +76,10 @@ double tt_norm(const Ctx& c, const DTT& x);
 double tt_residual_norm(Problem& p, const Ctx& c, const DTT& x, const DTT& f);
 // In-place rounding; x's cores must hold the input ranks.
 void tt_round(const Ctx& c, DTT& x, double tol, int rmax);
+// u = (Lint (+) K (+) Rint)^{-1} g on r1 x m x r2 tensors (device buffers),
+// method 0: eigendecompositions of Lint and Rint, 1: Hessenberg form of Lint.
+void local_kron_solve(const Ctx& c, int r1, int m, int r2, const double* Lint, const double* K, const double* Rint,
+                      const double* g, double* u, int method);
 // TT solve of the interior system; x holds the start (or is random) and
 // receives the solution; its cores need rank_cap * m * rank_cap doubles.
 int solve(Problem& p, const Ctx& c, const DTT& f, const DTT* x0, const SolveOptions& o, DTT& x, SolveReport& rep);

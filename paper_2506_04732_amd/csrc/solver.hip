@@ -23,6 +23,7 @@
 #include <cstdio>
 
 #include "ddnorm.h"
+#include "kron_hess.h"
 #include "spectral_host.h"
 
 namespace t2s2 {
@@ -355,6 +356,55 @@ struct EigT {
 using Eig = EigT<double2>;
 using Eig32 = EigT<float2>;
 
+template <class C>
+inline C cx_zero() {
+  C z;
+  z.x = 0;
+  z.y = 0;
+  return z;
+}
+
+// out = (L (+) K (+) R)^{-1} g on r1 x ml x r2 tensors (real in, real out),
+// L = VL diag(lamL) VL^{-1}, K = Z T Z^H (ZT = Z^T), R = VR diag(lamR) VR^{-1}:
+// mode transforms into the eigen/Schur bases, the triangular Kronecker-sum
+// solve along the mode index, transforms back; w0, w1: complex work of size
+// r1 ml r2
+template <class C>
+void kron_inverse_eig(const Ctx& c, int r1, int ml, int r2, const C* ZT, const C* T, const EigT<C>& eL,
+                      const EigT<C>& eR, const double* g, double* out, C* w0, C* w1) {
+  const long n = (long)r1 * ml * r2;
+  const C z0 = cx_zero<C>();
+  real_to_complex(c.s, g, w0, n);
+  mode3<C>(c, r1, ml, r2, r2, w0, eR.Vi, w1, z0);
+  mode2<C>(c, r1, ml, ml, r2, ZT, w1, w0, z0, OpR);
+  mode1<C>(c, r1, r1, ml, r2, eL.Vi, w0, w1, z0);
+  kron_trisolve(c.s, r1, ml, r2, T, eL.lam, eR.lam, w1);
+  mode1<C>(c, r1, r1, ml, r2, eL.V, w1, w0, z0);
+  mode2<C>(c, r1, ml, ml, r2, ZT, w0, w1, z0, OpT);
+  mode3<C>(c, r1, ml, r2, r2, w1, eR.V, w0, z0);
+  complex_real_part(c.s, w0, out, n);
+}
+
+// The same inverse with L = Q H Q^T (QT = Q^T row-major, Hc = H column-major,
+// H upper Hessenberg): Q^T on the real data, the mode-2/3 transforms, one
+// Hessenberg-Schur chain per right eigenvalue, back again; wr: real work of
+// size r1 ml r2
+template <class C, class R>
+void kron_inverse_hess(const Ctx& c, int r1, int ml, int r2, const C* ZT, const C* T, const double* QT, const R* Hc,
+                       const EigT<C>& eR, const double* g, double* out, C* w0, C* w1, double* wr) {
+  const long n = (long)r1 * ml * r2;
+  const C z0 = cx_zero<C>();
+  mode1<double>(c, r1, r1, ml, r2, QT, g, wr, 0.0);
+  real_to_complex(c.s, wr, w0, n);
+  mode3<C>(c, r1, ml, r2, r2, w0, eR.Vi, w1, z0);
+  mode2<C>(c, r1, ml, ml, r2, ZT, w1, w0, z0, OpR);
+  kron_hess_solve(c.s, r1, ml, r2, Hc, T, eR.lam, w0);
+  mode2<C>(c, r1, ml, ml, r2, ZT, w0, w1, z0, OpT);
+  mode3<C>(c, r1, ml, r2, r2, w1, eR.V, w0, z0);
+  complex_real_part(c.s, w0, wr, n);
+  mode1<double>(c, r1, r1, ml, r2, QT, wr, out, 0.0, OpT);
+}
+
 struct Amen {
   Problem& p;
   const Ctx& c;
@@ -368,6 +418,16 @@ struct Amen {
   std::vector<char> ok64;         // eig[pos] holds the factors of the current L[pos]
   std::vector<char> ok32;         // eig32[pos] holds the FP32 factors of the current L[pos]
   std::vector<char> need64;       // mixed: bond pos needed FP64 factors once, keep them
+  // left interfaces in Hessenberg form L = Q H Q^T: the local solve then
+  // needs no eigendecomposition of L (Hessenberg-Schur chain per right
+  // eigenvalue); QT = Q^T row-major, Hc = H column-major, Hc32 its FP32 copy
+  struct HessF {
+    double* QT = nullptr;
+    double* Hc = nullptr;
+    float* Hc32 = nullptr;
+  };
+  std::vector<HessF> hf;
+  std::vector<char> lhess;        // L[pos] is held as HessF (else as eig / eig32)
   bool mixed = false;
   std::vector<int> xr, zr, sr;  // ranks of x, z, f~ per bond
   std::vector<double*> xc, zc, bc;  // cores
@@ -376,6 +436,7 @@ struct Amen {
   double *u, *f, *res, *y, *T1, *T2, *A1, *S, *kick_buf, *zbuf, *U, *W, *tmp, *Qk, *Rk;
   double2 *h0, *h1;
   float2 *g0, *g1;
+  double* hr;
 
   Amen(Problem& p_, const Ctx& c_, const SolveOptions& o_) : p(p_), c(c_), o(o_) {}
 
@@ -389,39 +450,46 @@ struct Amen {
   }
 
   // out = B^{-1} g for B = L_L (+) K_l (+) L_R via the eigen/Schur factors
+  // out = B^{-1} g for B = L_L (+) K_l (+) L_R with the FP64 factors
   void local_solve(int l, int r1, int r2, const Eig& eL, const Eig& eR, const double* g, double* out) {
-    const int ml = m[l];
-    const long n = (long)r1 * ml * r2;
-    const double2 z0 = make_double2(0.0, 0.0);
-    real_to_complex(c.s, g, h0, n);
-    mode3<double2>(c, r1, ml, r2, r2, h0, eR.Vi, h1, z0);
-    mode2<double2>(c, r1, ml, ml, r2, p.dK_ZT[l], h1, h0, z0, OpR);
-    mode1<double2>(c, r1, r1, ml, r2, eL.Vi, h0, h1, z0);
-    kron_trisolve(c.s, r1, ml, r2, p.dK_T[l], eL.lam, eR.lam, h1);
-    mode1<double2>(c, r1, r1, ml, r2, eL.V, h1, h0, z0);
-    mode2<double2>(c, r1, ml, ml, r2, p.dK_ZT[l], h0, h1, z0, OpT);
-    mode3<double2>(c, r1, ml, r2, r2, h1, eR.V, h0, z0);
-    complex_real_part(c.s, h0, out, n);
+    if (lhess[l])
+      kron_inverse_hess<double2, double>(c, r1, m[l], r2, p.dK_ZT[l], p.dK_T[l], hf[l].QT, hf[l].Hc, eR, g, out, h0,
+                                         h1, hr);
+    else
+      kron_inverse_eig<double2>(c, r1, m[l], r2, p.dK_ZT[l], p.dK_T[l], eL, eR, g, out, h0, h1);
   }
 
-  // same solve with the FP32 factors (FP64 in, FP64 out)
+  // same solve with the FP32 factors (FP64 in, FP64 out; the orthogonal
+  // Hessenberg transform stays FP64)
   void local_solve32(int l, int r1, int r2, const Eig32& eL, const Eig32& eR, const double* g, double* out) {
-    const int ml = m[l];
-    const long n = (long)r1 * ml * r2;
-    const float2 z0 = make_float2(0.0f, 0.0f);
-    real_to_complex(c.s, g, g0, n);
-    mode3<float2>(c, r1, ml, r2, r2, g0, eR.Vi, g1, z0);
-    mode2<float2>(c, r1, ml, ml, r2, p.dK_ZT32[l], g1, g0, z0, OpR);
-    mode1<float2>(c, r1, r1, ml, r2, eL.Vi, g0, g1, z0);
-    kron_trisolve(c.s, r1, ml, r2, p.dK_T32[l], eL.lam, eR.lam, g1);
-    mode1<float2>(c, r1, r1, ml, r2, eL.V, g1, g0, z0);
-    mode2<float2>(c, r1, ml, ml, r2, p.dK_ZT32[l], g0, g1, z0, OpT);
-    mode3<float2>(c, r1, ml, r2, r2, g1, eR.V, g0, z0);
-    complex_real_part(c.s, g0, out, n);
+    if (lhess[l])
+      kron_inverse_hess<float2, float>(c, r1, m[l], r2, p.dK_ZT32[l], p.dK_T32[l], hf[l].QT, hf[l].Hc32, eR, g, out,
+                                       g0, g1, hr);
+    else
+      kron_inverse_eig<float2>(c, r1, m[l], r2, p.dK_ZT32[l], p.dK_T32[l], eL, eR, g, out, g0, g1);
+  }
+
+  // factorise a left interface at bond pos (size n): Hessenberg form when the
+  // chain kernel supports the local system of site pos, else as factor()
+  void factor_left(int pos, int n) {
+    if (!(pos < d && kron_hess_fits(n, m[pos], (int)sizeof(double2)))) {
+      factor(pos, n);
+      return;
+    }
+    double* Hw = buf("hess.H", (size_t)n * n);
+    double* work = buf("hess.work", 2 * (size_t)n);
+    c.d2d(Hw, L[pos], (size_t)n * n);
+    hessenberg(c.s, n, Hw, hf[pos].QT, work);
+    transpose(c.s, n, n, Hw, n, hf[pos].Hc, n);
+    if (mixed) to_float(c.s, hf[pos].Hc, hf[pos].Hc32, (long)n * n);
+    lhess[pos] = 1;
+    ok64[pos] = 1;
+    ok32[pos] = 1;
   }
 
   // factorise the interface at bond pos (size n) in the working precision
   void factor(int pos, int n) {
+    lhess[pos] = 0;
     if (mixed && !need64[pos]) {
       eig_nonsym(c, n, L[pos], eig32[pos].lam, eig32[pos].V, eig32[pos].Vi);
       ok32[pos] = 1;
@@ -433,7 +501,7 @@ struct Amen {
     }
   }
   void ensure64(int pos, int n) {
-    if (!ok64[pos]) {
+    if (!lhess[pos] && !ok64[pos]) {
       eig_nonsym(c, n, L[pos], eig[pos].lam, eig[pos].V, eig[pos].Vi);
       ok64[pos] = 1;
     }
@@ -457,6 +525,15 @@ struct Amen {
     c.h2d(eig32[pos].Vi, &of, 1);
     ok64[pos] = 1;
     ok32[pos] = 1;
+    // left boundary: also as a (trivial) Hessenberg factor H = 0, Q = 1
+    lhess[pos] = 0;
+    if (pos == 0 && kron_hess_fits(1, m[0], (int)sizeof(double2))) {
+      const float zf1 = 0.0f;
+      c.h2d(hf[pos].QT, &one, 1);
+      c.h2d(hf[pos].Hc, &zero, 1);
+      c.h2d(hf[pos].Hc32, &zf1, 1);
+      lhess[pos] = 1;
+    }
     c.sync();
   }
 
@@ -482,7 +559,7 @@ struct Amen {
     // ZB' = Z^T (ZB x1 b)
     mode1<double>(c, q0, s0, ml, s1, ZB[l], bc[l], T1, 0.0);
     gemm<double>(c.s, OpT, OpN, q1, s1, q0 * ml, 1.0, Z, q1, 0, T1, s1, 0, 0.0, ZB[l + 1], s1, 0, 1);
-    factor(l + 1, r1);
+    factor_left(l + 1, r1);
   }
 
   // right interfaces at pos l from pos l+1 and cores x_l, z_l
@@ -567,6 +644,8 @@ struct Amen {
     ok64.assign(d + 1, 0);
     ok32.assign(d + 1, 0);
     need64.assign(d + 1, 0);
+    hf.resize(d + 1);
+    lhess.assign(d + 1, 0);
     mixed = (o.precision == 1);
     for (int l = 0; l <= d; ++l) {
       const std::string t = std::to_string(l);
@@ -581,6 +660,9 @@ struct Amen {
       eig32[l].lam = c.sc->get<float2>("am.lam32" + t, cap);
       eig32[l].V = c.sc->get<float2>("am.V32" + t, (size_t)cap * cap);
       eig32[l].Vi = c.sc->get<float2>("am.Vi32" + t, (size_t)cap * cap);
+      hf[l].QT = buf("QT" + t, (size_t)cap * cap);
+      hf[l].Hc = buf("Hc" + t, (size_t)cap * cap);
+      hf[l].Hc32 = c.sc->get<float>("am.Hc32" + t, (size_t)cap * cap);
     }
     u = buf("u", big);
     f = buf("f", big);
@@ -601,6 +683,7 @@ struct Amen {
     h1 = c.sc->get<double2>("am.h1", big);
     g0 = c.sc->get<float2>("am.g0", big);
     g1 = c.sc->get<float2>("am.g1", big);
+    hr = buf("hr", big);
     if (x0 && o.warm_judge) {
       // the given start is kept only if its FP64 residual beats that of the
       // seeded random start a cold solve would use (the fallback)
@@ -899,6 +982,46 @@ struct Amen {
 };
 
 }  // namespace
+
+void local_kron_solve(const Ctx& c, int r1, int m, int r2, const double* Lint, const double* K, const double* Rint,
+                      const double* g, double* u, int method) {
+  T2S2_CHECK(r1 >= 1 && m >= 1 && r2 >= 1, "local_solve: sizes must be positive");
+  T2S2_CHECK(r1 <= 512 && r2 <= 512 && m <= 64, "local_solve: r1, r2 <= 512 and m <= 64 required");
+  T2S2_CHECK(method == 0 || method == 1, "local_solve: method must be 0 (eigen) or 1 (Hessenberg)");
+  T2S2_CHECK(method == 0 || kron_hess_fits(r1, m, (int)sizeof(double2)),
+             "local_solve: method 1 needs r1 <= 256 and the m right-hand sides of a chain in LDS");
+  Scratch& S = *c.sc;
+  const long n = (long)r1 * m * r2;
+  double2* ZT = S.get<double2>("loc.ZT", (size_t)m * m);
+  double2* T = S.get<double2>("loc.T", (size_t)m * m);
+  schur_real(c, m, K, ZT, T);
+  Eig eR;
+  eR.lam = S.get<double2>("loc.lamR", r2);
+  eR.V = S.get<double2>("loc.VR", (size_t)r2 * r2);
+  eR.Vi = S.get<double2>("loc.ViR", (size_t)r2 * r2);
+  eig_nonsym(c, r2, Rint, eR.lam, eR.V, eR.Vi);
+  double2* w0 = S.get<double2>("loc.w0", n);
+  double2* w1 = S.get<double2>("loc.w1", n);
+  if (method == 0) {
+    Eig eL;
+    eL.lam = S.get<double2>("loc.lamL", r1);
+    eL.V = S.get<double2>("loc.VL", (size_t)r1 * r1);
+    eL.Vi = S.get<double2>("loc.ViL", (size_t)r1 * r1);
+    eig_nonsym(c, r1, Lint, eL.lam, eL.V, eL.Vi);
+    kron_inverse_eig<double2>(c, r1, m, r2, ZT, T, eL, eR, g, u, w0, w1);
+  } else {
+    double* Hw = S.get<double>("loc.H", (size_t)r1 * r1);
+    double* QT = S.get<double>("loc.QT", (size_t)r1 * r1);
+    double* Hc = S.get<double>("loc.Hc", (size_t)r1 * r1);
+    double* work = S.get<double>("loc.work", 2 * (size_t)r1);
+    double* wr = S.get<double>("loc.wr", n);
+    c.d2d(Hw, Lint, (size_t)r1 * r1);
+    hessenberg(c.s, r1, Hw, QT, work);
+    transpose(c.s, r1, r1, Hw, r1, Hc, r1);
+    kron_inverse_hess<double2, double>(c, r1, m, r2, ZT, T, QT, Hc, eR, g, u, w0, w1, wr);
+  }
+  c.sync();
+}
 
 int solve(Problem& p, const Ctx& c, const DTT& f, const DTT* x0, const SolveOptions& o, DTT& x, SolveReport& rep) {
   Amen a(p, c, o);

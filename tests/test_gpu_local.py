@@ -1,0 +1,89 @@
+"""GPU parity of the local Kronecker-sum solve (t2s2_local_solve) against a
+dense FP64 solve of the assembled local operator (oracle.amen.kron_sum_dense
+and LU).
+
+Inputs are shaped like the solver's local systems: the left and right
+interfaces are Galerkin projections of Kronecker sums of scaled 1D
+advection-diffusion operators onto random orthonormal bases, K is a scaled 1D
+operator.  Sizes span 1..4 row slots of the Hessenberg-Schur kernel (r1 = 1,
+37, 70, 130, 200, 256), ragged m and r2.
+
+Bar: both methods (eigendecompositions of both interfaces; Hessenberg form
+of the left one) solve in FP64 through similarity transforms, so their
+forward error is bounded by a modest multiple of the unit roundoff times
+cond(B) and the condition numbers of the eigenvector bases used:
+||u - u*|| <= 64 eps cond(B) cond(V_L) cond(V_R) ||u*|| (cond(V_L) taken as 1
+for the orthogonal Hessenberg transform would also hold; the looser bound is
+used for both).
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+import torch  # noqa: E402
+
+import paper_2506_04732_amd as t2s2  # noqa: E402
+from oracle import amen as oamen  # noqa: E402
+from oracle import collocation as oc  # noqa: E402
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _k1d(N, eps, beta):
+    Es, Ms = oc.interior_factors(oc.build_ops(1, N, eps, [beta]))
+    return np.linalg.solve(Es[0], Ms[0])
+
+
+def _interface(rng, r, Ks):
+    A = Ks[0]
+    for Kk in Ks[1:]:
+        A = np.kron(A, np.eye(Kk.shape[0])) + np.kron(np.eye(A.shape[0]), Kk)
+    X, _ = np.linalg.qr(rng.standard_normal((A.shape[0], r)))
+    return X.T @ A @ X
+
+
+def _case(seed, r1, m, r2):
+    rng = np.random.default_rng(seed)
+    KL = _interface(rng, r1, [_k1d(18, 2e-3, 0.4), _k1d(18, 2e-3, -0.7)]) if r1 > 1 else np.zeros((1, 1))
+    K = _k1d(m + 2, 2e-3, 0.3)
+    KR = _interface(rng, r2, [_k1d(8, 2e-3, 0.5)]) if r2 > 1 else np.zeros((1, 1))
+    g = rng.standard_normal((r1, m, r2))
+    return KL, K, KR, g
+
+
+def _cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+CASES = [(1, 6, 4), (37, 5, 3), (70, 6, 5), (130, 4, 3), (200, 3, 2), (256, 2, 2), (64, 9, 1)]
+
+
+@pytest.mark.parametrize("r1,m,r2", CASES)
+def test_local_solve_matches_dense(r1, m, r2):
+    KL, K, KR, g = _case(100 + r1, r1, m, r2)
+    B = oamen.kron_sum_dense(KL, K, KR)
+    ref = np.linalg.solve(B, g.ravel()).reshape(r1, m, r2)
+    cond = np.linalg.cond(B) * np.linalg.cond(np.linalg.eig(KL)[1]) * np.linalg.cond(np.linalg.eig(KR)[1])
+    bar = 64 * np.finfo(np.float64).eps * cond
+    outs = {}
+    for method in (t2s2.LOCAL_EIG, t2s2.LOCAL_HESS):
+        _say("local solve", r1, m, r2, "method", method)
+        u = t2s2.local_solve(_cuda(KL), _cuda(K), _cuda(KR), _cuda(g), method=method).cpu().numpy()
+        err = np.linalg.norm(u - ref) / np.linalg.norm(ref)
+        _say(f"  rel err {err:.2e} (bar {bar:.2e})")
+        assert err <= bar
+        outs[method] = u
+    assert np.linalg.norm(outs[0] - outs[1]) <= 2 * bar * np.linalg.norm(ref)
+
+
+def test_local_solve_rejects_unsupported_sizes():
+    KL, K, KR, g = _case(7, 4, 3, 2)
+    with pytest.raises(t2s2.T2S2Error):
+        # Hessenberg-Schur chains hold at most 256 rows
+        big = np.eye(300)
+        t2s2.local_solve(_cuda(big), _cuda(K), _cuda(KR), _cuda(np.zeros((300, 3, 2))), method=t2s2.LOCAL_HESS)
+    with pytest.raises(t2s2.T2S2Error):
+        t2s2.local_solve(_cuda(KL), _cuda(K), _cuda(KR), _cuda(g), method=5)

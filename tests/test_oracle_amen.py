@@ -83,3 +83,29 @@ def test_amen_transport_dominated_is_oscillation_free():
     assert expected == 1
     assert not metrics.is_oscillatory(out[sp.SCHEME_SC], expected)
     assert metrics.is_oscillatory(out[sp.SCHEME_PLAIN], expected)
+
+
+def test_kron_sum_dense_matches_interface_assembly_and_spectrum():
+    """kron_sum_dense against the assembly from rank-2 interfaces
+    (local_dense with the Kronecker-sum TT-matrix core [[I, 0], [K, I]] and
+    identity E-blocks), and its spectrum against the closed form: the
+    eigenvalues of a Kronecker sum are the sums of the factors' eigenvalues."""
+    rng = np.random.default_rng(31)
+    KL, K, KR = rng.standard_normal((4, 4)), rng.standard_normal((3, 3)), rng.standard_normal((5, 5))
+    PhiL = np.stack([KL, np.eye(4)], axis=1)          # (L-part, E-part)
+    PhiR = np.stack([np.eye(5), KR], axis=1)          # (E-part, L-part)
+    A = np.zeros((2, 3, 3, 2))
+    A[0, :, :, 0] = np.eye(3)
+    A[1, :, :, 0] = K
+    A[1, :, :, 1] = np.eye(3)
+    B = amen.kron_sum_dense(KL, K, KR)
+    assert np.max(np.abs(B - amen.local_dense(PhiL, A, PhiR))) <= 1e-14
+    sums = (np.linalg.eigvals(KL)[:, None, None] + np.linalg.eigvals(K)[None, :, None]
+            + np.linalg.eigvals(KR)[None, None, :]).ravel()
+    ev = np.linalg.eigvals(B)
+    # every eigenvalue of B is one of the sums (matched greedily)
+    rest = list(sums)
+    for z in ev:
+        k = int(np.argmin(np.abs(np.array(rest) - z)))
+        assert abs(rest[k] - z) <= 1e-9 * max(1.0, abs(z))
+        rest.pop(k)
