@@ -16,6 +16,17 @@ void trtri_upper(hipStream_t s, int n, const float2* R, float2* Rinv);
 // info needs k + 1 ints (info[0] = sweeps used).
 void jacobi_rows(hipStream_t s, int k, int c, double* B, double* JT, double* U, double* Wt, double* sigma,
                  int* info, int max_sweeps = 60);
+// Whether hessenberg() keeps an n x n matrix of rbytes-sized entries in LDS.
+bool hessenberg_fits_lds(int n, int rbytes);
+// A (n x n) <- H = Q^T A Q upper Hessenberg (zeros below the subdiagonal),
+// H in global memory; the reflector of step k goes to column k of V (n x n)
+// and beta[k] (n entries, 0: no reflector), Q = P_0 ... P_{n-3}, P_k =
+// I - beta_k v_k v_k^T.  n <= 512.
+void hessenberg_global(hipStream_t s, int n, double* A, double* V, double* beta);
+// Tinv = strict upper part of S with diagonal 1/beta (1 where beta = 0).
+void hess_tinv(hipStream_t s, int n, const double* S, const double* beta, double* Tinv);
+// X (n x n) <- identity.
+void identity(hipStream_t s, int n, double* X);
 // A (n x n) <- H = Q^T A Q upper Hessenberg, QT <- Q^T; work >= 2n doubles.
 void hessenberg(hipStream_t s, int n, double* A, double* QT, double* work);
 void hessenberg(hipStream_t s, int n, float* A, float* QT, float* work);

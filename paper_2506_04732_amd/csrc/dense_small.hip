@@ -464,6 +464,190 @@ __global__ void __launch_bounds__(kNT) trevec_kernel(int n, const typename CxOf<
   }
 }
 
+
+// Householder reduction to Hessenberg form for matrices that exceed LDS.  H
+// stays in global memory (L2-resident).  Per step, one read pass over the
+// active block (all rows, columns k..n-1) gives both w = H^T v and t = H v,
+// and one read-modify-write pass applies
+//   P H P = H - beta v w^T - beta t v^T + beta^2 (v^T t) v v^T.
+// Column k is written exactly (alpha on the subdiagonal, zeros below).  The
+// reflectors go to V (column k, zero above row k+1) and beta[k] (0: none);
+// Q is formed from them afterwards.  Wavefronts stride over rows, lanes over
+// columns (coalesced rows of the row-major H).
+// kHgCols column slots per lane (n <= 64 kHgCols), kHgRows rows in flight
+// per wavefront
+template <int kHgCols, int kHgRows>
+__global__ void __launch_bounds__(kNT) hess_global_kernel(int n, double* __restrict__ H, double* __restrict__ V,
+                                                          double* __restrict__ beta_out) {
+  extern __shared__ double sm[];
+  double* v = sm;             // n
+  double* t = v + n;          // n
+  double* w = t + n;          // n
+  double* wpart = w + n;      // (kNT / 64) * n
+  __shared__ double red[kNT / 64];
+  __shared__ double s_beta, s_alpha, s_c;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, NW = blockDim.x >> 6;
+  for (int k = 0; k < n - 2; ++k) {
+    // ---- reflector from H[k+1:, k]
+    double ss = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const double x = (i >= k + 1) ? H[(long)i * n + k] : 0.0;
+      v[i] = x;
+      ss = fma(x, x, ss);
+    }
+    for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
+    if (lane == 0) red[wave] = ss;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double tot = 0.0;
+      for (int i = 0; i < NW; ++i) tot += red[i];
+      const double x0 = v[k + 1];
+      const double tail = tot - x0 * x0;
+      if (tail <= TinyOf<double>::value * fmax(1.0, tot)) {
+        s_beta = 0.0;
+      } else {
+        const double alpha = (x0 >= 0.0) ? -sqrt(tot) : sqrt(tot);
+        v[k + 1] = x0 - alpha;
+        s_beta = 2.0 / (tail + (x0 - alpha) * (x0 - alpha));
+        s_alpha = alpha;
+      }
+    }
+    __syncthreads();
+    const double beta = s_beta;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) V[(long)i * n + k] = (beta != 0.0) ? v[i] : 0.0;
+    if (threadIdx.x == 0) beta_out[k] = beta;
+    if (beta == 0.0) continue;  // column already reduced
+    // ---- read pass: w_j = sum_i v_i H_ij (j >= k), t_i = sum_j H_ij v_j
+    double vj[kHgCols], wp[kHgCols];
+#pragma unroll
+    for (int q = 0; q < kHgCols; ++q) {
+      const int j = k + lane + 64 * q;
+      vj[q] = (j < n) ? v[j] : 0.0;
+      wp[q] = 0.0;
+    }
+    // kHgRows rows per iteration: their loads are issued together
+    for (int i0 = wave; i0 < n; i0 += kHgRows * NW) {
+      double hv[kHgRows][kHgCols];
+#pragma unroll
+      for (int r = 0; r < kHgRows; ++r) {
+        const int i = i0 + r * NW;
+#pragma unroll
+        for (int q = 0; q < kHgCols; ++q) {
+          const int j = k + lane + 64 * q;
+          hv[r][q] = (i < n && j < n) ? H[(long)i * n + j] : 0.0;
+        }
+      }
+      double tp[kHgRows];
+#pragma unroll
+      for (int r = 0; r < kHgRows; ++r) {
+        const int i = i0 + r * NW;
+        const double vi = (i < n) ? v[i] : 0.0;
+        tp[r] = 0.0;
+#pragma unroll
+        for (int q = 0; q < kHgCols; ++q) {
+          wp[q] = fma(vi, hv[r][q], wp[q]);
+          tp[r] = fma(hv[r][q], vj[q], tp[r]);
+        }
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int r = 0; r < kHgRows; ++r) tp[r] += __shfl_xor(tp[r], off, 64);
+      }
+      if (lane == 0) {
+#pragma unroll
+        for (int r = 0; r < kHgRows; ++r)
+          if (i0 + r * NW < n) t[i0 + r * NW] = tp[r];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kHgCols; ++q) {
+      const int j = k + lane + 64 * q;
+      if (j < n) wpart[(long)wave * n + j] = wp[q];
+    }
+    __syncthreads();
+    for (int j = k + threadIdx.x; j < n; j += blockDim.x) {
+      double a = 0.0;
+      for (int g = 0; g < NW; ++g) a += wpart[(long)g * n + j];
+      w[j] = a;
+    }
+    // c = v^T t
+    double cc = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) cc = fma(v[i], t[i], cc);
+    for (int off = 32; off > 0; off >>= 1) cc += __shfl_xor(cc, off, 64);
+    if (lane == 0) red[wave] = cc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double tot = 0.0;
+      for (int i = 0; i < NW; ++i) tot += red[i];
+      s_c = tot;
+    }
+    __syncthreads();
+    const double b2c = beta * beta * s_c;
+    const double alpha = s_alpha;
+    // ---- update pass
+    double wj[kHgCols];
+#pragma unroll
+    for (int q = 0; q < kHgCols; ++q) {
+      const int j = k + lane + 64 * q;
+      wj[q] = (j < n) ? w[j] : 0.0;
+    }
+    for (int i0 = wave; i0 < n; i0 += kHgRows * NW) {
+      double hv[kHgRows][kHgCols];
+#pragma unroll
+      for (int r = 0; r < kHgRows; ++r) {
+        const int i = i0 + r * NW;
+#pragma unroll
+        for (int q = 0; q < kHgCols; ++q) {
+          const int j = k + lane + 64 * q;
+          hv[r][q] = (i < n && j < n) ? H[(long)i * n + j] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < kHgRows; ++r) {
+        const int i = i0 + r * NW;
+        if (i >= n) continue;
+        const double vi = v[i], ti = t[i];
+#pragma unroll
+        for (int q = 0; q < kHgCols; ++q) {
+          const int j = k + lane + 64 * q;
+          if (j < n) {
+            double h;
+            if (j == k)
+              h = (i == k + 1) ? alpha : (i > k + 1 ? 0.0 : hv[r][q] - beta * ti * vj[q]);
+            else
+              h = hv[r][q] - beta * (vi * wj[q] + ti * vj[q]) + b2c * vi * vj[q];
+            H[(long)i * n + j] = h;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    for (int k = (n >= 2 ? n - 2 : 0); k < n; ++k) V[(long)i * n + k] = 0.0;
+  if (threadIdx.x == 0)
+    for (int k = (n >= 2 ? n - 2 : 0); k < n; ++k) beta_out[k] = 0.0;
+}
+
+// Tinv = strict upper part of S (= V^T V) with diagonal 1/beta (1 where no
+// reflector): the inverse of the compact-WY factor T of P_0 ... P_{n-3}
+__global__ void hess_tinv_kernel(int n, const double* __restrict__ S, const double* __restrict__ beta,
+                                 double* __restrict__ Tinv) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e >= (long)n * n) return;
+  const int i = (int)(e / n), j = (int)(e % n);
+  double x = 0.0;
+  if (j > i) x = S[e];
+  else if (j == i) x = (beta[i] != 0.0) ? 1.0 / beta[i] : 1.0;
+  Tinv[e] = x;
+}
+
+__global__ void identity_kernel(int n, double* __restrict__ X) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e >= (long)n * n) return;
+  X[e] = ((e / n) == (e % n)) ? 1.0 : 0.0;
+}
+
 }  // namespace
 
 // ============================================================ launchers
@@ -540,5 +724,36 @@ static void trevec_t(hipStream_t s, int n, const typename CxOf<R>::type* T, type
 }
 void trevec(hipStream_t s, int n, const double2* T, double2* Y) { trevec_t<double>(s, n, T, Y); }
 void trevec(hipStream_t s, int n, const float2* T, float2* Y) { trevec_t<float>(s, n, T, Y); }
+
+
+bool hessenberg_fits_lds(int n, int rbytes) {
+  const long need = ((long)n * n + 2L * n) * rbytes;
+  const long static_bytes = (long)rbytes * (kNT + kNT / 64 + 2);
+  return need <= kLdsBytes - static_bytes;
+}
+
+void hessenberg_global(hipStream_t s, int n, double* A, double* V, double* beta) {
+  T2S2_CHECK(n >= 1 && n <= 512, "hessenberg_global: n must be in [1, 512]");
+  const size_t lds = (size_t)(3L * n + (long)(kNT / 64) * n) * sizeof(double);
+  TimedScope ts(s, KC_HESS, sizeof(double) * 3.0 * n * n * n / 2.0, 10.0 * n * n * n / 3.0);
+  if (n <= 256)
+    hipLaunchKernelGGL((hess_global_kernel<4, 4>), dim3(1), dim3(kNT), lds, s, n, A, V, beta);
+  else
+    hipLaunchKernelGGL((hess_global_kernel<8, 2>), dim3(1), dim3(kNT), lds, s, n, A, V, beta);
+  T2S2_LAUNCH_CHECK();
+}
+
+void hess_tinv(hipStream_t s, int n, const double* S, const double* beta, double* Tinv) {
+  const long nn = (long)n * n;
+  TimedScope ts(s, KC_HESS, sizeof(double) * 2.0 * nn, 0.0);
+  hipLaunchKernelGGL(hess_tinv_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, n, S, beta, Tinv);
+  T2S2_LAUNCH_CHECK();
+}
+
+void identity(hipStream_t s, int n, double* X) {
+  const long nn = (long)n * n;
+  hipLaunchKernelGGL(identity_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, n, X);
+  T2S2_LAUNCH_CHECK();
+}
 
 }  // namespace t2s2

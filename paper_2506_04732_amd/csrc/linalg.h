@@ -89,6 +89,11 @@ void eig_nonsym(const Ctx& c, int n, const double* A, double2* lam, double2* V, 
 // The same factorisation computed in FP32 from A rounded to FP32.
 void eig_nonsym(const Ctx& c, int n, const double* A, float2* lam, float2* V, float2* Vinv);
 
+// A (n x n) <- H = Q^T A Q upper Hessenberg, QT <- Q^T (LDS-resident kernel
+// when it fits, else the global-memory reduction with Q formed by compact-WY
+// GEMMs).
+void hessenberg(const Ctx& c, int n, double* A, double* QT);
+
 // A (n x n real) = Z T Z^H; outputs ZT = Z^T and upper-triangular T.
 void schur_real(const Ctx& c, int n, const double* A, double2* ZT, double2* T);
 

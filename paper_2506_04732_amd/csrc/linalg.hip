@@ -221,18 +221,39 @@ int trunc_svd(const Ctx& c, int M, int n, const double* A, long lda, double delt
 }
 
 // ------------------------------------------------------------ eigen / Schur
+void hessenberg(const Ctx& c, int n, double* A, double* QT) {
+  Scratch& S = *c.sc;
+  if (hessenberg_fits_lds(n, (int)sizeof(double))) {
+    double* work = S.get<double>("hq.work", 2 * (size_t)n);
+    hessenberg(c.s, n, A, QT, work);
+    return;
+  }
+  // H in global memory; Q^T = I - V W^T, W = V T, T^{-1} = striu(V^T V) + diag(1/beta)
+  double* V = S.get<double>("hq.V", (size_t)n * n);
+  double* beta = S.get<double>("hq.beta", n);
+  double* G = S.get<double>("hq.G", (size_t)n * n);
+  double* T = S.get<double>("hq.T", (size_t)n * n);
+  double* W = S.get<double>("hq.W", (size_t)n * n);
+  hessenberg_global(c.s, n, A, V, beta);
+  gemm<double>(c.s, OpT, OpN, n, n, n, 1.0, V, n, 0, V, n, 0, 0.0, G, n, 0, 1);
+  hess_tinv(c.s, n, G, beta, W);
+  trtri_upper(c.s, n, W, T);
+  gemm<double>(c.s, OpN, OpN, n, n, n, 1.0, V, n, 0, T, n, 0, 0.0, W, n, 0, 1);
+  identity(c.s, n, QT);
+  gemm<double>(c.s, OpN, OpT, n, n, n, -1.0, V, n, 0, W, n, 0, 1.0, QT, n, 0, 1);
+}
+
 void schur_real(const Ctx& c, int n, const double* A, double2* ZT, double2* T) {
   Scratch& S = *c.sc;
   double* H = S.get<double>("eig.H", (size_t)n * n);
   double* QT = S.get<double>("eig.QT", (size_t)n * n);
-  double* work = S.get<double>("eig.work", 2 * (size_t)n);
   double* Hw = S.get<double>("eig.Hw", (size_t)n * n);
   double* Tr = S.get<double>("eig.Tr", (size_t)n * n);
   int* info = S.get<int>("eig.info", 1);
   int* bstart = S.get<int>("eig.bstart", n);
   double2* U = S.get<double2>("eig.U2", 2 * (size_t)n);
   c.d2d(H, A, (size_t)n * n);
-  hessenberg(c.s, n, H, QT, work);
+  hessenberg(c, n, H, QT);
   schur_francis(c.s, n, H, Hw, QT, Tr, info);
   rsf2csf(c.s, n, Tr, QT, T, ZT, bstart, U);
 }
@@ -266,8 +287,18 @@ void eig_nonsym(const Ctx& c, int n, const double* A, float2* lam, float2* V, fl
   float2* T = S.get<float2>("eig32.T", (size_t)n * n);
   float2* Y = S.get<float2>("eig32.Y", (size_t)n * n);
   float2* Yi = S.get<float2>("eig32.Yi", (size_t)n * n);
-  to_float(c.s, A, H, (long)n * n);
-  hessenberg(c.s, n, H, QT, work);
+  if (hessenberg_fits_lds(n, (int)sizeof(float))) {
+    to_float(c.s, A, H, (long)n * n);
+    hessenberg(c.s, n, H, QT, work);
+  } else {
+    // beyond the FP32 LDS size: FP64 reduction, rounded to FP32
+    double* Hd = S.get<double>("eig32.Hd", (size_t)n * n);
+    double* QTd = S.get<double>("eig32.QTd", (size_t)n * n);
+    c.d2d(Hd, A, (size_t)n * n);
+    hessenberg(c, n, Hd, QTd);
+    to_float(c.s, Hd, H, (long)n * n);
+    to_float(c.s, QTd, QT, (long)n * n);
+  }
   schur_francis(c.s, n, H, Hw, QT, Tr, info);
   rsf2csf(c.s, n, Tr, QT, T, ZT, bstart, U);
   trevec(c.s, n, T, Y);

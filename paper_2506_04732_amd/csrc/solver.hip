@@ -477,9 +477,8 @@ struct Amen {
       return;
     }
     double* Hw = buf("hess.H", (size_t)n * n);
-    double* work = buf("hess.work", 2 * (size_t)n);
     c.d2d(Hw, L[pos], (size_t)n * n);
-    hessenberg(c.s, n, Hw, hf[pos].QT, work);
+    hessenberg(c, n, Hw, hf[pos].QT);
     transpose(c.s, n, n, Hw, n, hf[pos].Hc, n);
     if (mixed) to_float(c.s, hf[pos].Hc, hf[pos].Hc32, (long)n * n);
     lhess[pos] = 1;
@@ -1013,10 +1012,9 @@ void local_kron_solve(const Ctx& c, int r1, int m, int r2, const double* Lint, c
     double* Hw = S.get<double>("loc.H", (size_t)r1 * r1);
     double* QT = S.get<double>("loc.QT", (size_t)r1 * r1);
     double* Hc = S.get<double>("loc.Hc", (size_t)r1 * r1);
-    double* work = S.get<double>("loc.work", 2 * (size_t)r1);
     double* wr = S.get<double>("loc.wr", n);
     c.d2d(Hw, Lint, (size_t)r1 * r1);
-    hessenberg(c.s, r1, Hw, QT, work);
+    hessenberg(c, r1, Hw, QT);
     transpose(c.s, r1, r1, Hw, r1, Hc, r1);
     kron_inverse_hess<double2, double>(c, r1, m, r2, ZT, T, QT, Hc, eR, g, u, w0, w1, wr);
   }

@@ -47,7 +47,8 @@ def _interface(rng, r, Ks):
 
 def _case(seed, r1, m, r2):
     rng = np.random.default_rng(seed)
-    KL = _interface(rng, r1, [_k1d(18, 2e-3, 0.4), _k1d(18, 2e-3, -0.7)]) if r1 > 1 else np.zeros((1, 1))
+    N1 = max(18, int(np.ceil(np.sqrt(r1))) + 3)        # (N1 - 2)^2 >= r1
+    KL = _interface(rng, r1, [_k1d(N1, 2e-3, 0.4), _k1d(N1, 2e-3, -0.7)]) if r1 > 1 else np.zeros((1, 1))
     K = _k1d(m + 2, 2e-3, 0.3)
     KR = _interface(rng, r2, [_k1d(8, 2e-3, 0.5)]) if r2 > 1 else np.zeros((1, 1))
     g = rng.standard_normal((r1, m, r2))
@@ -77,6 +78,22 @@ def test_local_solve_matches_dense(r1, m, r2):
         assert err <= bar
         outs[method] = u
     assert np.linalg.norm(outs[0] - outs[1]) <= 2 * bar * np.linalg.norm(ref)
+
+
+def test_local_solve_eigen_path_beyond_256_rows():
+    """r1 = 300: both interfaces by eigendecomposition (Hessenberg reduction of
+    a matrix beyond 256 rows, Francis QR from global memory); same bar."""
+    r1, m, r2 = 300, 2, 2
+    KL, K, KR, g = _case(300, r1, m, r2)
+    B = oamen.kron_sum_dense(KL, K, KR)
+    ref = np.linalg.solve(B, g.ravel()).reshape(r1, m, r2)
+    cond = np.linalg.cond(B) * np.linalg.cond(np.linalg.eig(KL)[1]) * np.linalg.cond(np.linalg.eig(KR)[1])
+    bar = 64 * np.finfo(np.float64).eps * cond
+    _say("local solve", r1, m, r2, "method 0")
+    u = t2s2.local_solve(_cuda(KL), _cuda(K), _cuda(KR), _cuda(g), method=t2s2.LOCAL_EIG).cpu().numpy()
+    err = np.linalg.norm(u - ref) / np.linalg.norm(ref)
+    _say(f"  rel err {err:.2e} (bar {bar:.2e})")
+    assert err <= bar
 
 
 def test_local_solve_rejects_unsupported_sizes():
