@@ -178,6 +178,50 @@ __global__ void __launch_bounds__(kNT) trtri_upper_kernel(int n, const T* __rest
 }
 
 // ------------------------------------------------ one-sided Jacobi SVD
+// Row norms of the rotated B (k x c), rows ranked by decreasing norm (ties by
+// index) and scattered: Wt (sorted rows), U (column dest(i) = row i of JT),
+// sigma (sorted norms); info[0] = sweeps, info[1..k] scratch.
+__device__ void jacobi_finish(int k, int c, const double* Bw, const double* Jw, double* __restrict__ U,
+                              double* __restrict__ Wt, double* __restrict__ sigma, int* __restrict__ info,
+                              int sweep) {
+  const long bsz = (long)k * c, jsz = (long)k * k;
+  // row norms, rank by decreasing norm (ties by index), scatter
+  for (int i = threadIdx.x; i < k; i += blockDim.x) {
+    double s = 0.0;
+    for (int e = 0; e < c; ++e) s = fma(Bw[(long)i * c + e], Bw[(long)i * c + e], s);
+    sigma[i] = sqrt(s);  // temporary, unsorted
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < k; i += blockDim.x) {
+    const double si = sigma[i];
+    int rank = 0;
+    for (int j = 0; j < k; ++j) {
+      const double sj = sigma[j];
+      rank += (sj > si) || (sj == si && j < i);
+    }
+    info[1 + i] = rank;  // scratch: destination of row i
+  }
+  __syncthreads();
+  for (long e = threadIdx.x; e < bsz; e += blockDim.x) {
+    const int i = (int)(e / c), col = (int)(e % c);
+    Wt[(long)info[1 + i] * c + col] = Bw[e];
+  }
+  // U = J: column dest(i) of U is row i of JT
+  for (long e = threadIdx.x; e < jsz; e += blockDim.x) {
+    const int i = (int)(e / k), r = (int)(e % k);
+    U[(long)r * k + info[1 + i]] = Jw[e];
+  }
+  __syncthreads();
+  // sorted sigma
+  for (int i = threadIdx.x; i < k; i += blockDim.x) {
+    double s = 0.0;
+    for (int e = 0; e < c; ++e) s = fma(Wt[(long)i * c + e], Wt[(long)i * c + e], s);
+    sigma[i] = sqrt(s);
+  }
+  if (threadIdx.x == 0) info[0] = sweep;
+}
+
+
 // B (k x c, row-major) = U * Wt with U orthogonal k x k and the rows of Wt
 // mutually orthogonal: rotations from the left orthogonalise the rows of B
 // (Hestenes' method applied to B^T), the rotations accumulate in U.  Rows are
@@ -259,40 +303,110 @@ __global__ void __launch_bounds__(kNT) jacobi_rows_kernel(int k, int c, double* 
     __syncthreads();
     if (rot == 0) break;
   }
-  // row norms, rank by decreasing norm (ties by index), scatter
-  for (int i = threadIdx.x; i < k; i += blockDim.x) {
-    double s = 0.0;
-    for (int e = 0; e < c; ++e) s = fma(Bw[(long)i * c + e], Bw[(long)i * c + e], s);
-    sigma[i] = sqrt(s);  // temporary, unsorted
+  jacobi_finish(k, c, Bw, Jw, U, Wt, sigma, info, sweep);
+}
+
+// One-sided Jacobi for matrices beyond LDS (block Jacobi).  The rows of B
+// (k x c) and of the rotation accumulator JT (k x k) are split into blocks of
+// bsz rows; in round `round` the blocks are paired round-robin (nplay
+// players, a bye when the block count is odd) and one workgroup per pair
+// loads both blocks into LDS, runs one Jacobi sweep over all row pairs of the
+// union and writes the rows back.  counter accumulates the rotations.
+__global__ void __launch_bounds__(kNT) jacobi_block_kernel(int k, int c, double* __restrict__ B,
+                                                           double* __restrict__ JT, int bsz, int nblk, int nplay,
+                                                           int round, int* __restrict__ counter) {
+  extern __shared__ double lds[];
+  __shared__ int s_rot;
+  const int s1 = blockIdx.x, s2 = nplay - 1 - blockIdx.x;
+  const int P = (s1 == 0) ? 0 : ((s1 - 1 + round) % (nplay - 1)) + 1;
+  const int Q = (s2 == 0) ? 0 : ((s2 - 1 + round) % (nplay - 1)) + 1;
+  if (P >= nblk || Q >= nblk) return;  // bye
+  const int p0 = P * bsz, pn = min(bsz, k - p0), q0 = Q * bsz, qn = min(bsz, k - q0);
+  const int rows = pn + qn;
+  double* Bw = lds;
+  double* Jw = lds + (long)rows * c;
+  for (long e = threadIdx.x; e < (long)rows * c; e += blockDim.x) {
+    const int r = (int)(e / c), col = (int)(e % c);
+    const int g = r < pn ? p0 + r : q0 + (r - pn);
+    Bw[e] = B[(long)g * c + col];
   }
+  for (long e = threadIdx.x; e < (long)rows * k; e += blockDim.x) {
+    const int r = (int)(e / k), col = (int)(e % k);
+    const int g = r < pn ? p0 + r : q0 + (r - pn);
+    Jw[e] = JT[(long)g * k + col];
+  }
+  if (threadIdx.x == 0) s_rot = 0;
   __syncthreads();
-  for (int i = threadIdx.x; i < k; i += blockDim.x) {
-    const double si = sigma[i];
-    int rank = 0;
-    for (int j = 0; j < k; ++j) {
-      const double sj = sigma[j];
-      rank += (sj > si) || (sj == si && j < i);
+  const int RP = rows + (rows & 1);
+  const int grp = threadIdx.x / kJacG, sub = threadIdx.x % kJacG, ngrp = blockDim.x / kJacG;
+  const double tol = 1e-10;
+  for (int rr = 0; rr < RP - 1; ++rr) {
+    for (int pi = grp; pi < RP / 2; pi += ngrp) {
+      const int t1 = pi, t2 = RP - 1 - pi;
+      int p = (t1 == 0) ? 0 : ((t1 - 1 + rr) % (RP - 1)) + 1;
+      int q = (t2 == 0) ? 0 : ((t2 - 1 + rr) % (RP - 1)) + 1;
+      if (p >= rows || q >= rows) continue;
+      if (p > q) {
+        const int t = p;
+        p = q;
+        q = t;
+      }
+      double* bp = Bw + (long)p * c;
+      double* bq = Bw + (long)q * c;
+      double a = 0.0, b = 0.0, g = 0.0;
+      for (int e = sub; e < c; e += kJacG) {
+        const double x = bp[e], y = bq[e];
+        a = fma(x, x, a);
+        b = fma(y, y, b);
+        g = fma(x, y, g);
+      }
+      for (int off = kJacG / 2; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off, kJacG);
+        b += __shfl_xor(b, off, kJacG);
+        g += __shfl_xor(g, off, kJacG);
+      }
+      if (g == 0.0 || fabs(g) <= tol * sqrt(a * b)) continue;
+      const double zeta = (b - a) / (2.0 * g);
+      const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+      const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+      for (int e = sub; e < c; e += kJacG) {
+        const double x = bp[e], y = bq[e];
+        bp[e] = cs * x - sn * y;
+        bq[e] = sn * x + cs * y;
+      }
+      double* jp = Jw + (long)p * k;
+      double* jq = Jw + (long)q * k;
+      for (int e = sub; e < k; e += kJacG) {
+        const double x = jp[e], y = jq[e];
+        jp[e] = cs * x - sn * y;
+        jq[e] = sn * x + cs * y;
+      }
+      if (sub == 0) atomicAdd(&s_rot, 1);
     }
-    info[1 + i] = rank;  // scratch: destination of row i
+    __syncthreads();
   }
-  __syncthreads();
-  for (long e = threadIdx.x; e < bsz; e += blockDim.x) {
-    const int i = (int)(e / c), col = (int)(e % c);
-    Wt[(long)info[1 + i] * c + col] = Bw[e];
+  for (long e = threadIdx.x; e < (long)rows * c; e += blockDim.x) {
+    const int r = (int)(e / c), col = (int)(e % c);
+    const int g = r < pn ? p0 + r : q0 + (r - pn);
+    B[(long)g * c + col] = Bw[e];
   }
-  // U = J: column dest(i) of U is row i of JT
-  for (long e = threadIdx.x; e < jsz; e += blockDim.x) {
-    const int i = (int)(e / k), r = (int)(e % k);
-    U[(long)r * k + info[1 + i]] = Jw[e];
+  for (long e = threadIdx.x; e < (long)rows * k; e += blockDim.x) {
+    const int r = (int)(e / k), col = (int)(e % k);
+    const int g = r < pn ? p0 + r : q0 + (r - pn);
+    JT[(long)g * k + col] = Jw[e];
   }
-  __syncthreads();
-  // sorted sigma
-  for (int i = threadIdx.x; i < k; i += blockDim.x) {
-    double s = 0.0;
-    for (int e = 0; e < c; ++e) s = fma(Wt[(long)i * c + e], Wt[(long)i * c + e], s);
-    sigma[i] = sqrt(s);
-  }
-  if (threadIdx.x == 0) info[0] = sweep;
+  if (threadIdx.x == 0 && s_rot > 0) atomicAdd(counter, s_rot);
+}
+
+__global__ void __launch_bounds__(kNT) jacobi_finish_kernel(int k, int c, const double* __restrict__ B,
+                                                            const double* __restrict__ JT, double* __restrict__ U,
+                                                            double* __restrict__ Wt, double* __restrict__ sigma,
+                                                            int* __restrict__ info, int sweep) {
+  jacobi_finish(k, c, B, JT, U, Wt, sigma, info, sweep);
+}
+
+__global__ void set_int_kernel(int* p, int v) {
+  if (threadIdx.x == 0) p[0] = v;
 }
 
 // ------------------------------------------------- Hessenberg reduction
@@ -688,6 +802,29 @@ void jacobi_rows(hipStream_t s, int k, int c, double* B, double* JT, double* U, 
   const long bsz = (long)k * c, jsz = (long)k * k;
   long need = 0;
   if (bsz <= kLdsDoubles) need = (bsz + jsz <= kLdsDoubles) ? bsz + jsz : bsz;
+  // beyond LDS: block Jacobi, one workgroup per pair of row blocks
+  const int blk = (int)(kLdsDoubles / (2L * (c + k)));
+  if (need == 0 && blk >= 2 && (k + blk - 1) / blk >= 3) {
+    TimedScope ts(s, KC_JACOBI, 8.0 * (2.0 * bsz + 2.0 * jsz), 0.0);
+    const int nblk = (k + blk - 1) / blk, nplay = nblk + (nblk & 1);
+    const size_t lds = (size_t)2 * blk * (c + k) * sizeof(double);
+    identity(s, k, JT);
+    int sweep = 0;
+    for (; sweep < max_sweeps; ++sweep) {
+      hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, s, info, 0);
+      for (int round = 0; round < nplay - 1; ++round)
+        hipLaunchKernelGGL(jacobi_block_kernel, dim3(nplay / 2), dim3(kNT), lds, s, k, c, B, JT, blk, nblk, nplay,
+                           round, info);
+      T2S2_LAUNCH_CHECK();
+      int rot = 0;
+      T2S2_HIP(hipMemcpyAsync(&rot, info, sizeof(int), hipMemcpyDeviceToHost, s));
+      T2S2_HIP(hipStreamSynchronize(s));
+      if (rot == 0) break;
+    }
+    hipLaunchKernelGGL(jacobi_finish_kernel, dim3(1), dim3(kNT), 0, s, k, c, B, JT, U, Wt, sigma, info, sweep);
+    T2S2_LAUNCH_CHECK();
+    return;
+  }
   TimedScope ts(s, KC_JACOBI, 8.0 * (2.0 * bsz + 2.0 * jsz), 0.0);
   if (need == bsz + jsz && need > 0)
     hipLaunchKernelGGL(jacobi_rows_kernel<2>, dim3(1), dim3(kNT), lds_bytes(need), s, k, c, B, JT, U, Wt, sigma,

@@ -1,15 +1,16 @@
-// Real Schur form by the implicit double-shift (Francis) QR iteration, and its
+// Real Schur form by the implicit multishift QR iteration (small-bulge
+// multishift: several double-shift bulges chased together), and its
 // conversion to a complex Schur form, for the small nonsymmetric matrices of
 // the TT solver (Hessenberg input, n <= 512).
 //
 // One workgroup.  The Hessenberg matrix lives in LDS in packed row form (row
-// i keeps columns max(0, i-3) .. n-1: the 3 x 3 bulge reaches three below the
-// diagonal) whenever it fits (n <= ~195 in FP64, ~275 in FP32), else in
-// global memory.  Both precisions share one template.  The
-// Schur vectors (rows of Z^T) are updated lazily: the reflectors of up to kFB
-// consecutive bulge-chase steps are multiplied into a small (kFB+3)^2 matrix
-// in LDS and applied to the affected rows of Z^T in one pass, so the chase
-// itself never waits on global memory.
+// i keeps columns max(0, i-3) .. n-1: a 3 x 3 bulge reaches three below the
+// diagonal) whenever it fits (n <= ~191 in FP64, ~271 in FP32), else in
+// global memory.  Both precisions share one template.  The Schur vectors
+// (rows of Z^T) are updated lazily: the reflectors of a few consecutive
+// phases are multiplied into a small matrix G in LDS and applied to the
+// affected rows of Z^T in one pass, so the chase itself never waits on
+// global memory.
 #include <cfloat>
 
 #include "dense_small.h"
@@ -19,11 +20,6 @@ namespace t2s2 {
 namespace {
 
 constexpr int kFqThreads = 256;
-constexpr int kFB = 16;          // reflectors per Z batch
-constexpr int kFG = kFB + 3;     // rows covered by one batch
-// bytes of dynamic LDS for the packed H: 160 KB less the static arrays
-template <class R>
-constexpr long kFqLdsBytes = 160000 - (long)(kFG * kFG) * sizeof(R) - 514 * 4 - 256;
 
 __host__ __device__ inline int row_start(int i) { return i > 3 ? i - 3 : 0; }
 
@@ -35,7 +31,7 @@ __host__ __device__ inline int packed_off(int n, int i, int j) {
 }
 
 template <bool LDS, class R>
-struct HStoreCF {
+struct HStore {
   R* base;
   int n;
   __device__ R& at(int i, int j) const {
@@ -43,216 +39,6 @@ struct HStoreCF {
     else return base[(long)i * n + j];
   }
 };
-
-template <bool LDS, class R>
-struct HStore {
-  R* base;
-  const int* rowoff;  // LDS: offset of row i in the packed array
-  int n;
-  __device__ R& at(int i, int j) const {
-    if constexpr (LDS) return base[rowoff[i] + (j - row_start(i))];
-    else return base[(long)i * n + j];
-  }
-};
-
-template <bool LDS, class R>
-__global__ void __launch_bounds__(kFqThreads) francis_kernel(int n, const R* __restrict__ Hin, R* __restrict__ Hg,
-                                                             R* __restrict__ ZT, R* __restrict__ Tout,
-                                                             int* __restrict__ info, int max_iter) {
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  R* lds = reinterpret_cast<R*>(lds_raw);
-  __shared__ R G[kFG * kFG];
-  __shared__ int rowoff[513];
-  __shared__ int s_l, s_hi, s_it, s_done, s_zk0, s_zcnt, s_zlast;
-  __shared__ R s_shift[2];
-  if constexpr (LDS) {
-    if (threadIdx.x == 0) {
-      int o = 0;
-      for (int i = 0; i < n; ++i) {
-        rowoff[i] = o;
-        o += n - row_start(i);
-      }
-      rowoff[n] = o;
-    }
-  }
-  __syncthreads();
-  HStore<LDS, R> H{LDS ? lds : Hg, rowoff, n};
-  for (long e = threadIdx.x; e < (long)n * n; e += blockDim.x) {
-    const int i = (int)(e / n), j = (int)(e % n);
-    if (j >= row_start(i)) H.at(i, j) = (j >= i - 1) ? Hin[e] : R(0.0);
-  }
-  if (threadIdx.x == 0) {
-    s_hi = n - 1;
-    s_it = 0;
-    s_done = 0;
-    s_zcnt = 0;
-    s_zk0 = 0;
-    s_zlast = 0;
-  }
-  __syncthreads();
-
-  // multiply the accumulated batch into rows zk0 .. zk0+kFG-1 of ZT
-  auto flush = [&]() {
-    const int cnt = s_zcnt, k0 = s_zk0;
-    if (cnt > 0) {
-      const int rows = min(kFG, n - k0);
-      for (int col = threadIdx.x; col < n; col += blockDim.x) {
-        R old[kFG];
-#pragma unroll
-        for (int b = 0; b < kFG; ++b) old[b] = (b < rows) ? ZT[(long)(k0 + b) * n + col] : R(0.0);
-#pragma unroll
-        for (int a = 0; a < kFG; ++a) {
-          if (a >= rows) break;
-          R acc = R(0.0);
-#pragma unroll
-          for (int b = 0; b < kFG; ++b) acc = fma(G[a * kFG + b], old[b], acc);
-          ZT[(long)(k0 + a) * n + col] = acc;
-        }
-      }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) s_zcnt = 0;
-    __syncthreads();
-  };
-
-  // bring the batch window to rows [a, a+w-1] (flushing when needed)
-  auto batch_open = [&](int a, int w) {
-    if (s_zcnt > 0 && (a < s_zlast || a + w - 1 > s_zk0 + kFG - 1)) flush();
-    if (s_zcnt == 0) {
-      for (int e = threadIdx.x; e < kFG * kFG; e += blockDim.x) G[e] = ((e / kFG) == (e % kFG)) ? R(1.0) : R(0.0);
-      __syncthreads();
-      if (threadIdx.x == 0) s_zk0 = a;
-      __syncthreads();
-    }
-  };
-
-  // apply the reflector P = I - tau v v^T (rows a..a+w-1) to H (rows from
-  // column c0, columns up to row r1) and to the batch matrix G
-  auto reflect = [&](int a, int w, R v0, R v1, R v2, R tau, int c0, int r1, int zero_col) {
-    batch_open(a, w);
-    const int ga = a - s_zk0;
-    for (int j = c0 + threadIdx.x; j < n; j += blockDim.x) {
-      const R h0 = H.at(a, j), h1 = H.at(a + 1, j), h2 = (w == 3) ? H.at(a + 2, j) : R(0.0);
-      const R s = tau * (v0 * h0 + v1 * h1 + v2 * h2);
-      if (j == zero_col) {
-        H.at(a, j) = h0 - s * v0;
-        H.at(a + 1, j) = R(0.0);
-        if (w == 3) H.at(a + 2, j) = R(0.0);
-      } else {
-        H.at(a, j) = h0 - s * v0;
-        H.at(a + 1, j) = h1 - s * v1;
-        if (w == 3) H.at(a + 2, j) = h2 - s * v2;
-      }
-    }
-    for (int c = threadIdx.x; c < kFG; c += blockDim.x) {
-      const R g0 = G[ga * kFG + c], g1 = G[(ga + 1) * kFG + c], g2 = (w == 3) ? G[(ga + 2) * kFG + c] : R(0.0);
-      const R s = tau * (v0 * g0 + v1 * g1 + v2 * g2);
-      G[ga * kFG + c] = g0 - s * v0;
-      G[(ga + 1) * kFG + c] = g1 - s * v1;
-      if (w == 3) G[(ga + 2) * kFG + c] = g2 - s * v2;
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i <= r1; i += blockDim.x) {
-      const R h0 = H.at(i, a), h1 = H.at(i, a + 1), h2 = (w == 3) ? H.at(i, a + 2) : R(0.0);
-      const R s = tau * (h0 * v0 + h1 * v1 + h2 * v2);
-      H.at(i, a) = h0 - s * v0;
-      H.at(i, a + 1) = h1 - s * v1;
-      if (w == 3) H.at(i, a + 2) = h2 - s * v2;
-    }
-    if (threadIdx.x == 0) {
-      s_zlast = a;
-      s_zcnt = s_zcnt + 1;
-    }
-    __syncthreads();
-  };
-
-  // deflation threshold: the factorisation only feeds the exact-solve
-  // preconditioner inside FP64 refinement, so subdiagonals below 1e-13 (FP64)
-  // or one FP32 ulp of their neighbours are dropped
-  const R ulp = sizeof(R) == 8 ? (R)1e-13 : (R)FLT_EPSILON;
-  int total = 0;
-  while (true) {
-    // ---- deflation: largest l <= hi with a negligible subdiagonal
-    if (threadIdx.x == 0) s_l = 0;
-    __syncthreads();
-    int hi = s_hi;
-    for (int i = 1 + threadIdx.x; i <= hi; i += blockDim.x) {
-      R sc = fabs(H.at(i - 1, i - 1)) + fabs(H.at(i, i));
-      if (sc == R(0.0)) sc = R(1.0);
-      if (fabs(H.at(i, i - 1)) <= ulp * sc) atomicMax(&s_l, i);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      const int l = s_l;
-      if (l >= 1 && l <= hi) H.at(l, l - 1) = R(0.0);
-      if (hi < 0) {
-        s_done = 1;
-      } else if (l >= hi - 1) {
-        s_hi = l - 1;  // 1 x 1 or 2 x 2 block converged
-        s_it = 0;
-        s_l = -1;
-        if (l - 1 < 0) s_done = 1;
-      } else {
-        const R a = H.at(hi - 1, hi - 1), b = H.at(hi - 1, hi), c = H.at(hi, hi - 1), d = H.at(hi, hi);
-        R sum = a + d, prod = a * d - b * c;
-        if (s_it > 0 && s_it % 10 == 0) {
-          const R e = fabs(c) + fabs(H.at(hi - 1, hi - 2));
-          sum = R(1.5) * e;
-          prod = e * e;
-        }
-        s_shift[0] = sum;
-        s_shift[1] = prod;
-        ++s_it;
-      }
-    }
-    __syncthreads();
-    if (s_done || total >= max_iter) break;
-    const int l = s_l;
-    hi = s_hi;
-    if (l < 0) continue;
-    ++total;
-    // ---- one Francis R-shift step on [l, hi]
-    const R sum = s_shift[0], prod = s_shift[1];
-    const int p = hi - l + 1;
-    R x, y, z;
-    {
-      const R h00 = H.at(l, l), h01 = H.at(l, l + 1), h10 = H.at(l + 1, l), h11 = H.at(l + 1, l + 1);
-      const R h21 = H.at(l + 2, l + 1);
-      x = h00 * h00 + h01 * h10 - sum * h00 + prod;
-      y = h10 * (h00 + h11 - sum);
-      z = h10 * h21;
-    }
-    for (int k = 0; k <= p - 3; ++k) {
-      const int a = l + k;
-      const R sg = sqrt(x * x + y * y + z * z);
-      if (sg > R(0.0) && (y != R(0.0) || z != R(0.0))) {
-        const R v0 = x + (x >= R(0.0) ? sg : -sg);
-        const R tau = R(2.0) / (v0 * v0 + y * y + z * z);
-        const int c0 = l + (k > 0 ? k - 1 : 0);
-        const int r1 = l + min(k + 3, p - 1);
-        reflect(a, 3, v0, y, z, tau, c0, r1, k > 0 ? a - 1 : -1);
-      }
-      x = H.at(a + 1, a);
-      y = H.at(a + 2, a);
-      z = (k < p - 3) ? H.at(a + 3, a) : R(0.0);
-    }
-    {
-      const R sg = sqrt(x * x + y * y);
-      if (sg > R(0.0) && y != R(0.0)) {
-        const R v0 = x + (x >= R(0.0) ? sg : -sg);
-        const R tau = R(2.0) / (v0 * v0 + y * y);
-        reflect(hi - 1, 2, v0, y, R(0.0), tau, hi - 2, hi, hi - 2);
-      }
-    }
-  }
-  flush();
-  for (long e = threadIdx.x; e < (long)n * n; e += blockDim.x) {
-    const int i = (int)(e / n), j = (int)(e % n);
-    Tout[e] = (j >= i - 1 && j >= row_start(i)) ? H.at(i, j) : R(0.0);
-  }
-  if (threadIdx.x == 0) info[0] = s_done ? total : -total;
-}
-
 
 // ------------------------------------------------- multishift bulge chase
 // KB double-shift bulges chased together (small-bulge multishift QR): the
@@ -429,7 +215,7 @@ __global__ void __launch_bounds__(kFqThreads) francis_ms_kernel(int n, const R* 
   __shared__ R s_wr[NS], s_wi[NS];
   __shared__ R s_sh[KB][2];
   __shared__ int s_l, s_hi, s_done;
-  HStoreCF<LDS, R> H{LDS ? lds : Hg, n};
+  HStore<LDS, R> H{LDS ? lds : Hg, n};
   for (long e = threadIdx.x; e < (long)n * n; e += blockDim.x) {
     const int i = (int)(e / n), j = (int)(e % n);
     if (j >= row_start(i)) H.at(i, j) = (j >= i - 1) ? Hin[e] : R(0.0);
