@@ -804,7 +804,7 @@ void jacobi_rows(hipStream_t s, int k, int c, double* B, double* JT, double* U, 
   if (bsz <= kLdsDoubles) need = (bsz + jsz <= kLdsDoubles) ? bsz + jsz : bsz;
   // beyond LDS: block Jacobi, one workgroup per pair of row blocks
   const int blk = (int)(kLdsDoubles / (2L * (c + k)));
-  if (need == 0 && blk >= 2 && (k + blk - 1) / blk >= 3) {
+  if (need < bsz + jsz && blk >= 2 && (k + blk - 1) / blk >= 3) {
     TimedScope ts(s, KC_JACOBI, 8.0 * (2.0 * bsz + 2.0 * jsz), 0.0);
     const int nblk = (k + blk - 1) / blk, nplay = nblk + (nblk & 1);
     const size_t lds = (size_t)2 * blk * (c + k) * sizeof(double);
