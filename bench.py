@@ -52,16 +52,37 @@ def roofline_entry(name: str, st: dict, traffic=None) -> dict:
             "avg_launch_us": avg_s * 1e6, "algorithmic_flops_per_launch": per_launch_flops}
 
 
+# source file of each kernel class (the traffic counters are valid for one version of it)
+KERNEL_SOURCE = {"schur_qr": "schur.hip", "gemm_f64": "gemm.hip", "jacobi_svd": "dense_small.hip",
+                 "hessenberg": "dense_small.hip", "hess_solve": "kron_hess.hip", "ttm_matvec": "tt_kernels.hip"}
+
+
+def kernel_source_sha1(kernel: str):
+    import hashlib
+    name = KERNEL_SOURCE.get(kernel)
+    if name is None:
+        return None
+    path = os.path.join(ROOT, "paper_2506_04732_amd", "csrc", name)
+    if not os.path.exists(path):
+        return None
+    with open(path, "rb") as fh:
+        return hashlib.sha1(fh.read()).hexdigest()
+
+
 def load_traffic(kernel: str):
-    """HBM bytes per launch from committed rocprofv3 --pmc summaries, if present."""
+    """HBM bytes per launch from committed rocprofv3 --pmc summaries, if present
+    and taken on the current source of the kernel (else None)."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{WORKLOAD}.json")
     if not os.path.exists(path):
         return None
     try:
         with open(path) as fh:
-            return json.load(fh).get("hbm_bytes_per_launch")
+            rec = json.load(fh)
     except Exception:
         return None
+    if rec.get("kernel_source_sha1") != kernel_source_sha1(kernel):
+        return None
+    return rec.get("hbm_bytes_per_launch")
 
 
 def cpu_baseline(prob, gpu_result, sweeps: int) -> dict:
