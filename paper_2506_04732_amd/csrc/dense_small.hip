@@ -310,8 +310,13 @@ __global__ void __launch_bounds__(kNT) jacobi_rows_kernel(int k, int c, double* 
 // (k x c) and of the rotation accumulator JT (k x k) are split into blocks of
 // bsz rows; in round `round` the blocks are paired round-robin (nplay
 // players, a bye when the block count is odd) and one workgroup per pair
-// loads both blocks into LDS, runs one Jacobi sweep over all row pairs of the
-// union and writes the rows back.  counter accumulates the rotations.
+// loads the rows of B of both blocks into LDS and runs one Jacobi sweep over
+// all row pairs of the union, accumulating its rotations in a small
+// rows x rows matrix Jl; the B rows are written back and JT's rows of the
+// pair are replaced by Jl times them.  Each lane keeps its share of a row
+// pair in registers between the dot products and the rotation (c <= NR
+// kJacG).  counter accumulates the rotations.
+template <int NR>
 __global__ void __launch_bounds__(kNT) jacobi_block_kernel(int k, int c, double* __restrict__ B,
                                                            double* __restrict__ JT, int bsz, int nblk, int nplay,
                                                            int round, int* __restrict__ counter) {
@@ -323,18 +328,14 @@ __global__ void __launch_bounds__(kNT) jacobi_block_kernel(int k, int c, double*
   if (P >= nblk || Q >= nblk) return;  // bye
   const int p0 = P * bsz, pn = min(bsz, k - p0), q0 = Q * bsz, qn = min(bsz, k - q0);
   const int rows = pn + qn;
-  double* Bw = lds;
-  double* Jw = lds + (long)rows * c;
+  double* Bw = lds;                     // rows x c (later: the old JT rows, rows x k, k <= c)
+  double* Jl = lds + (long)rows * c;    // rows x rows
+  auto grow = [&](int r) { return r < pn ? p0 + r : q0 + (r - pn); };
   for (long e = threadIdx.x; e < (long)rows * c; e += blockDim.x) {
     const int r = (int)(e / c), col = (int)(e % c);
-    const int g = r < pn ? p0 + r : q0 + (r - pn);
-    Bw[e] = B[(long)g * c + col];
+    Bw[e] = B[(long)grow(r) * c + col];
   }
-  for (long e = threadIdx.x; e < (long)rows * k; e += blockDim.x) {
-    const int r = (int)(e / k), col = (int)(e % k);
-    const int g = r < pn ? p0 + r : q0 + (r - pn);
-    Jw[e] = JT[(long)g * k + col];
-  }
+  for (int e = threadIdx.x; e < rows * rows; e += blockDim.x) Jl[e] = ((e / rows) == (e % rows)) ? 1.0 : 0.0;
   if (threadIdx.x == 0) s_rot = 0;
   __syncthreads();
   const int RP = rows + (rows & 1);
@@ -353,12 +354,16 @@ __global__ void __launch_bounds__(kNT) jacobi_block_kernel(int k, int c, double*
       }
       double* bp = Bw + (long)p * c;
       double* bq = Bw + (long)q * c;
+      double xs[NR], ys[NR];
       double a = 0.0, b = 0.0, g = 0.0;
-      for (int e = sub; e < c; e += kJacG) {
-        const double x = bp[e], y = bq[e];
-        a = fma(x, x, a);
-        b = fma(y, y, b);
-        g = fma(x, y, g);
+#pragma unroll
+      for (int u = 0; u < NR; ++u) {
+        const int e = sub + u * kJacG;
+        xs[u] = (e < c) ? bp[e] : 0.0;
+        ys[u] = (e < c) ? bq[e] : 0.0;
+        a = fma(xs[u], xs[u], a);
+        b = fma(ys[u], ys[u], b);
+        g = fma(xs[u], ys[u], g);
       }
       for (int off = kJacG / 2; off > 0; off >>= 1) {
         a += __shfl_xor(a, off, kJacG);
@@ -369,14 +374,17 @@ __global__ void __launch_bounds__(kNT) jacobi_block_kernel(int k, int c, double*
       const double zeta = (b - a) / (2.0 * g);
       const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
       const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-      for (int e = sub; e < c; e += kJacG) {
-        const double x = bp[e], y = bq[e];
-        bp[e] = cs * x - sn * y;
-        bq[e] = sn * x + cs * y;
+#pragma unroll
+      for (int u = 0; u < NR; ++u) {
+        const int e = sub + u * kJacG;
+        if (e < c) {
+          bp[e] = cs * xs[u] - sn * ys[u];
+          bq[e] = sn * xs[u] + cs * ys[u];
+        }
       }
-      double* jp = Jw + (long)p * k;
-      double* jq = Jw + (long)q * k;
-      for (int e = sub; e < k; e += kJacG) {
+      double* jp = Jl + (long)p * rows;
+      double* jq = Jl + (long)q * rows;
+      for (int e = sub; e < rows; e += kJacG) {
         const double x = jp[e], y = jq[e];
         jp[e] = cs * x - sn * y;
         jq[e] = sn * x + cs * y;
@@ -387,13 +395,24 @@ __global__ void __launch_bounds__(kNT) jacobi_block_kernel(int k, int c, double*
   }
   for (long e = threadIdx.x; e < (long)rows * c; e += blockDim.x) {
     const int r = (int)(e / c), col = (int)(e % c);
-    const int g = r < pn ? p0 + r : q0 + (r - pn);
-    B[(long)g * c + col] = Bw[e];
+    B[(long)grow(r) * c + col] = Bw[e];
   }
+  __syncthreads();
+  // JT rows of the pair <- Jl x (old rows), the old rows staged where Bw was
   for (long e = threadIdx.x; e < (long)rows * k; e += blockDim.x) {
     const int r = (int)(e / k), col = (int)(e % k);
-    const int g = r < pn ? p0 + r : q0 + (r - pn);
-    JT[(long)g * k + col] = Jw[e];
+    Bw[e] = JT[(long)grow(r) * k + col];
+  }
+  __syncthreads();
+  // thread: one column, rows r = rs, rs + nrs, ...
+  const int nrs = max(1, (int)(blockDim.x / k));
+  const int col = threadIdx.x % k, rs = threadIdx.x / k;
+  if (rs < nrs && threadIdx.x < nrs * k) {
+    for (int r = rs; r < rows; r += nrs) {
+      double acc = 0.0;
+      for (int s2i = 0; s2i < rows; ++s2i) acc = fma(Jl[r * rows + s2i], Bw[(long)s2i * k + col], acc);
+      JT[(long)grow(r) * k + col] = acc;
+    }
   }
   if (threadIdx.x == 0 && s_rot > 0) atomicAdd(counter, s_rot);
 }
@@ -803,18 +822,22 @@ void jacobi_rows(hipStream_t s, int k, int c, double* B, double* JT, double* U, 
   long need = 0;
   if (bsz <= kLdsDoubles) need = (bsz + jsz <= kLdsDoubles) ? bsz + jsz : bsz;
   // beyond LDS: block Jacobi, one workgroup per pair of row blocks
-  const int blk = (int)(kLdsDoubles / (2L * (c + k)));
-  if (need < bsz + jsz && blk >= 2 && (k + blk - 1) / blk >= 3) {
+  // block size: 2 blk rows of B and the 2blk x 2blk rotation block in LDS,
+  // at least 8 blocks (4 workgroups per round)
+  int blk = 1;
+  while (2L * (blk + 1) * c + 4L * (blk + 1) * (blk + 1) <= kLdsDoubles) ++blk;
+  blk = std::min(blk, std::max(2, (k + 7) / 8));
+  if (need < bsz + jsz && k <= c && c <= 16 * kJacG && blk >= 2 && (k + blk - 1) / blk >= 3) {
     TimedScope ts(s, KC_JACOBI, 8.0 * (2.0 * bsz + 2.0 * jsz), 0.0);
     const int nblk = (k + blk - 1) / blk, nplay = nblk + (nblk & 1);
-    const size_t lds = (size_t)2 * blk * (c + k) * sizeof(double);
+    const size_t lds = (size_t)(2L * blk * c + 4L * blk * blk) * sizeof(double);
     identity(s, k, JT);
     int sweep = 0;
     for (; sweep < max_sweeps; ++sweep) {
       hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, s, info, 0);
       for (int round = 0; round < nplay - 1; ++round)
-        hipLaunchKernelGGL(jacobi_block_kernel, dim3(nplay / 2), dim3(kNT), lds, s, k, c, B, JT, blk, nblk, nplay,
-                           round, info);
+        hipLaunchKernelGGL(jacobi_block_kernel<16>, dim3(nplay / 2), dim3(kNT), lds, s, k, c, B, JT, blk, nblk,
+                           nplay, round, info);
       T2S2_LAUNCH_CHECK();
       int rot = 0;
       T2S2_HIP(hipMemcpyAsync(&rot, info, sizeof(int), hipMemcpyDeviceToHost, s));
