@@ -103,45 +103,57 @@ int dcholqr(const Ctx& c, int M, int n, const double* A, long lda, double* Qout,
   int* mask = S.get<int>("dq.mask", n);
   int* cnt = S.get<int>("dq.cnt", 1);
   int* idx = S.get<int>("dq.idx", n);
-  copy2d(c.s, M, n, A, lda, Aw, n);
-  const double normA2 = c.dot(Aw, Aw, (long)M * n);
-  if (!(normA2 > 0.0)) {
-    T2S2_CHECK(normA2 == 0.0, "dcholqr: non-finite input");
-    return 0;
+  // A (contiguous) is read in place
+  const double* Ain = A;
+  if (lda != n) {
+    copy2d(c.s, M, n, A, lda, Aw, n);
+    Ain = Aw;
   }
-  c.d2d(Work, Aw, (size_t)M * n);
+  const double* Wk = Ain;      // the part of A not yet represented (level 0: A)
+  double normA2 = -1.0;        // ||A||^2, computed when a deflation test needs it
   std::vector<int> hmask(n), hidx;
   int k = 0;
   for (int level = 0; level < 5 && k < kmax; ++level) {
-    gemm<double>(c.s, OpT, OpN, n, n, M, 1.0, Work, n, 0, Work, n, 0, 0.0, G, n, 0, 1);
+    gemm<double>(c.s, OpT, OpN, n, n, M, 1.0, Wk, n, 0, Wk, n, 0, 0.0, G, n, 0, 1);
     chol_skip(c.s, n, G, Rl, mask, cnt, 1e-11);
     int kl = 0;
     c.d2h(&kl, cnt, 1);
     if (kl == 0) break;
-    c.d2h(hmask.data(), mask, n);
-    hidx.clear();
-    for (int j = 0; j < n && (int)hidx.size() < kmax - k; ++j)
-      if (hmask[j]) hidx.push_back(j);
-    kl = (int)hidx.size();
-    if (kl == 0) break;
-    c.h2d(idx, hidx.data(), kl);
-    gather_cols(c.s, M, kl, Work, n, idx, Ak, kl);
-    // R11 = Rl[idx][idx]: gather rows into R11i (as scratch), then columns
-    gather_cols(c.s, n, kl, Rl, n, idx, R11i, kl);           // n x kl: columns idx
-    // rows idx of that: transpose, gather columns, transpose back
-    transpose(c.s, n, kl, R11i, kl, G, n);                   // kl x n
-    gather_cols(c.s, kl, kl, G, n, idx, R11, kl);            // kl x kl = (R11)^T
-    transpose(c.s, kl, kl, R11, kl, G, kl);                  // R11
-    trtri_upper(c.s, kl, G, R11i);
-    gemm<double>(c.s, OpN, OpN, M, kl, kl, 1.0, Ak, kl, 0, R11i, kl, 0, 0.0, Qk, kl, 0, 1);
+    const double* Ablk;   // the kept columns of Wk (M x kl)
+    const double* Rblk;   // their Cholesky factor (kl x kl)
+    if (kl == n && n <= kmax - k) {
+      // every column kept: no gathers
+      Ablk = Wk;
+      Rblk = Rl;
+    } else {
+      c.d2h(hmask.data(), mask, n);
+      hidx.clear();
+      for (int j = 0; j < n && (int)hidx.size() < kmax - k; ++j)
+        if (hmask[j]) hidx.push_back(j);
+      kl = (int)hidx.size();
+      if (kl == 0) break;
+      c.h2d(idx, hidx.data(), kl);
+      gather_cols(c.s, M, kl, Wk, n, idx, Ak, kl);
+      // R11 = Rl[idx][idx]: gather columns, then rows (via transposes)
+      gather_cols(c.s, n, kl, Rl, n, idx, R11i, kl);           // n x kl: columns idx
+      transpose(c.s, n, kl, R11i, kl, G, n);                   // kl x n
+      gather_cols(c.s, kl, kl, G, n, idx, R11, kl);            // kl x kl = (R11)^T
+      transpose(c.s, kl, kl, R11, kl, G, kl);                  // R11
+      Ablk = Ak;
+      Rblk = G;
+    }
+    trtri_upper(c.s, kl, Rblk, R11i);
+    gemm<double>(c.s, OpN, OpN, M, kl, kl, 1.0, Ablk, kl, 0, R11i, kl, 0, 0.0, Qk, kl, 0, 1);
     // orthogonality pass(es): reorthogonalise against earlier levels, then a
-    // Cholesky QR pass on the new block
+    // Cholesky QR pass on the new block (results alternate between Qk and Ak)
+    double* qa = Qk;
+    double* qb = Ak;
     for (int pass = 0; pass < 2; ++pass) {
       if (k > 0) {
-        gemm<double>(c.s, OpT, OpN, k, kl, M, 1.0, Q, kmax, 0, Qk, kl, 0, 0.0, C, kl, 0, 1);
-        gemm<double>(c.s, OpN, OpN, M, kl, k, -1.0, Q, kmax, 0, C, kl, 0, 1.0, Qk, kl, 0, 1);
+        gemm<double>(c.s, OpT, OpN, k, kl, M, 1.0, Q, kmax, 0, qa, kl, 0, 0.0, C, kl, 0, 1);
+        gemm<double>(c.s, OpN, OpN, M, kl, k, -1.0, Q, kmax, 0, C, kl, 0, 1.0, qa, kl, 0, 1);
       }
-      gemm<double>(c.s, OpT, OpN, kl, kl, M, 1.0, Qk, kl, 0, Qk, kl, 0, 0.0, G, kl, 0, 1);
+      gemm<double>(c.s, OpT, OpN, kl, kl, M, 1.0, qa, kl, 0, qa, kl, 0, 0.0, G, kl, 0, 1);
       chol_skip(c.s, kl, G, R11, mask, cnt, 1e-14);
       int k2 = 0;
       c.d2h(&k2, cnt, 1);
@@ -153,28 +165,39 @@ int dcholqr(const Ctx& c, int M, int n, const double* A, long lda, double* Qout,
           if (m2[j]) id2.push_back(j);
         if (id2.empty()) { kl = 0; break; }
         c.h2d(idx, id2.data(), id2.size());
-        gather_cols(c.s, M, (int)id2.size(), Qk, kl, idx, Ak, (long)id2.size());
+        gather_cols(c.s, M, (int)id2.size(), qa, kl, idx, qb, (long)id2.size());
         kl = (int)id2.size();
-        c.d2d(Qk, Ak, (size_t)M * kl);
+        std::swap(qa, qb);
         --pass;  // redo this pass on the reduced block
         continue;
       }
       trtri_upper(c.s, kl, R11, R11i);
-      gemm<double>(c.s, OpN, OpN, M, kl, kl, 1.0, Qk, kl, 0, R11i, kl, 0, 0.0, Ak, kl, 0, 1);
-      c.d2d(Qk, Ak, (size_t)M * kl);
+      gemm<double>(c.s, OpN, OpN, M, kl, kl, 1.0, qa, kl, 0, R11i, kl, 0, 0.0, qb, kl, 0, 1);
+      std::swap(qa, qb);
     }
     if (kl == 0) break;
-    copy2d(c.s, M, kl, Qk, kl, Q + k, kmax);
+    copy2d(c.s, M, kl, qa, kl, Q + k, kmax);
     k += kl;
+    if (k >= kmax) break;  // full rank: nothing left to represent
     // deflate: Work = A - Q Q^T A
-    gemm<double>(c.s, OpT, OpN, k, n, M, 1.0, Q, kmax, 0, Aw, n, 0, 0.0, C, n, 0, 1);
-    c.d2d(Work, Aw, (size_t)M * n);
+    if (normA2 < 0.0) {
+      normA2 = c.dot(Ain, Ain, (long)M * n);
+      T2S2_CHECK(std::isfinite(normA2), "dcholqr: non-finite input");
+    }
+    gemm<double>(c.s, OpT, OpN, k, n, M, 1.0, Q, kmax, 0, Ain, n, 0, 0.0, C, n, 0, 1);
+    c.d2d(Work, Ain, (size_t)M * n);
     gemm<double>(c.s, OpN, OpN, M, n, k, -1.0, Q, kmax, 0, C, n, 0, 1.0, Work, n, 0, 1);
+    Wk = Work;
     const double rem = c.dot(Work, Work, (long)M * n);
     if (rem <= drop * drop * normA2) break;
   }
-  if (k == 0) return 0;
-  gemm<double>(c.s, OpT, OpN, k, n, M, 1.0, Q, kmax, 0, Aw, n, 0, 0.0, Rout, n, 0, 1);
+  if (k == 0) {
+    // zero matrix (or a non-finite one, which is an error)
+    const double a2 = c.dot(Ain, Ain, (long)M * n);
+    T2S2_CHECK(std::isfinite(a2), "dcholqr: non-finite input");
+    return 0;
+  }
+  gemm<double>(c.s, OpT, OpN, k, n, M, 1.0, Q, kmax, 0, Ain, n, 0, 0.0, Rout, n, 0, 1);
   copy2d(c.s, M, k, Q, kmax, Qout, k);
   return k;
 }

@@ -128,6 +128,27 @@ def test_round_matches_oracle(tol):
     assert np.linalg.norm(ott.full(gr) - ott.full(orr)) <= 2 * tol * np.linalg.norm(full_y) + 1e-12 * np.linalg.norm(full_y)
 
 
+@pytest.mark.parametrize("tol", [1e-8, 1e-12])
+def test_round_large_ranks_matches_oracle(tol):
+    """Middle bond of rank ~200: the truncated SVD there is of a 203 x 203
+    triangular factor, beyond LDS (block Jacobi over pairs of row blocks)."""
+    _say("round large", tol)
+    rng = np.random.default_rng(12)
+    ms = [15, 15, 15, 15]
+    x = _rand_tt(rng, ms, [1, 15, 200, 15, 1])
+    y = ott.add(x, _rand_tt(rng, ms, [1, 3, 3, 3, 1]), 1.0, 1e-4)
+    p = t2s2.Problem(4, [v + 2 for v in ms], 1e-2, np.ones(4), 1, rank_cap=256)
+    g = TT.from_numpy(y)
+    p.tt_round(g, tol)
+    gr = g.to_numpy()
+    orr = ott.round_tt(y, tol)
+    full_y = ott.full(y)
+    err_g = np.linalg.norm(ott.full(gr) - full_y)
+    assert err_g <= tol * np.linalg.norm(full_y) * (1 + 1e-8) + 1e-13 * np.linalg.norm(full_y)
+    assert max(ott.ranks(gr)) <= max(ott.ranks(orr)) + 1
+    assert np.linalg.norm(ott.full(gr) - ott.full(orr)) <= 2 * tol * np.linalg.norm(full_y) + 1e-12 * np.linalg.norm(full_y)
+
+
 @pytest.mark.parametrize("d,N", [(1, [20]), (3, [9, 5, 11]), (6, [32] * 6)])
 def test_sources_match_oracle(d, N):
     """Device-sampled separable sources against the oracle's factors on its own grid."""
