@@ -354,10 +354,15 @@ int t2s2_tt_unpack(int d, const int* n, int rank, const float* in,
  * t2s2_timing_enable(1) resets the counters; (0) stops recording.
  * Classes: 0 real GEMM, 1 complex GEMM, 2 TT-matvec core, 3 Schur QR,
  * 4 Hessenberg, 5 Jacobi SVD, 6 Cholesky, 7 triangular inverse,
- * 8 triangular eigenvectors, 9 Kronecker-sum triangular solves, 10 other.
- * t2s2_timing_read synchronises the device work it reads; EINVAL for a bad
- * class. */
+ * 8 triangular eigenvectors, 9 Kronecker-sum triangular solves,
+ * 10 Hessenberg-Schur chains, 11 other.
+ * t2s2_timing_classes(mask) restricts recording to the classes whose bit is
+ * set in mask (bit c = class c; default all): each recorded launch costs two
+ * event records on the host, so a timed run can record only the classes it
+ * reports.  t2s2_timing_read synchronises the device work it reads; EINVAL
+ * for a bad class. */
 int t2s2_timing_enable(int on);
+int t2s2_timing_classes(unsigned int mask);
 int t2s2_timing_read(int cls, double* total_ms, long long* launches, double* bytes, double* flops);
 const char* t2s2_timing_class_name(int cls);
 

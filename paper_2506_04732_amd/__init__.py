@@ -53,6 +53,17 @@ def timing_enable(on: bool = True) -> None:
     check(lib().t2s2_timing_enable(1 if on else 0))
 
 
+def timing_classes(names=None) -> None:
+    """Record only the named kernel classes while timing is on (None: all)."""
+    if names is None:
+        mask = 0xFFFFFFFF
+    else:
+        mask = 0
+        for nm in names:
+            mask |= 1 << _lib.TIMING_CLASSES.index(nm)
+    check(lib().t2s2_timing_classes(mask))
+
+
 def timing_read() -> dict:
     """{class name: {"ms", "launches", "bytes", "flops"}} accumulated since timing_enable(True)."""
     out = {}

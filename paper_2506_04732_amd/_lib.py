@@ -16,7 +16,7 @@ EXPORTED = [
     "t2s2_last_error", "t2s2_nodes", "t2s2_matrices_1d", "t2s2_problem_create", "t2s2_problem_destroy",
     "t2s2_problem_operator", "t2s2_problem_colloc", "t2s2_tt_matvec", "t2s2_tt_norm",
     "t2s2_tt_residual_norm", "t2s2_tt_round", "t2s2_local_solve", "t2s2_solve", "t2s2_solve_batched", "t2s2_default_options",
-    "t2s2_timing_enable", "t2s2_timing_read", "t2s2_timing_class_name",
+    "t2s2_timing_enable", "t2s2_timing_classes", "t2s2_timing_read", "t2s2_timing_class_name",
     "t2s2_mlp_create", "t2s2_mlp_destroy", "t2s2_mlp_param_count", "t2s2_mlp_get_params", "t2s2_mlp_set_params",
     "t2s2_mlp_forward", "t2s2_mlp_backward", "t2s2_mlp_adam_step", "t2s2_mlp_infer_bf16", "t2s2_mlp_train",
     "t2s2_tt_fit_loss", "t2s2_tt_pack", "t2s2_tt_unpack", "t2s2_source_gaussians", "t2s2_source_manufactured",
@@ -110,6 +110,7 @@ def lib() -> C.CDLL:
     L.t2s2_default_options.argtypes = [C.POINTER(Options)]
     L.t2s2_default_options.restype = None
     L.t2s2_timing_enable.argtypes = [C.c_int]
+    L.t2s2_timing_classes.argtypes = [C.c_uint]
     L.t2s2_timing_read.argtypes = [C.c_int, dp, C.POINTER(C.c_longlong), dp, dp]
     L.t2s2_timing_class_name.argtypes = [C.c_int]
     L.t2s2_timing_class_name.restype = C.c_char_p

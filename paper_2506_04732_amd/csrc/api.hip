@@ -28,6 +28,7 @@ struct t2s2_problem {
 
 namespace t2s2 {
 void timing_set(bool on);
+void timing_select(unsigned mask);
 void timing_read(int cls, double* ms, long* launches, double* bytes, double* flops);
 static thread_local std::string g_last_error;
 void set_last_error(const std::string& msg) { g_last_error = msg; }
@@ -298,6 +299,13 @@ int t2s2_local_solve(int r1, int m, int r2, const double* Lint, const double* K,
 int t2s2_timing_enable(int on) {
   return guarded([&] {
     t2s2::timing_set(on != 0);
+    return T2S2_OK;
+  });
+}
+
+int t2s2_timing_classes(unsigned int mask) {
+  return guarded([&] {
+    t2s2::timing_select(mask);
     return T2S2_OK;
   });
 }

@@ -19,13 +19,13 @@ enum KernelClass {
 // its stream; algorithmic bytes / flops of the launch are accumulated.
 void timing_record_begin(hipStream_t s, int cls, double bytes, double flops);
 void timing_record_end(hipStream_t s);
-bool timing_enabled();
+bool timing_enabled(int cls = -1);  // cls < 0: any class
 
 struct TimedScope {
   hipStream_t s;
   bool on;
   TimedScope(hipStream_t s_, int cls, double bytes, double flops, bool enable = true)
-      : s(s_), on(enable && timing_enabled()) {
+      : s(s_), on(enable && timing_enabled(cls)) {
     if (on) timing_record_begin(s, cls, bytes, flops);
   }
   ~TimedScope() {

@@ -14,6 +14,7 @@ struct Rec {
 };
 struct TimingState {
   bool enabled = false;
+  unsigned mask = ~0u;  // classes recorded while enabled
   std::vector<Rec> done;      // both recorded
   std::vector<hipEvent_t> pool;
   double ms[KC_COUNT] = {0}, bytes[KC_COUNT] = {0}, flops[KC_COUNT] = {0};
@@ -53,7 +54,12 @@ void drain() {
 }
 }  // namespace
 
-bool timing_enabled() { return g_t.enabled; }
+bool timing_enabled(int cls) { return g_t.enabled && (cls < 0 || ((g_t.mask >> cls) & 1u)); }
+
+void timing_select(unsigned mask) {
+  std::lock_guard<std::mutex> lk(g_m);
+  g_t.mask = mask;
+}
 
 void timing_record_begin(hipStream_t s, int cls, double bytes, double flops) {
   std::lock_guard<std::mutex> lk(g_m);
