@@ -100,6 +100,93 @@ __global__ void __launch_bounds__(kNT) chol_skip_kernel(int n, const double* __r
   if (threadIdx.x == 0) count[0] = s_count;
 }
 
+// Register-resident versions for n <= NMAX on one wavefront: lane j holds
+// column j in registers and every other entry it needs is read from the lane
+// that holds it (compile-time lane and row indices after unrolling), so no
+// step waits on LDS or a barrier.  Same arithmetic, in the same order, as the
+// workgroup kernels above and below.
+__device__ inline double rdl(double v, int l) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffLL), l);
+  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int NMAX>
+__global__ void __launch_bounds__(64) chol_skip_reg_kernel(int n, const double* __restrict__ G, double* R,
+                                                          int* __restrict__ mask, int* __restrict__ count,
+                                                          double tau) {
+  const int j = threadIdx.x;
+  double g[NMAX];
+#pragma unroll
+  for (int i = 0; i < NMAX; ++i) g[i] = (i < n && j < n) ? G[i * n + j] : 0.0;
+  double gmax = (j < n) ? G[j * n + j] : 0.0;
+  for (int off = 32; off > 0; off >>= 1) gmax = fmax(gmax, __shfl_xor(gmax, off, 64));
+  int cnt = 0;
+#pragma unroll
+  for (int k = 0; k < NMAX; ++k) {
+    if (k < n) {
+      const double d = rdl(g[k], k);
+      const int keep = (d > tau * gmax) && (d > 0.0) && gmax > 0.0;
+      if (j == 0) mask[k] = keep;
+      cnt += keep;
+      if (!keep) {
+        if (j >= k) g[k] = 0.0;
+      } else {
+        const double piv = sqrt(d);
+        const double inv = 1.0 / piv;
+        if (j > k) g[k] *= inv;
+        if (j == k) g[k] = piv;
+#pragma unroll
+        for (int i = k + 1; i < NMAX; ++i) {
+          if (i < n) {
+            const double rki = rdl(g[k], i);
+            if (j >= i && j < n) g[i] -= rki * g[k];
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NMAX; ++i)
+    if (i < n && j < n) R[i * n + j] = (j < i) ? 0.0 : g[i];
+  if (j == 0) count[0] = cnt;
+}
+
+// lane j computes column j of R^{-1}; the dot products keep the eight
+// strided partial sums and the pairwise combination of the workgroup kernel
+template <int NMAX>
+__global__ void __launch_bounds__(64) trtri_reg_kernel(int n, const double* __restrict__ R,
+                                                      double* __restrict__ Rinv) {
+  const int j = threadIdx.x;
+  double r[NMAX], x[NMAX];
+#pragma unroll
+  for (int i = 0; i < NMAX; ++i) {
+    r[i] = (i < n && j < n) ? R[i * n + j] : 0.0;
+    x[i] = 0.0;
+  }
+#pragma unroll
+  for (int i = NMAX - 1; i >= 0; --i) {
+    if (i < n) {
+      const double rii = rdl(r[i], i);
+      double p[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int t = i + 1; t < NMAX; ++t) {
+        if (t < n) {
+          const double rit = rdl(r[i], t);
+          if (t <= j) p[(t - i - 1) & 7] = fma(rit, x[t], p[(t - i - 1) & 7]);
+        }
+      }
+      const double sm = ((p[0] + p[4]) + (p[2] + p[6])) + ((p[1] + p[5]) + (p[3] + p[7]));
+      if (j == i) x[i] = 1.0 / rii;
+      else if (j > i) x[i] = (-sm) / rii;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NMAX; ++i)
+    if (i < n && j < n) Rinv[i * n + j] = x[i];
+}
+
 // ------------------------------------------------- triangular inverses
 // Rinv = R^{-1} for a nonsingular upper-triangular n x n R (row-major), by
 // rows from the bottom: Rinv[i][j] = -(sum_{t=i+1..j} R[i][t] Rinv[t][j]) / R[i][i].
@@ -790,7 +877,9 @@ void chol_skip(hipStream_t s, int n, const double* G, double* R, int* mask, int*
   T2S2_CHECK(n >= 1 && n <= 4096, "chol_skip: bad size");
   const long need = (long)n * n;
   TimedScope ts(s, KC_CHOL, 16.0 * need, (double)n * n * n / 3.0);
-  if (need <= kLdsDoubles)
+  if (n <= 32)
+    hipLaunchKernelGGL(chol_skip_reg_kernel<32>, dim3(1), dim3(64), 0, s, n, G, R, mask, count, tau);
+  else if (need <= kLdsDoubles)
     hipLaunchKernelGGL(chol_skip_kernel<true>, dim3(1), dim3(kNT), lds_bytes(need), s, n, G, R, mask, count, tau);
   else
     hipLaunchKernelGGL(chol_skip_kernel<false>, dim3(1), dim3(kNT), 0, s, n, G, R, mask, count, tau);
@@ -799,7 +888,10 @@ void chol_skip(hipStream_t s, int n, const double* G, double* R, int* mask, int*
 
 void trtri_upper(hipStream_t s, int n, const double* R, double* Rinv) {
   TimedScope ts(s, KC_TRTRI, 8.0 * n * n, (double)n * n * n / 3.0);
-  hipLaunchKernelGGL(trtri_upper_kernel<double>, dim3(1), dim3(kNT), 0, s, n, R, Rinv);
+  if (n <= 32)
+    hipLaunchKernelGGL(trtri_reg_kernel<32>, dim3(1), dim3(64), 0, s, n, R, Rinv);
+  else
+    hipLaunchKernelGGL(trtri_upper_kernel<double>, dim3(1), dim3(kNT), 0, s, n, R, Rinv);
   T2S2_LAUNCH_CHECK();
 }
 
