@@ -153,6 +153,166 @@ __global__ void __launch_bounds__(64) chol_skip_reg_kernel(int n, const double* 
   if (j == 0) count[0] = cnt;
 }
 
+// Blocked right-looking form of chol_skip_kernel for 32 < n <= 256, columns
+// taken kCholP at a time.  Each panel is one pass in which every wavefront
+// factors the panel's diagonal block in lanes 0..31 (one column per lane; all
+// wavefronts compute the same values) and carries 32 trailing columns
+// through the same steps in lanes 32..63.  At step k the diagonal lanes
+// write their row-k entries to the wavefront's own LDS row, and every lane
+// reads the pivot and the row back (the pivot test is chol_skip_kernel's).
+// The trailing upper triangle then receives the panel's updates in 4 x 4
+// tiles.  Each entry gets the same operations in the same order as in
+// chol_skip_kernel (scaling by the pivot's reciprocal, then one subtraction
+// per earlier kept column, in column order), so R is bitwise identical; the
+// workgroup meets 2 barriers per panel instead of 3 per column.
+// LDS: W holds the matrix (n*n doubles); otherwise W is R in global memory
+// and the panel's rows are copied to LDS for the trailing update.
+constexpr int kCholP = 32;
+constexpr int kCholBlkMax = 256;
+constexpr int kCholNT = 512;  // 8 wavefronts: 8 x 32 trailing columns per panel
+
+// The steps of one panel in one wavefront (see chol_blk_kernel): g holds the
+// lane's column within the panel rows, row is the wavefront's LDS row.  Lanes
+// other than the diagonal block's upper part and the valid trailing columns
+// are updated too (their values are never read or stored), which keeps the
+// steps free of per-lane conditions.  W = kCholP: a full panel (w == kCholP).
+template <int W>
+__device__ __forceinline__ void chol_panel(double (&g)[kCholP], double* row, int w, int lane, bool diag, int wv,
+                                           double tau, double gmax, int* __restrict__ mask, int* s_keep, int& cnt) {
+  if constexpr (W > 0) w = W;
+#pragma unroll
+  for (int k = 0; k < kCholP; ++k) {
+    if (W > 0 || k < w) {
+      if (diag) row[lane] = g[k];
+      __builtin_amdgcn_wave_barrier();
+      const double d = row[k];
+      const int keep = (d > tau * gmax) && (d > 0.0) && gmax > 0.0;
+      if (wv == 0 && lane == 0) {
+        mask[k] = keep;
+        s_keep[k] = keep;
+      }
+      cnt += keep;
+      const bool right = !diag || lane > k;  // entries right of the pivot in row k
+      if (!keep) {
+        if (right || lane == k) g[k] = 0.0;
+      } else {
+        const double piv = sqrt(d);
+        const double inv = 1.0 / piv;
+        g[k] = (diag && lane == k) ? piv : (right ? g[k] * inv : g[k]);
+#pragma unroll
+        for (int i = k + 1; i < kCholP; ++i)
+          if (W > 0 || i < w) g[i] -= (row[i] * inv) * g[k];
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+}
+
+template <bool LDS>
+__global__ void __launch_bounds__(kCholNT) chol_blk_kernel(int n, const double* __restrict__ G, double* R,
+                                                           int* __restrict__ mask, int* __restrict__ count,
+                                                           double tau) {
+  extern __shared__ double lds[];
+  __shared__ double red[kNT / 64];
+  __shared__ double rows[kCholNT / 64][kCholP];  // per wavefront: the current row of the diagonal block
+  __shared__ int s_keep[kCholP];
+  double* W;
+  if constexpr (LDS) W = lds; else W = R;
+  const long nn = (long)n * n;
+  for (long e = threadIdx.x; e < nn; e += blockDim.x) W[e] = G[e];
+  __syncthreads();
+  double dm = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dm = fmax(dm, W[(long)i * n + i]);
+  const double gmax = block_max(dm, red);
+  const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const bool diag = lane < kCholP;
+  int cnt = 0;  // kept columns, tracked by wavefront 0
+  for (int k0 = 0; k0 < n; k0 += kCholP) {
+    const int w = min(kCholP, n - k0);
+    const int c0 = k0 + w;  // first trailing column
+    const int col = diag ? k0 + lane : c0 + kCholP * wv + (lane - kCholP);
+    const bool valid = diag ? lane < w : col < n;
+    double* P;  // row k of the panel at P[k * n + column]
+    if constexpr (LDS) P = W + (long)k0 * n; else P = lds;
+    if (wv == 0 || c0 + kCholP * wv < n) {  // wavefronts with trailing columns, and wavefront 0
+      double g[kCholP];
+#pragma unroll
+      for (int i = 0; i < kCholP; ++i)
+        g[i] = (i < w && valid && (!diag || i <= lane)) ? W[(long)(k0 + i) * n + col] : 0.0;
+      if (w == kCholP)
+        chol_panel<kCholP>(g, rows[wv], kCholP, lane, diag, wv, tau, gmax, mask + k0, s_keep, cnt);
+      else
+        chol_panel<0>(g, rows[wv], w, lane, diag, wv, tau, gmax, mask + k0, s_keep, cnt);
+#pragma unroll
+      for (int i = 0; i < kCholP; ++i) {
+        if (i < w && valid && (!diag || (wv == 0 && i <= lane))) {
+          W[(long)(k0 + i) * n + col] = g[i];
+          if constexpr (!LDS) if (!diag) P[(long)i * n + col] = g[i];
+        }
+      }
+    }
+    __syncthreads();
+    // trailing upper triangle: 4 x 4 tiles (bi <= bj), column-major over the tiles;
+    // the panel's rows are read 4 at a time
+    const int t = n - c0;
+    const int T4 = (t + 3) / 4;
+    const int ntile = T4 * (T4 + 1) / 2;
+    for (int q = threadIdx.x; q < ntile; q += blockDim.x) {
+      int bj = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
+      while (bj * (bj + 1) / 2 > q) --bj;
+      while ((bj + 1) * (bj + 2) / 2 <= q) ++bj;
+      const int bi = q - bj * (bj + 1) / 2;
+      const int i0 = c0 + 4 * bi, j0 = c0 + 4 * bj;
+      double acc[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int i = i0 + a, j = j0 + b;
+          acc[a][b] = (i <= j && j < n) ? W[(long)i * n + j] : 0.0;
+        }
+#pragma unroll
+      for (int k4 = 0; k4 < kCholP; k4 += 4) {
+        if (k4 < w) {
+          double u[4][4], v[4][4];
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+              const bool in = k4 + kk < w;
+              u[kk][a] = (in && i0 + a < n) ? P[(long)(k4 + kk) * n + i0 + a] : 0.0;
+              v[kk][a] = (in && j0 + a < n) ? P[(long)(k4 + kk) * n + j0 + a] : 0.0;
+            }
+          }
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            if (k4 + kk < w && s_keep[k4 + kk]) {
+#pragma unroll
+              for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] -= u[kk][a] * v[kk][b];
+            }
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int i = i0 + a, j = j0 + b;
+          if (i <= j && j < n) W[(long)i * n + j] = acc[a][b];
+        }
+    }
+    __syncthreads();
+  }
+  for (long e = threadIdx.x; e < nn; e += blockDim.x) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    R[e] = (j < i) ? 0.0 : W[e];
+  }
+  if (threadIdx.x == 0) count[0] = cnt;
+}
+
 // lane j computes column j of R^{-1}; the dot products keep the eight
 // strided partial sums and the pairwise combination of the workgroup kernel
 template <int NMAX>
@@ -204,7 +364,10 @@ template <>
 struct TriOps<double2> {
   __device__ static double2 zero() { return make_double2(0.0, 0.0); }
   __device__ static double2 one() { return make_double2(1.0, 0.0); }
-  __device__ static double2 fma(double2 a, double2 b, double2 c) { return cadd(cmul(a, b), c); }
+  // c + a b with explicit fused operations, so every kernel rounds it alike
+  __device__ static double2 fma(double2 a, double2 b, double2 c) {
+    return make_double2(::fma(a.x, b.x, ::fma(-a.y, b.y, c.x)), ::fma(a.x, b.y, ::fma(a.y, b.x, c.y)));
+  }
   __device__ static double2 div(double2 a, double2 b) { return cdiv(a, b); }
   __device__ static double2 neg(double2 a) { return make_double2(-a.x, -a.y); }
 };
@@ -213,7 +376,9 @@ template <>
 struct TriOps<float2> {
   __device__ static float2 zero() { return make_float2(0.0f, 0.0f); }
   __device__ static float2 one() { return make_float2(1.0f, 0.0f); }
-  __device__ static float2 fma(float2 a, float2 b, float2 c) { return cadd(cmul(a, b), c); }
+  __device__ static float2 fma(float2 a, float2 b, float2 c) {
+    return make_float2(fmaf(a.x, b.x, fmaf(-a.y, b.y, c.x)), fmaf(a.x, b.y, fmaf(a.y, b.x, c.y)));
+  }
   __device__ static float2 div(float2 a, float2 b) { return cdiv(a, b); }
   __device__ static float2 neg(float2 a) { return make_float2(-a.x, -a.y); }
 };
@@ -262,6 +427,118 @@ __global__ void __launch_bounds__(kNT) trtri_upper_kernel(int n, const T* __rest
     }
     __syncthreads();
   }
+}
+
+// The columns of R^{-1} are independent, so for n <= kTriColMax each group of
+// kTriG lanes of a one-wavefront workgroup computes one column on its own,
+// without barriers: workgroup b owns columns kTriG b .. kTriG b + kTriG - 1.
+// Lane s of a group keeps the entries x[t] of its column with t = s (mod kTriG)
+// in registers.  For row i the lane's partial sum runs over the same terms in
+// the same order as lane (s - i - 1) mod kTriG of the workgroup kernel, and
+// the xor butterfly pairs the same partial sums, so every entry is bitwise
+// identical to that kernel's (for finite R).  Rows of R are staged in LDS kTriG at a time
+// (the row block and the columns up to the group's last one); the next block
+// is loaded into registers while the current one is used.
+constexpr int kTriColMax = 256;
+constexpr int kTriColBlocks = kTriColMax / kTriG;
+
+// one row block MI of trtri_col_kernel, then the blocks above it
+// register slots for the next row block's entries (the rest is loaded when staged)
+template <class T>
+constexpr int tri_col_slots() { return sizeof(T) > 8 ? kTriColBlocks / 2 : kTriColBlocks; }
+
+template <class T, int MI>
+__device__ __forceinline__ void trtri_col_block(int n, int B, int j, int s, int lr, int lc, const T* __restrict__ R,
+                                                T* __restrict__ Rinv, T* tile, T (&x)[kTriColBlocks],
+                                                T (&pre)[tri_col_slots<T>()]) {
+  if constexpr (MI >= 0) {
+    using O = TriOps<T>;
+    constexpr int MB = kTriColBlocks, LD = kTriColMax;
+    if (MI <= B) {
+      if constexpr (MI > 0) {
+        const int row = kTriG * (MI - 1) + lr;
+#pragma unroll
+        for (int q = 0; q <= MB - MI && q < tri_col_slots<T>(); ++q) {
+          const int col = kTriG * (MI - 1 + q) + lc;
+          if (q <= B - MI + 1) pre[q] = (row < n && col < n) ? R[(long)row * n + col] : O::zero();
+        }
+      }
+      for (int r = kTriG - 1; r >= 0; --r) {
+        const int i = kTriG * MI + r;
+        if (i >= n) continue;
+        // the row's entries are read CH at a time, all in flight before the
+        // fused steps.  Terms outside i < t <= j need no test: their x[t] is
+        // still exactly zero (rows past the column's last are never set, rows
+        // up to i not yet), the staged entries are finite (the tile starts
+        // zeroed), and the partial sum starts at +0 so it can never become -0:
+        // adding such a term leaves it bitwise unchanged.
+        constexpr int CH = sizeof(T) > 8 ? 4 : 8;
+        T p = O::zero();
+#pragma unroll
+        for (int m0 = MI; m0 < MB; m0 += CH) {
+          if (m0 <= B) {
+            T a[CH];
+#pragma unroll
+            for (int u = 0; u < CH; ++u)
+              if (m0 + u < MB) a[u] = tile[r * LD + s + kTriG * (m0 + u - MI)];
+#pragma unroll
+            for (int u = 0; u < CH; ++u)
+              if (m0 + u < MB) p = O::fma(a[u], x[m0 + u], p);
+          }
+        }
+        for (int off = kTriG / 2; off > 0; off >>= 1) p = tadd<T>(p, shfl_xor_t<T>(p, off, kTriG));
+        const T rii = tile[r * LD + r];
+        if (i <= j) {
+          const T xi = (i == j) ? O::div(O::one(), rii) : O::div(O::neg(p), rii);
+          if (s == r) x[MI] = xi;
+          if (s == 0) Rinv[(long)i * n + j] = xi;
+        }
+      }
+      if constexpr (MI > 0) {
+        __syncthreads();
+        const int row = kTriG * (MI - 1) + lr;
+#pragma unroll
+        for (int q = 0; q <= MB - MI; ++q) {
+          if (q <= B - MI + 1) {
+            if (q < tri_col_slots<T>()) {
+              tile[lr * LD + kTriG * q + lc] = pre[q];
+            } else {
+              const int col = kTriG * (MI - 1 + q) + lc;
+              tile[lr * LD + kTriG * q + lc] = (row < n && col < n) ? R[(long)row * n + col] : O::zero();
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    trtri_col_block<T, MI - 1>(n, B, j, s, lr, lc, R, Rinv, tile, x, pre);
+  }
+}
+
+template <class T>
+__global__ void __launch_bounds__(64) trtri_col_kernel(int n, const T* __restrict__ R, T* __restrict__ Rinv) {
+  using O = TriOps<T>;
+  __shared__ T tile[kTriG * kTriColMax];
+  const int lane = threadIdx.x, s = lane % kTriG;
+  const int B = blockIdx.x;                // last row block this workgroup needs
+  const int j0 = kTriG * B + lane / kTriG;
+  const int j = (j0 < n) ? j0 : -1;        // -1: a group past the last column
+  for (int i = j0 + 1 + s; i < n && j >= 0; i += kTriG) Rinv[(long)i * n + j] = O::zero();
+  // staging: lane l holds row kTriG mi + l / kTriG, columns kTriG (mi + q) + l % kTriG
+  const int lr = lane / kTriG, lc = lane % kTriG;
+  for (int e = lane; e < kTriG * kTriColMax; e += 64) tile[e] = O::zero();
+  __syncthreads();
+  T pre[tri_col_slots<T>()];
+  T x[kTriColBlocks];
+#pragma unroll
+  for (int m = 0; m < kTriColBlocks; ++m) x[m] = O::zero();
+  {
+    const int row = kTriG * B + lr;
+    const int col = kTriG * B + lc;
+    tile[lr * kTriColMax + lc] = (row < n && col < n) ? R[(long)row * n + col] : O::zero();
+  }
+  __syncthreads();
+  trtri_col_block<T, kTriColBlocks - 1>(n, B, j, s, lr, lc, R, Rinv, tile, x, pre);
 }
 
 // ------------------------------------------------ one-sided Jacobi SVD
@@ -879,6 +1156,12 @@ void chol_skip(hipStream_t s, int n, const double* G, double* R, int* mask, int*
   TimedScope ts(s, KC_CHOL, 16.0 * need, (double)n * n * n / 3.0);
   if (n <= 32)
     hipLaunchKernelGGL(chol_skip_reg_kernel<32>, dim3(1), dim3(64), 0, s, n, G, R, mask, count, tau);
+  else if (n <= kCholBlkMax && need + kCholP * kCholP <= kLdsDoubles)
+    hipLaunchKernelGGL(chol_blk_kernel<true>, dim3(1), dim3(kCholNT), need * sizeof(double), s, n, G, R, mask, count,
+                       tau);
+  else if (n <= kCholBlkMax)
+    hipLaunchKernelGGL(chol_blk_kernel<false>, dim3(1), dim3(kCholNT), (size_t)kCholP * n * sizeof(double), s, n, G, R,
+                       mask, count, tau);
   else if (need <= kLdsDoubles)
     hipLaunchKernelGGL(chol_skip_kernel<true>, dim3(1), dim3(kNT), lds_bytes(need), s, n, G, R, mask, count, tau);
   else
@@ -886,24 +1169,32 @@ void chol_skip(hipStream_t s, int n, const double* G, double* R, int* mask, int*
   T2S2_LAUNCH_CHECK();
 }
 
+template <class T>
+static void trtri_launch(hipStream_t s, int n, const T* R, T* Rinv) {
+  if (n <= kTriColMax)
+    hipLaunchKernelGGL(trtri_col_kernel<T>, dim3((n + kTriG - 1) / kTriG), dim3(64), 0, s, n, R, Rinv);
+  else
+    hipLaunchKernelGGL(trtri_upper_kernel<T>, dim3(1), dim3(kNT), 0, s, n, R, Rinv);
+}
+
 void trtri_upper(hipStream_t s, int n, const double* R, double* Rinv) {
   TimedScope ts(s, KC_TRTRI, 8.0 * n * n, (double)n * n * n / 3.0);
   if (n <= 32)
     hipLaunchKernelGGL(trtri_reg_kernel<32>, dim3(1), dim3(64), 0, s, n, R, Rinv);
   else
-    hipLaunchKernelGGL(trtri_upper_kernel<double>, dim3(1), dim3(kNT), 0, s, n, R, Rinv);
+    trtri_launch(s, n, R, Rinv);
   T2S2_LAUNCH_CHECK();
 }
 
 void trtri_upper(hipStream_t s, int n, const double2* R, double2* Rinv) {
   TimedScope ts(s, KC_TRTRI, 16.0 * n * n, 4.0 * n * n * n / 3.0);
-  hipLaunchKernelGGL(trtri_upper_kernel<double2>, dim3(1), dim3(kNT), 0, s, n, R, Rinv);
+  trtri_launch(s, n, R, Rinv);
   T2S2_LAUNCH_CHECK();
 }
 
 void trtri_upper(hipStream_t s, int n, const float2* R, float2* Rinv) {
   TimedScope ts(s, KC_TRTRI, 8.0 * n * n, 4.0 * n * n * n / 3.0);
-  hipLaunchKernelGGL(trtri_upper_kernel<float2>, dim3(1), dim3(kNT), 0, s, n, R, Rinv);
+  trtri_launch(s, n, R, Rinv);
   T2S2_LAUNCH_CHECK();
 }
 
