@@ -20,6 +20,8 @@ constexpr int kNT = 1024;          // threads of the single workgroup
 constexpr long kLdsDoubles = 20000;  // LDS budget of these kernels (160000 B)
 constexpr long kLdsBytes = 160000;
 constexpr int kJacG = 16;            // Jacobi: lanes per row pair
+constexpr int kJacBG = 16;           // block Jacobi: lanes per row pair (32 measured slower)
+constexpr int kJacBR = 16;           // block Jacobi: row entries per lane (c <= kJacBR kJacBG)
 
 template <class R> struct TinyOf;   // a safe "negligible" magnitude
 template <> struct TinyOf<double> { static constexpr double value = 1e-290; };
@@ -39,6 +41,25 @@ __device__ inline double block_max(double v, double* red) {
   for (int i = 1; i < (int)(blockDim.x / 64); ++i) r = fmax(r, red[i]);
   __syncthreads();
   return r;
+}
+
+// Sum over each aligned group of 16 lanes (a DPP row), left in every lane of
+// the group, by data-parallel-primitive moves (VALU, no LDS round trip):
+// swap with the xor-1 and xor-2 neighbours in the quad, then with the
+// mirrored lane in the half row and in the row.
+template <int CTRL>
+__device__ inline double dpp_f64(double v) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(u & 0xffffffffLL), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ inline double row16_sum(double v) {
+  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141>(v);  // row_half_mirror
+  v += dpp_f64<0x140>(v);  // row_mirror
+  return v;
 }
 
 // ------------------------------------------------------------ Cholesky
@@ -638,11 +659,10 @@ __global__ void __launch_bounds__(kNT) jacobi_rows_kernel(int k, int c, double* 
           b = fma(y, y, b);
           g = fma(x, y, g);
         }
-        for (int off = kJacG / 2; off > 0; off >>= 1) {
-          a += __shfl_xor(a, off, kJacG);
-          b += __shfl_xor(b, off, kJacG);
-          g += __shfl_xor(g, off, kJacG);
-        }
+        static_assert(kJacG == 16, "row16_sum reduces over 16 lanes");
+        a = row16_sum(a);
+        b = row16_sum(b);
+        g = row16_sum(g);
         if (g == 0.0 || fabs(g) <= tol * sqrt(a * b)) continue;
         const double zeta = (b - a) / (2.0 * g);
         const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
@@ -672,25 +692,32 @@ __global__ void __launch_bounds__(kNT) jacobi_rows_kernel(int k, int c, double* 
 
 // One-sided Jacobi for matrices beyond LDS (block Jacobi).  The rows of B
 // (k x c) and of the rotation accumulator JT (k x k) are split into blocks of
-// bsz rows; in round `round` the blocks are paired round-robin (nplay
-// players, a bye when the block count is odd) and one workgroup per pair
-// loads the rows of B of both blocks into LDS and runs one Jacobi sweep over
-// all row pairs of the union, accumulating its rotations in a small
-// rows x rows matrix Jl; the B rows are written back and JT's rows of the
-// pair are replaced by Jl times them.  Each lane keeps its share of a row
-// pair in registers between the dot products and the rotation (c <= NR
-// kJacG).  counter accumulates the rotations.
-template <int NR>
+// bsz rows.  A sweep is one launch in which workgroup b sweeps the row pairs
+// inside block b (cross = 0, round-robin over its rows), then one launch per
+// round of a round-robin pairing of the blocks (nplay players, a bye when the
+// block count is odd) in which one workgroup per block pair (P, Q) rotates
+// only the pairs between them (cross = 1: max(pn, qn) rounds of disjoint
+// pairs, row i of P with row (i + round) mod max(pn, qn) of Q).  Every row
+// pair is thus rotated once per sweep, as in cyclic Jacobi.  A workgroup
+// loads its rows of B into LDS, accumulates its rotations in a small
+// rows x rows matrix Jl, writes the B rows back and replaces its JT rows by
+// Jl times them.  Each lane keeps its share of a row pair in registers
+// between the dot products and the rotation (LG lanes per pair, c <= NR LG).  counter
+// accumulates the rotations.
+template <int NR, int LG>
 __global__ void __launch_bounds__(kNT) jacobi_block_kernel(int k, int c, double* __restrict__ B,
                                                            double* __restrict__ JT, int bsz, int nblk, int nplay,
-                                                           int round, int* __restrict__ counter) {
+                                                           int round, int cross, int* __restrict__ counter) {
   extern __shared__ double lds[];
   __shared__ int s_rot;
-  const int s1 = blockIdx.x, s2 = nplay - 1 - blockIdx.x;
-  const int P = (s1 == 0) ? 0 : ((s1 - 1 + round) % (nplay - 1)) + 1;
-  const int Q = (s2 == 0) ? 0 : ((s2 - 1 + round) % (nplay - 1)) + 1;
+  int P = blockIdx.x, Q = blockIdx.x;
+  if (cross) {
+    const int s1 = blockIdx.x, s2 = nplay - 1 - blockIdx.x;
+    P = (s1 == 0) ? 0 : ((s1 - 1 + round) % (nplay - 1)) + 1;
+    Q = (s2 == 0) ? 0 : ((s2 - 1 + round) % (nplay - 1)) + 1;
+  }
   if (P >= nblk || Q >= nblk) return;  // bye
-  const int p0 = P * bsz, pn = min(bsz, k - p0), q0 = Q * bsz, qn = min(bsz, k - q0);
+  const int p0 = P * bsz, pn = min(bsz, k - p0), q0 = Q * bsz, qn = cross ? min(bsz, k - q0) : 0;
   const int rows = pn + qn;
   double* Bw = lds;                     // rows x c (later: the old JT rows, rows x k, k <= c)
   double* Jl = lds + (long)rows * c;    // rows x rows
@@ -703,18 +730,29 @@ __global__ void __launch_bounds__(kNT) jacobi_block_kernel(int k, int c, double*
   if (threadIdx.x == 0) s_rot = 0;
   __syncthreads();
   const int RP = rows + (rows & 1);
-  const int grp = threadIdx.x / kJacG, sub = threadIdx.x % kJacG, ngrp = blockDim.x / kJacG;
+  const int MQ = max(pn, qn);
+  const int nrounds = cross ? MQ : RP - 1, npairs = cross ? pn : RP / 2;
+  const int grp = threadIdx.x / LG, sub = threadIdx.x % LG, ngrp = blockDim.x / LG;
   const double tol = 1e-10;
-  for (int rr = 0; rr < RP - 1; ++rr) {
-    for (int pi = grp; pi < RP / 2; pi += ngrp) {
-      const int t1 = pi, t2 = RP - 1 - pi;
-      int p = (t1 == 0) ? 0 : ((t1 - 1 + rr) % (RP - 1)) + 1;
-      int q = (t2 == 0) ? 0 : ((t2 - 1 + rr) % (RP - 1)) + 1;
-      if (p >= rows || q >= rows) continue;
-      if (p > q) {
-        const int t = p;
-        p = q;
-        q = t;
+  for (int rr = 0; rr < nrounds; ++rr) {
+    for (int pi = grp; pi < npairs; pi += ngrp) {
+      int p, q;
+      if (cross) {
+        // row pi of block P with row (pi + rr) mod MQ of block Q
+        p = pi;
+        q = (pi + rr) % MQ;
+        if (q >= qn) continue;
+        q += pn;
+      } else {
+        const int t1 = pi, t2 = RP - 1 - pi;
+        p = (t1 == 0) ? 0 : ((t1 - 1 + rr) % (RP - 1)) + 1;
+        q = (t2 == 0) ? 0 : ((t2 - 1 + rr) % (RP - 1)) + 1;
+        if (p >= rows || q >= rows) continue;
+        if (p > q) {
+          const int t = p;
+          p = q;
+          q = t;
+        }
       }
       double* bp = Bw + (long)p * c;
       double* bq = Bw + (long)q * c;
@@ -722,17 +760,23 @@ __global__ void __launch_bounds__(kNT) jacobi_block_kernel(int k, int c, double*
       double a = 0.0, b = 0.0, g = 0.0;
 #pragma unroll
       for (int u = 0; u < NR; ++u) {
-        const int e = sub + u * kJacG;
+        const int e = sub + u * LG;
         xs[u] = (e < c) ? bp[e] : 0.0;
         ys[u] = (e < c) ? bq[e] : 0.0;
         a = fma(xs[u], xs[u], a);
         b = fma(ys[u], ys[u], b);
         g = fma(xs[u], ys[u], g);
       }
-      for (int off = kJacG / 2; off > 0; off >>= 1) {
-        a += __shfl_xor(a, off, kJacG);
-        b += __shfl_xor(b, off, kJacG);
-        g += __shfl_xor(g, off, kJacG);
+      if constexpr (LG == 16) {
+        a = row16_sum(a);
+        b = row16_sum(b);
+        g = row16_sum(g);
+      } else {
+        for (int off = LG / 2; off > 0; off >>= 1) {
+          a += __shfl_xor(a, off, LG);
+          b += __shfl_xor(b, off, LG);
+          g += __shfl_xor(g, off, LG);
+        }
       }
       if (g == 0.0 || fabs(g) <= tol * sqrt(a * b)) continue;
       const double zeta = (b - a) / (2.0 * g);
@@ -740,7 +784,7 @@ __global__ void __launch_bounds__(kNT) jacobi_block_kernel(int k, int c, double*
       const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
 #pragma unroll
       for (int u = 0; u < NR; ++u) {
-        const int e = sub + u * kJacG;
+        const int e = sub + u * LG;
         if (e < c) {
           bp[e] = cs * xs[u] - sn * ys[u];
           bq[e] = sn * xs[u] + cs * ys[u];
@@ -748,7 +792,7 @@ __global__ void __launch_bounds__(kNT) jacobi_block_kernel(int k, int c, double*
       }
       double* jp = Jl + (long)p * rows;
       double* jq = Jl + (long)q * rows;
-      for (int e = sub; e < rows; e += kJacG) {
+      for (int e = sub; e < rows; e += LG) {
         const double x = jp[e], y = jq[e];
         jp[e] = cs * x - sn * y;
         jq[e] = sn * x + cs * y;
@@ -1210,7 +1254,7 @@ void jacobi_rows(hipStream_t s, int k, int c, double* B, double* JT, double* U, 
   int blk = 1;
   while (2L * (blk + 1) * c + 4L * (blk + 1) * (blk + 1) <= kLdsDoubles) ++blk;
   blk = std::min(blk, std::max(2, (k + 7) / 8));
-  if (need < bsz + jsz && k <= c && c <= 16 * kJacG && blk >= 2 && (k + blk - 1) / blk >= 3) {
+  if (need < bsz + jsz && k <= c && c <= kJacBR * kJacBG && blk >= 2 && (k + blk - 1) / blk >= 3) {
     TimedScope ts(s, KC_JACOBI, 8.0 * (2.0 * bsz + 2.0 * jsz), 0.0);
     const int nblk = (k + blk - 1) / blk, nplay = nblk + (nblk & 1);
     const size_t lds = (size_t)(2L * blk * c + 4L * blk * blk) * sizeof(double);
@@ -1218,9 +1262,11 @@ void jacobi_rows(hipStream_t s, int k, int c, double* B, double* JT, double* U, 
     int sweep = 0;
     for (; sweep < max_sweeps; ++sweep) {
       hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, s, info, 0);
+      hipLaunchKernelGGL((jacobi_block_kernel<kJacBR, kJacBG>), dim3(nblk), dim3(kNT), lds, s, k, c, B, JT, blk,
+                         nblk, nplay, 0, 0, info);
       for (int round = 0; round < nplay - 1; ++round)
-        hipLaunchKernelGGL(jacobi_block_kernel<16>, dim3(nplay / 2), dim3(kNT), lds, s, k, c, B, JT, blk, nblk,
-                           nplay, round, info);
+        hipLaunchKernelGGL((jacobi_block_kernel<kJacBR, kJacBG>), dim3(nplay / 2), dim3(kNT), lds, s, k, c, B, JT,
+                           blk, nblk, nplay, round, 1, info);
       T2S2_LAUNCH_CHECK();
       int rot = 0;
       T2S2_HIP(hipMemcpyAsync(&rot, info, sizeof(int), hipMemcpyDeviceToHost, s));
