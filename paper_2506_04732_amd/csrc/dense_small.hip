@@ -48,17 +48,22 @@ __device__ inline double block_max(double v, double* red) {
 // swap with the xor-1 and xor-2 neighbours in the quad, then with the
 // mirrored lane in the half row and in the row.
 template <int CTRL>
-__device__ inline double dpp_f64(double v) {
+__device__ inline double dpp_move(double v) {
   const long long u = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_update_dpp(0, (int)(u & 0xffffffffLL), CTRL, 0xF, 0xF, true);
   const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, 0xF, 0xF, true);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
-__device__ inline double row16_sum(double v) {
-  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
-  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
-  v += dpp_f64<0x141>(v);  // row_half_mirror
-  v += dpp_f64<0x140>(v);  // row_mirror
+template <int CTRL>
+__device__ inline float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+template <class T>
+__device__ inline T row16_sum(T v) {
+  v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_move<0x141>(v);  // row_half_mirror
+  v += dpp_move<0x140>(v);  // row_mirror
   return v;
 }
 
@@ -131,6 +136,16 @@ __device__ inline double rdl(double v, int l) {
   const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffLL), l);
   const int hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ inline float rdl(float v, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)); }
+
+// sum over the wavefront, in every lane: DPP sums of the four 16-lane rows,
+// then the rows' sums read from lanes 0, 16, 32 and 48
+template <class T>
+__device__ inline T wave_sum64(T v) {
+  v = row16_sum(v);
+  return (rdl(v, 0) + rdl(v, 16)) + (rdl(v, 32) + rdl(v, 48));
 }
 
 template <int NMAX>
@@ -898,7 +913,7 @@ __global__ void __launch_bounds__(kNT) hessenberg_kernel(int n, R* __restrict__ 
       v[i] = x;
       s = fma(x, x, s);
     }
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    s = wave_sum64(s);
     __syncthreads();
     if (lane == 0) red[wave] = s;
     __syncthreads();
@@ -935,7 +950,7 @@ __global__ void __launch_bounds__(kNT) hessenberg_kernel(int n, R* __restrict__ 
     for (int i = wave; i < n; i += nwave) {
       R d = R(0.0);
       for (int j = k + 1 + lane; j < n; j += 64) d = fma(H[(long)i * n + j], v[j], d);
-      for (int off = 32; off > 0; off >>= 1) d += __shfl_xor(d, off, 64);
+      d = wave_sum64(d);
       if (lane == 0) w[i] = beta * d;
     }
     __syncthreads();
@@ -1036,7 +1051,7 @@ __global__ void __launch_bounds__(kNT) hess_global_kernel(int n, double* __restr
       v[i] = x;
       ss = fma(x, x, ss);
     }
-    for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
+    ss = wave_sum64(ss);
     if (lane == 0) red[wave] = ss;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1090,10 +1105,8 @@ __global__ void __launch_bounds__(kNT) hess_global_kernel(int n, double* __restr
           tp[r] = fma(hv[r][q], vj[q], tp[r]);
         }
       }
-      for (int off = 32; off > 0; off >>= 1) {
 #pragma unroll
-        for (int r = 0; r < kHgRows; ++r) tp[r] += __shfl_xor(tp[r], off, 64);
-      }
+      for (int r = 0; r < kHgRows; ++r) tp[r] = wave_sum64(tp[r]);
       if (lane == 0) {
 #pragma unroll
         for (int r = 0; r < kHgRows; ++r)
@@ -1114,7 +1127,7 @@ __global__ void __launch_bounds__(kNT) hess_global_kernel(int n, double* __restr
     // c = v^T t
     double cc = 0.0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) cc = fma(v[i], t[i], cc);
-    for (int off = 32; off > 0; off >>= 1) cc += __shfl_xor(cc, off, 64);
+    cc = wave_sum64(cc);
     if (lane == 0) red[wave] = cc;
     __syncthreads();
     if (threadIdx.x == 0) {
