@@ -465,6 +465,28 @@ __global__ void __launch_bounds__(kNT) trtri_upper_kernel(int n, const T* __rest
   }
 }
 
+// The value of lane L ^ X (X = 1, 2, 4) within aligned groups of 8 lanes, by
+// DPP moves: xor 1 and xor 2 are quad permutations; xor 4 is the half-row
+// mirror (L -> L ^ 7) followed by the quad reversal (L -> L ^ 3).  Pure data
+// movement, so a butterfly built on it gives the same bits as one built on
+// __shfl_xor.
+template <int X>
+__device__ inline double xor8_move(double v) {
+  if constexpr (X == 1) return dpp_move<0xB1>(v);
+  else if constexpr (X == 2) return dpp_move<0x4E>(v);
+  else return dpp_move<0x1B>(dpp_move<0x141>(v));
+}
+template <int X>
+__device__ inline float xor8_move(float v) {
+  if constexpr (X == 1) return dpp_move<0xB1>(v);
+  else if constexpr (X == 2) return dpp_move<0x4E>(v);
+  else return dpp_move<0x1B>(dpp_move<0x141>(v));
+}
+template <int X>
+__device__ inline double2 xor8_move(double2 v) { return make_double2(xor8_move<X>(v.x), xor8_move<X>(v.y)); }
+template <int X>
+__device__ inline float2 xor8_move(float2 v) { return make_float2(xor8_move<X>(v.x), xor8_move<X>(v.y)); }
+
 // The columns of R^{-1} are independent, so for n <= kTriColMax each group of
 // kTriG lanes of a one-wavefront workgroup computes one column on its own,
 // without barriers: workgroup b owns columns kTriG b .. kTriG b + kTriG - 1.
@@ -472,17 +494,18 @@ __global__ void __launch_bounds__(kNT) trtri_upper_kernel(int n, const T* __rest
 // in registers.  For row i the lane's partial sum runs over the same terms in
 // the same order as lane (s - i - 1) mod kTriG of the workgroup kernel, and
 // the xor butterfly pairs the same partial sums, so every entry is bitwise
-// identical to that kernel's (for finite R).  Rows of R are staged in LDS kTriG at a time
-// (the row block and the columns up to the group's last one); the next block
-// is loaded into registers while the current one is used.
+// identical to that kernel's (for finite R; the butterfly moves data by DPP
+// instead of shuffles).  Rows of R are staged in LDS kTriG at a time (the row
+// block and the columns up to the group's last one); the next block is
+// loaded into registers while the current one is used.
 constexpr int kTriColMax = 256;
 constexpr int kTriColBlocks = kTriColMax / kTriG;
 
-// one row block MI of trtri_col_kernel, then the blocks above it
 // register slots for the next row block's entries (the rest is loaded when staged)
 template <class T>
 constexpr int tri_col_slots() { return sizeof(T) > 8 ? kTriColBlocks / 2 : kTriColBlocks; }
 
+// one row block MI of trtri_col_kernel, then the blocks above it
 template <class T, int MI>
 __device__ __forceinline__ void trtri_col_block(int n, int B, int j, int s, int lr, int lc, const T* __restrict__ R,
                                                 T* __restrict__ Rinv, T* tile, T (&x)[kTriColBlocks],
@@ -522,7 +545,9 @@ __device__ __forceinline__ void trtri_col_block(int n, int B, int j, int s, int 
               if (m0 + u < MB) p = O::fma(a[u], x[m0 + u], p);
           }
         }
-        for (int off = kTriG / 2; off > 0; off >>= 1) p = tadd<T>(p, shfl_xor_t<T>(p, off, kTriG));
+        p = tadd<T>(p, xor8_move<4>(p));
+        p = tadd<T>(p, xor8_move<2>(p));
+        p = tadd<T>(p, xor8_move<1>(p));
         const T rii = tile[r * LD + r];
         if (i <= j) {
           const T xi = (i == j) ? O::div(O::one(), rii) : O::div(O::neg(p), rii);
@@ -578,6 +603,40 @@ __global__ void __launch_bounds__(64) trtri_col_kernel(int n, const T* __restric
 }
 
 // ------------------------------------------------ one-sided Jacobi SVD
+// 1/x from the hardware estimate refined by two Newton steps (full FP64
+// accuracy for finite nonzero x), and 1/sqrt(x) likewise for x in [1, 2]
+__device__ inline double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ inline double rsq_nr12(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * fma(-0.5 * x, y * y, 1.5);
+  return y * fma(-0.5 * x, y * y, 1.5);
+}
+
+// Rotation (cs, sn), rows (x, y) -> (cs x - sn y, sn x + cs y), that makes
+// two rows with squared norms a, b and inner product g orthogonal (the
+// smaller of the two angles); false when |g| <= tol sqrt(a b) or the angle
+// is below 1e-300.  The reciprocals come from refined hardware estimates:
+// the rotation has to be orthogonal to working precision, not correctly
+// rounded, and the shorter dependent chain is most of a Jacobi round's
+// latency.
+__device__ inline bool jacobi_rotation(double a, double b, double g, double tol, double& cs, double& sn) {
+  if (g == 0.0 || g * g <= (tol * tol) * (a * b)) return false;
+  const double zeta = (b - a) * rcp_nr(2.0 * g);
+  const double d = fabs(zeta) + sqrt(fma(zeta, zeta, 1.0));  // >= 1
+  if (!(d < 1e300)) return false;  // angle below 1e-300 (or g at underflow): nothing to rotate
+  const double ta = rcp_nr(d);
+  const double t = (zeta >= 0.0) ? ta : -ta;
+  cs = rsq_nr12(fma(t, t, 1.0));
+  sn = cs * t;
+  return true;
+}
+
 // Row norms of the rotated B (k x c), rows ranked by decreasing norm (ties by
 // index) and scattered: Wt (sorted rows), U (column dest(i) = row i of JT),
 // sigma (sorted norms); info[0] = sweeps, info[1..k] scratch.
@@ -678,10 +737,8 @@ __global__ void __launch_bounds__(kNT) jacobi_rows_kernel(int k, int c, double* 
         a = row16_sum(a);
         b = row16_sum(b);
         g = row16_sum(g);
-        if (g == 0.0 || fabs(g) <= tol * sqrt(a * b)) continue;
-        const double zeta = (b - a) / (2.0 * g);
-        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+        double cs, sn;
+        if (!jacobi_rotation(a, b, g, tol, cs, sn)) continue;
         for (int e = sub; e < c; e += kJacG) {
           const double x = bp[e], y = bq[e];
           bp[e] = cs * x - sn * y;
@@ -793,10 +850,8 @@ __global__ void __launch_bounds__(kNT) jacobi_block_kernel(int k, int c, double*
           g += __shfl_xor(g, off, LG);
         }
       }
-      if (g == 0.0 || fabs(g) <= tol * sqrt(a * b)) continue;
-      const double zeta = (b - a) / (2.0 * g);
-      const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-      const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+      double cs, sn;
+      if (!jacobi_rotation(a, b, g, tol, cs, sn)) continue;
 #pragma unroll
       for (int u = 0; u < NR; ++u) {
         const int e = sub + u * LG;
