@@ -11,6 +11,7 @@
 #include "dense_small.h"
 
 #include <cfloat>
+#include <cstring>
 
 namespace t2s2 {
 
@@ -637,6 +638,19 @@ __device__ inline bool jacobi_rotation(double a, double b, double g, double tol,
   return true;
 }
 
+// Sweeps stop once no pair had a squared cosine g^2 / (a b) above kJacStop2
+// (cosine 1e-4) before its rotation: one-sided Jacobi converges
+// quadratically, so the cosines left are ~1e-8.  B = U Wt stays exact (U is a
+// product of rotations) and the error of dropping rows of Wt is their norm
+// whatever their orthogonality, so what is left only makes the kept rows
+// marginally less than optimal; a further sweep would rotate next to nothing.
+constexpr float kJacStop2 = 1e-8f;
+// g^2 / (a b) as the bits of a non-negative float (ordered like ints)
+__device__ inline int cos2_bits(double a, double b, double g) {
+  const double ab = a * b;
+  return __float_as_int(ab > 0.0 ? (float)((g * g) * rcp_nr(ab)) : 0.0f);
+}
+
 // Row norms of the rotated B (k x c), rows ranked by decreasing norm (ties by
 // index) and scattered: Wt (sorted rows), U (column dest(i) = row i of JT),
 // sigma (sorted norms); info[0] = sweeps, info[1..k] scratch.
@@ -694,7 +708,7 @@ __global__ void __launch_bounds__(kNT) jacobi_rows_kernel(int k, int c, double* 
                                                           double* __restrict__ Wt, double* __restrict__ sigma,
                                                           int* __restrict__ info, int max_sweeps) {
   extern __shared__ double lds[];
-  __shared__ int s_rot;
+  __shared__ int s_rot, s_cmax;
   const long bsz = (long)k * c, jsz = (long)k * k;
   double* Bw;
   double* Jw;
@@ -714,7 +728,10 @@ __global__ void __launch_bounds__(kNT) jacobi_rows_kernel(int k, int c, double* 
   const double tol = 1e-10;
   int sweep = 0;
   for (; sweep < max_sweeps; ++sweep) {
-    if (threadIdx.x == 0) s_rot = 0;
+    if (threadIdx.x == 0) {
+      s_rot = 0;
+      s_cmax = 0;
+    }
     __syncthreads();
     for (int round = 0; round < K - 1; ++round) {
       for (int pi = grp; pi < npairs; pi += ngrp) {
@@ -737,6 +754,7 @@ __global__ void __launch_bounds__(kNT) jacobi_rows_kernel(int k, int c, double* 
         a = row16_sum(a);
         b = row16_sum(b);
         g = row16_sum(g);
+        if (sub == 0) atomicMax(&s_cmax, cos2_bits(a, b, g));
         double cs, sn;
         if (!jacobi_rotation(a, b, g, tol, cs, sn)) continue;
         for (int e = sub; e < c; e += kJacG) {
@@ -756,8 +774,9 @@ __global__ void __launch_bounds__(kNT) jacobi_rows_kernel(int k, int c, double* 
       __syncthreads();
     }
     const int rot = s_rot;
+    const float cmax = __int_as_float(s_cmax);
     __syncthreads();
-    if (rot == 0) break;
+    if (rot == 0 || cmax <= kJacStop2) break;
   }
   jacobi_finish(k, c, Bw, Jw, U, Wt, sigma, info, sweep);
 }
@@ -781,7 +800,7 @@ __global__ void __launch_bounds__(kNT) jacobi_block_kernel(int k, int c, double*
                                                            double* __restrict__ JT, int bsz, int nblk, int nplay,
                                                            int round, int cross, int* __restrict__ counter) {
   extern __shared__ double lds[];
-  __shared__ int s_rot;
+  __shared__ int s_rot, s_cmax;
   int P = blockIdx.x, Q = blockIdx.x;
   if (cross) {
     const int s1 = blockIdx.x, s2 = nplay - 1 - blockIdx.x;
@@ -799,7 +818,10 @@ __global__ void __launch_bounds__(kNT) jacobi_block_kernel(int k, int c, double*
     Bw[e] = B[(long)grow(r) * c + col];
   }
   for (int e = threadIdx.x; e < rows * rows; e += blockDim.x) Jl[e] = ((e / rows) == (e % rows)) ? 1.0 : 0.0;
-  if (threadIdx.x == 0) s_rot = 0;
+  if (threadIdx.x == 0) {
+    s_rot = 0;
+    s_cmax = 0;
+  }
   __syncthreads();
   const int RP = rows + (rows & 1);
   const int MQ = max(pn, qn);
@@ -850,6 +872,7 @@ __global__ void __launch_bounds__(kNT) jacobi_block_kernel(int k, int c, double*
           g += __shfl_xor(g, off, LG);
         }
       }
+      if (sub == 0) atomicMax(&s_cmax, cos2_bits(a, b, g));
       double cs, sn;
       if (!jacobi_rotation(a, b, g, tol, cs, sn)) continue;
 #pragma unroll
@@ -892,7 +915,10 @@ __global__ void __launch_bounds__(kNT) jacobi_block_kernel(int k, int c, double*
       JT[(long)grow(r) * k + col] = acc;
     }
   }
-  if (threadIdx.x == 0 && s_rot > 0) atomicAdd(counter, s_rot);
+  if (threadIdx.x == 0) {
+    if (s_rot > 0) atomicAdd(counter, s_rot);
+    atomicMax(counter + 1, s_cmax);
+  }
 }
 
 __global__ void __launch_bounds__(kNT) jacobi_finish_kernel(int k, int c, const double* __restrict__ B,
@@ -902,8 +928,8 @@ __global__ void __launch_bounds__(kNT) jacobi_finish_kernel(int k, int c, const 
   jacobi_finish(k, c, B, JT, U, Wt, sigma, info, sweep);
 }
 
-__global__ void set_int_kernel(int* p, int v) {
-  if (threadIdx.x == 0) p[0] = v;
+__global__ void set_ints_kernel(int* p, int v, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = v;
 }
 
 // ------------------------------------------------- Hessenberg reduction
@@ -1329,17 +1355,19 @@ void jacobi_rows(hipStream_t s, int k, int c, double* B, double* JT, double* U, 
     identity(s, k, JT);
     int sweep = 0;
     for (; sweep < max_sweeps; ++sweep) {
-      hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, s, info, 0);
+      hipLaunchKernelGGL(set_ints_kernel, dim3(1), dim3(64), 0, s, info, 0, 2);
       hipLaunchKernelGGL((jacobi_block_kernel<kJacBR, kJacBG>), dim3(nblk), dim3(kNT), lds, s, k, c, B, JT, blk,
                          nblk, nplay, 0, 0, info);
       for (int round = 0; round < nplay - 1; ++round)
         hipLaunchKernelGGL((jacobi_block_kernel<kJacBR, kJacBG>), dim3(nplay / 2), dim3(kNT), lds, s, k, c, B, JT,
                            blk, nblk, nplay, round, 1, info);
       T2S2_LAUNCH_CHECK();
-      int rot = 0;
-      T2S2_HIP(hipMemcpyAsync(&rot, info, sizeof(int), hipMemcpyDeviceToHost, s));
+      int st[2] = {0, 0};  // rotations, largest squared cosine (float bits)
+      T2S2_HIP(hipMemcpyAsync(st, info, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
       T2S2_HIP(hipStreamSynchronize(s));
-      if (rot == 0) break;
+      float cmax;
+      std::memcpy(&cmax, &st[1], sizeof(float));
+      if (st[0] == 0 || cmax <= kJacStop2) break;
     }
     hipLaunchKernelGGL(jacobi_finish_kernel, dim3(1), dim3(kNT), 0, s, k, c, B, JT, U, Wt, sigma, info, sweep);
     T2S2_LAUNCH_CHECK();
