@@ -502,15 +502,34 @@ __device__ inline float2 xor8_move(float2 v) { return make_float2(xor8_move<X>(v
 constexpr int kTriColMax = 256;
 constexpr int kTriColBlocks = kTriColMax / kTriG;
 
+// Entry i of the eigenvector of column j of a triangular matrix:
+// -s / (t_ii - t_jj), the denominator raised to smin = max(ulp |t_jj|, tiny)
+// in modulus when smaller (shared by both eigenvector kernels)
+template <class C>
+struct RealOfCx;
+template <>
+struct RealOfCx<double2> { using type = double; };
+template <>
+struct RealOfCx<float2> { using type = float; };
+template <class C>
+__device__ inline C trevec_entry(C s, C tii, C tjj) {
+  using R = typename RealOfCx<C>::type;
+  using CX = CxOf<R>;
+  C den = csub(tii, tjj);
+  const R smin = fmax(EpsOf<R>::value * cabs(tjj), TinyOf<R>::value);
+  if (cabs(den) < smin) den = CX::make(smin, R(0.0));
+  return cdiv(CX::make(-s.x, -s.y), den);
+}
+
 // register slots for the next row block's entries (the rest is loaded when staged)
 template <class T>
 constexpr int tri_col_slots() { return sizeof(T) > 8 ? kTriColBlocks / 2 : kTriColBlocks; }
 
 // one row block MI of trtri_col_kernel, then the blocks above it
-template <class T, int MI>
+template <class T, bool EV, int MI>
 __device__ __forceinline__ void trtri_col_block(int n, int B, int j, int s, int lr, int lc, const T* __restrict__ R,
                                                 T* __restrict__ Rinv, T* tile, T (&x)[kTriColBlocks],
-                                                T (&pre)[tri_col_slots<T>()]) {
+                                                T (&pre)[tri_col_slots<T>()], T tjj) {
   if constexpr (MI >= 0) {
     using O = TriOps<T>;
     constexpr int MB = kTriColBlocks, LD = kTriColMax;
@@ -550,10 +569,22 @@ __device__ __forceinline__ void trtri_col_block(int n, int B, int j, int s, int 
         p = tadd<T>(p, xor8_move<2>(p));
         p = tadd<T>(p, xor8_move<1>(p));
         const T rii = tile[r * LD + r];
-        if (i <= j) {
-          const T xi = (i == j) ? O::div(O::one(), rii) : O::div(O::neg(p), rii);
-          if (s == r) x[MI] = xi;
-          if (s == 0) Rinv[(long)i * n + j] = xi;
+        if constexpr (!EV) {
+          if (i <= j) {
+            const T xi = (i == j) ? O::div(O::one(), rii) : O::div(O::neg(p), rii);
+            if (s == r) x[MI] = xi;
+            if (s == 0) Rinv[(long)i * n + j] = xi;
+          }
+        } else {
+          // eigenvector of column j: y_j = 1 (kept out of x: its term T[i][j] is
+          // added after the butterfly, as in trevec_kernel)
+          if (i < j) {
+            const T xi = trevec_entry(tadd<T>(p, tile[r * LD + j - kTriG * MI]), rii, tjj);
+            if (s == r) x[MI] = xi;
+            if (s == 0) Rinv[(long)i * n + j] = xi;
+          } else if (i == j && s == 0) {
+            Rinv[(long)i * n + j] = O::one();
+          }
         }
       }
       if constexpr (MI > 0) {
@@ -573,11 +604,12 @@ __device__ __forceinline__ void trtri_col_block(int n, int B, int j, int s, int 
         __syncthreads();
       }
     }
-    trtri_col_block<T, MI - 1>(n, B, j, s, lr, lc, R, Rinv, tile, x, pre);
+    trtri_col_block<T, EV, MI - 1>(n, B, j, s, lr, lc, R, Rinv, tile, x, pre, tjj);
   }
 }
 
-template <class T>
+// EV: eigenvectors of the triangular R instead (trevec_kernel's results)
+template <class T, bool EV>
 __global__ void __launch_bounds__(64) trtri_col_kernel(int n, const T* __restrict__ R, T* __restrict__ Rinv) {
   using O = TriOps<T>;
   __shared__ T tile[kTriG * kTriColMax];
@@ -600,7 +632,8 @@ __global__ void __launch_bounds__(64) trtri_col_kernel(int n, const T* __restric
     tile[lr * kTriColMax + lc] = (row < n && col < n) ? R[(long)row * n + col] : O::zero();
   }
   __syncthreads();
-  trtri_col_block<T, kTriColBlocks - 1>(n, B, j, s, lr, lc, R, Rinv, tile, x, pre);
+  const T tjj = (EV && j >= 0) ? R[(long)j * n + j] : O::zero();
+  trtri_col_block<T, EV, kTriColBlocks - 1>(n, B, j, s, lr, lc, R, Rinv, tile, x, pre, tjj);
 }
 
 // ------------------------------------------------ one-sided Jacobi SVD
@@ -1086,15 +1119,11 @@ __global__ void __launch_bounds__(kNT) trevec_kernel(int n, const typename CxOf<
       const int k = k0 + grp;
       C s = CX::make(R(0.0), R(0.0));
       if (k < n)
-        for (int t = i + 1 + sub; t < k; t += kTriG) s = cadd(s, cmul(T[(long)i * n + t], Y[(long)t * n + k]));
+        for (int t = i + 1 + sub; t < k; t += kTriG) s = TriOps<C>::fma(T[(long)i * n + t], Y[(long)t * n + k], s);
       for (int off = kTriG / 2; off > 0; off >>= 1) s = tadd<C>(s, shfl_xor_t<C>(s, off, kTriG));
       if (k < n && sub == 0) {
         s = cadd(s, T[(long)i * n + k]);  // times y_k = 1
-        const C tkk = T[(long)k * n + k];
-        C den = csub(tii, tkk);
-        const R smin = fmax(EpsOf<R>::value * cabs(tkk), TinyOf<R>::value);
-        if (cabs(den) < smin) den = CX::make(smin, R(0.0));
-        Y[(long)i * n + k] = cdiv(CX::make(-s.x, -s.y), den);
+        Y[(long)i * n + k] = trevec_entry(s, tii, T[(long)k * n + k]);
       }
     }
     __syncthreads();
@@ -1310,7 +1339,7 @@ void chol_skip(hipStream_t s, int n, const double* G, double* R, int* mask, int*
 template <class T>
 static void trtri_launch(hipStream_t s, int n, const T* R, T* Rinv) {
   if (n <= kTriColMax)
-    hipLaunchKernelGGL(trtri_col_kernel<T>, dim3((n + kTriG - 1) / kTriG), dim3(64), 0, s, n, R, Rinv);
+    hipLaunchKernelGGL((trtri_col_kernel<T, false>), dim3((n + kTriG - 1) / kTriG), dim3(64), 0, s, n, R, Rinv);
   else
     hipLaunchKernelGGL(trtri_upper_kernel<T>, dim3(1), dim3(kNT), 0, s, n, R, Rinv);
 }
@@ -1404,7 +1433,11 @@ void hessenberg(hipStream_t s, int n, float* A, float* QT, float* work) { hessen
 template <class R>
 static void trevec_t(hipStream_t s, int n, const typename CxOf<R>::type* T, typename CxOf<R>::type* Y) {
   TimedScope ts(s, KC_TREVEC, 2.0 * sizeof(R) * 2.0 * n * n, 8.0 * n * n * n / 6.0);
-  hipLaunchKernelGGL(trevec_kernel<R>, dim3(1), dim3(kNT), 0, s, n, T, Y);
+  using C = typename CxOf<R>::type;
+  if (n <= kTriColMax)
+    hipLaunchKernelGGL((trtri_col_kernel<C, true>), dim3((n + kTriG - 1) / kTriG), dim3(64), 0, s, n, T, Y);
+  else
+    hipLaunchKernelGGL(trevec_kernel<R>, dim3(1), dim3(kNT), 0, s, n, T, Y);
   T2S2_LAUNCH_CHECK();
 }
 void trevec(hipStream_t s, int n, const double2* T, double2* Y) { trevec_t<double>(s, n, T, Y); }
