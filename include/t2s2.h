@@ -4,8 +4,9 @@
  * (T^2S^2).
  *
  * Problem (paper: Eq. advection-diffusion with Eq. pblm:time:B):
- *     -eps Lap u + beta . grad u = f   in [-1, 1]^d,   u = 0 on the boundary,
- * with constant eps > 0 and constant beta in R^d.
+ *     -eps Lap u + beta . grad u = f   in [-1, 1]^d,   u = g on the boundary,
+ * with constant eps > 0 and constant beta in R^d (g = 0 unless Dirichlet
+ * data are passed to t2s2_solve).
  *
  * Discretisation (paper: Overview (i)-(iii), Fig. 3):
  *   - N_l nodes per dimension, polynomial degree n_l = N_l - 1; representation
@@ -54,6 +55,9 @@ extern "C" {
 #define T2S2_ENOMEM 2      /* device allocation failed                     */
 #define T2S2_ENOTCONV 3    /* solve stopped at max_sweeps above target     */
 #define T2S2_EHIP 4        /* HIP runtime error (text in t2s2_last_error)  */
+#define T2S2_EFACTOR 5     /* a dense factorisation (Francis QR of an
+                              interface or 1D operator, one-sided Jacobi of a
+                              truncated SVD) stopped at its iteration limit */
 
 #define T2S2_SCHEME_PLAIN 0
 #define T2S2_SCHEME_SC 1
@@ -71,6 +75,7 @@ extern "C" {
 
 #define T2S2_MAX_DIM 16
 #define T2S2_MAX_HISTORY 128
+#define T2S2_PHASES 5
 
 typedef struct t2s2_problem t2s2_problem;
 
@@ -136,6 +141,19 @@ typedef struct {
                                                    else -1                  */
   double cold_residual;                         /* residual of the cold start
                                                    when judged, else -1     */
+  int refinement_capped;                        /* local refinements that
+                                                   stopped at their step cap
+                                                   above 0.1 tol / sqrt(d)  */
+  double phase_ms[T2S2_PHASES];                 /* device time per phase on
+                                                   the solve's stream: 0 set-up
+                                                   (Dirichlet lift, start,
+                                                   orthogonalisation, first
+                                                   interfaces, warm-start
+                                                   judge), 1 local solves,
+                                                   2 splits (truncated SVD,
+                                                   enrichment, QR), 3 interface
+                                                   updates and factorisations,
+                                                   4 FP64 residual checks   */
 } t2s2_report;
 
 /* Message of the last failing call on this thread ("" if none). */
@@ -183,14 +201,18 @@ int t2s2_problem_colloc(const t2s2_problem* p, int l, double* theta_out);
  * y->ranks is written.  Asynchronous on stream. */
 int t2s2_tt_matvec(const t2s2_ttm* A, const t2s2_tt* x, t2s2_tt* y, void* stream);
 
-/* ||x||_2 (Frobenius) via left-to-right QR orthogonalisation of a copy;
- * uses p's scratch.  Synchronises stream; result in *out (host). */
+/* ||x||_2 (Frobenius) by the Gram recursion G_l = sum_i X_l(i)^T G_{l-1}
+ * X_l(i) carried in double-double arithmetic (error-free products and
+ * two-sum accumulation), so ||x||^2 is resolved to ~1e-16 of itself; uses
+ * p's scratch.  Synchronises stream; result in *out (host). */
 int t2s2_tt_norm(t2s2_problem* p, const t2s2_tt* x, double* out, void* stream);
 
-/* ||f - L x||_2 / ||f||_2 with L the problem's operator, computed exactly in
- * FP64: x and f are concatenated into the TT of f - L x (ranks s + 2 r), which
- * is left-orthogonalised by QR; the norm is that of the last core.  Never
- * uses the cancelling Gram expansion.  Synchronises stream. */
+/* ||f - L x||_2 / ||f||_2 with L the problem's operator (paper: Results,
+ * Fig. 6 residual per swap): L x by the TT-matvec, f and -L x concatenated
+ * into the exact TT of f - L x (ranks s + 2 r), whose norm, and that of f,
+ * come from the double-double Gram recursion of t2s2_tt_norm.  The
+ * expansion ||f||^2 - 2<f, Lx> + ||Lx||^2 is never formed (it cancels below
+ * FP64 at residuals of 1e-8).  Synchronises stream. */
 int t2s2_tt_residual_norm(t2s2_problem* p, const t2s2_tt* x, const t2s2_tt* f,
                           double* out, void* stream);
 
@@ -218,8 +240,9 @@ int t2s2_tt_round(t2s2_problem* p, t2s2_tt* x, double tol, int rmax, void* strea
  * All arrays are FP64 device buffers owned by the caller, row-major: Lint
  * (r1 x r1), K (m x m), Rint (r2 x r2), g and u (r1 * m * r2); u must not
  * alias g.  One application in FP64, no refinement.  Sizes: r1, r2 <= 512,
- * m <= 64.  Returns T2S2_EINVAL for bad sizes or method, and an error if a
- * factorisation does not converge.  Synchronises stream. */
+ * m <= 64.  Returns T2S2_EINVAL for bad sizes or method, and T2S2_EFACTOR if
+ * a Francis QR stops at its step limit (see t2s2_debug_iteration_limits).
+ * Synchronises stream. */
 int t2s2_local_solve(int r1, int m, int r2, const double* Lint, const double* K, const double* Rint,
                      const double* g, double* u, int method, void* stream);
 
@@ -240,24 +263,40 @@ int t2s2_source_gaussians(t2s2_problem* p, int s, const double* amp,
 int t2s2_source_manufactured(t2s2_problem* p, t2s2_tt* f_out, void* stream);
 
 /* ---------------------------------------------------------------- solve ---
- * Solve L x = f in TT format by alternating sweeps with exact local solves
- * and residual enrichment (the paper cites AMEn for this step).
- *   f      TT right-hand side on the collocation grid (device cores)
- *   x0     optional TT start (NULL: seeded random TT of rank init_rank)
- *   x_out  output TT; cores[l] must hold rank_cap*N_l*rank_cap doubles
- *          (first/last: N_l*rank_cap); ranks written
- *   rep    optional host report
+ * Solve the collocation system in TT format by alternating sweeps with
+ * exact local solves and residual enrichment (the paper cites AMEn for this
+ * step).
+ *   f      TT right-hand side on the collocation grid (device cores, mode
+ *          sizes N_l - 2)
+ *   g      optional Dirichlet data (paper: Eq. pblm:time:B, u = g on the
+ *          boundary): a TT on the GLL grid, mode sizes N_l, whose values at
+ *          boundary nodes are used (interior values are ignored).  The
+ *          boundary rows are then u = g and the interior unknowns solve
+ *          L x = b with b = f - L_full g + L g_int (L_full: the collocation
+ *          rows on all GLL columns, g_int: g's interior slices), formed as
+ *          an exact TT sum and rounded at relative 1e-14 (rank <= rank_cap).
+ *          NULL: g = 0, b = f.
+ *   x0     optional TT start (NULL: seeded random TT of rank init_rank);
+ *          d and mode sizes N_l - 2 must match the problem and its ranks
+ *          must not exceed the rank cap, else T2S2_EINVAL before any copy
+ *   x_out  output TT of the interior values (mode sizes N_l - 2; with g the
+ *          boundary values of the solution are g's); cores[l] must hold
+ *          rank_cap*(N_l-2)*rank_cap doubles (first/last: (N_l-2)*rank_cap);
+ *          ranks written
+ *   rep    optional host report; its residual is ||b - L x|| / ||b||
  * Returns T2S2_OK when the FP64 residual meets opts->target, T2S2_ENOTCONV
  * (x_out still holds the last iterate) when max_sweeps is reached first,
- * T2S2_EINVAL for a precision other than T2S2_PRECISION_FP64 / _MIXED. */
-int t2s2_solve(t2s2_problem* p, const t2s2_tt* f, const t2s2_tt* x0,
-               const t2s2_options* opts, t2s2_tt* x_out, t2s2_report* rep,
-               void* stream);
+ * T2S2_EINVAL for bad descriptors or a precision other than
+ * T2S2_PRECISION_FP64 / _MIXED, T2S2_EFACTOR when a factorisation gives up. */
+int t2s2_solve(t2s2_problem* p, const t2s2_tt* f, const t2s2_tt* g,
+               const t2s2_tt* x0, const t2s2_options* opts, t2s2_tt* x_out,
+               t2s2_report* rep, void* stream);
 
 /* Batched solve of count independent instances of uneven size (each its own
  * d, N_l, eps, beta, source; the batched workload of hundreds of small
  * problems).  Instance i is solved exactly as t2s2_solve(probs[i], f[i],
- * x0 ? x0[i] : NULL, opts, x_out[i], reps ? &reps[i] : NULL) would, so its
+ * g ? g[i] : NULL, x0 ? x0[i] : NULL, opts, x_out[i], reps ? &reps[i] : NULL)
+ * would, so its
  * result is bitwise the same; instances run concurrently, up to `workers`
  * at a time (0: 16, at most 64), each on its own non-blocking HIP stream of
  * default priority driven by its own host thread, taken from a shared
@@ -266,6 +305,7 @@ int t2s2_solve(t2s2_problem* p, const t2s2_tt* f, const t2s2_tt* x0,
  * queued on `stream`; all work is complete when the call returns.
  *   probs  count distinct problems (a problem is not shared between
  *          concurrent solves: EINVAL if a pointer repeats)
+ *   g      NULL, or count entries each NULL or Dirichlet data (as t2s2_solve)
  *   x0     NULL, or count entries each NULL or a start TT
  *   opts   one option set for every instance (NULL: defaults)
  *   reps   NULL or count host reports
@@ -273,7 +313,8 @@ int t2s2_solve(t2s2_problem* p, const t2s2_tt* f, const t2s2_tt* x0,
  * (a hard error before T2S2_ENOTCONV), with the first such instance named
  * in t2s2_last_error; reps[i].status holds each instance's outcome. */
 int t2s2_solve_batched(int count, t2s2_problem* const* probs,
-                       const t2s2_tt* const* f, const t2s2_tt* const* x0,
+                       const t2s2_tt* const* f, const t2s2_tt* const* g,
+                       const t2s2_tt* const* x0,
                        const t2s2_options* opts, t2s2_tt* const* x_out,
                        t2s2_report* reps, int workers, void* stream);
 
@@ -365,6 +406,13 @@ int t2s2_timing_enable(int on);
 int t2s2_timing_classes(unsigned int mask);
 int t2s2_timing_read(int cls, double* total_ms, long long* launches, double* bytes, double* flops);
 const char* t2s2_timing_class_name(int cls);
+
+/* Iteration limits of the dense factorisations, process-wide (0 restores a
+ * default: 40 n + 100 Francis double-shift steps for an n x n matrix, 60
+ * one-sided Jacobi sweeps).  For tests of the error path: with a lowered
+ * limit the kernels stop normally and the calls that ran them return
+ * T2S2_EFACTOR.  EINVAL for negative values. */
+int t2s2_debug_iteration_limits(int francis_steps, int jacobi_sweeps);
 
 /* Defaults: tol 1e-10, target 1e-8, max_sweeps 40, kick 8, rank_cap = the
  * problem's, init_rank 2, seed 0, check_every 1, verbose 0. */

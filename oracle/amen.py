@@ -14,8 +14,13 @@ residual-based enrichment, alternating sweep directions):
     right bases of x, and of the residual onto the bases of z) are built.
 2.  At core l the Galerkin-projected local system
         B u = f,  B = Phi_L (x) A_l (x) Phi_R,  f = Psi_L (x) b_l (x) Psi_R
-    is solved: dense LU when r_{l-1} n_l r_l <= ``dense_max``, else
-    restarted GMRES started from the current core (scipy).
+    is solved exactly: by dense LU of the assembled local matrix
+    (``local_solver="dense"``, or ``"auto"`` while r_{l-1} n_l r_l <=
+    ``dense_max``), or, for a Kronecker-sum operator, by the complex Schur
+    forms of its three factors (``local_solver="kron"``, ``local_solve_kron``).
+    A local system too large for dense LU without Kronecker factors is an
+    error (no iterative local solver: unpreconditioned GMRES stalls on these
+    non-normal systems).
 3.  The new core is split by a truncated SVD, delta = tol ||u|| / sqrt(d)
     (Frobenius tail rule), rank <= ``rank_cap``.
 4.  Enrichment: the local residual projected onto the old-side basis of x
@@ -37,7 +42,6 @@ from __future__ import annotations
 from typing import List, Optional, Sequence
 
 import numpy as np
-import scipy.sparse.linalg as spla
 
 from . import tt
 
@@ -157,8 +161,7 @@ def _random_tt(rng, ns, r):
 
 def solve(A: Sequence[np.ndarray], b: Sequence[np.ndarray], x0: Optional[Sequence[np.ndarray]] = None,
           tol: float = 1e-10, target: float = 1e-8, max_sweeps: int = 30, kick: int = 4,
-          rank_cap: int = 200, dense_max: int = 3000, gmres_restart: int = 40,
-          gmres_maxiter: int = 8, seed: int = 0, verbose: bool = False,
+          rank_cap: int = 200, dense_max: int = 3000, seed: int = 0, verbose: bool = False,
           local_solver: str = "auto", kron_factors=None):
     """Solve A x = b in TT format.  Returns (x cores, info dict)."""
     rng = np.random.default_rng(seed)
@@ -205,15 +208,11 @@ def solve(A: Sequence[np.ndarray], b: Sequence[np.ndarray], x0: Optional[Sequenc
             if res0 > loc_tol:
                 if local_solver == "kron":
                     u = local_solve_kron(PhiL, PhiR, kron_factors[0][l], kron_factors[1][l], f)
-                elif size <= dense_max:
+                elif local_solver == "dense" or (local_solver == "auto" and size <= dense_max):
                     u = np.linalg.solve(local_dense(PhiL, A[l], PhiR), f.reshape(-1)).reshape(shape)
                 else:
-                    op = spla.LinearOperator(
-                        (size, size), dtype=np.float64,
-                        matvec=lambda v: local_apply(PhiL, A[l], PhiR, v.reshape(shape)).reshape(-1))
-                    sol, _ = spla.gmres(op, f.reshape(-1), x0=u0.reshape(-1), rtol=loc_tol,
-                                        atol=0.0, restart=gmres_restart, maxiter=gmres_maxiter)
-                    u = sol.reshape(shape)
+                    raise ValueError(f"local system of size {size} exceeds dense_max = {dense_max}: "
+                                     "pass local_solver='kron' with the Kronecker factors")
             else:
                 u = u0
             last = (direction > 0 and l == d - 1) or (direction < 0 and l == 0)

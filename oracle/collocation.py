@@ -29,10 +29,19 @@ Solvers:
   complex Schur K_l = Q_l T_l Q_l^H, unitary transforms along each mode and
   back substitution on the triangular Kronecker sum.
 
+* ``lift_rhs``     -- with Dirichlet data g != 0 the boundary values are
+  known, so the collocation rows applied to them move to the right-hand side:
+  b = f - L_rows (g with its interior values set to 0), L_rows the m^d x N^d
+  row block on all GLL columns; then ``solve_schur(ops, b)`` gives the
+  interior values.
+
 Pins (tests/test_oracle_collocation.py): the two solvers agree and each has a
 small backward error; exponential convergence to the manufactured solution;
 the 1D special case equals ``spectral.solve_1d``; a d-D product of 1D
-closed-form solutions is reproduced (exact separable case).
+closed-form solutions is reproduced (exact separable case); with non-zero
+boundary data a tensor-product polynomial of degree <= N-1 per dimension is
+reproduced exactly by the dense solve, and lift + Schur equals the dense
+solve.
 """
 from __future__ import annotations
 
@@ -152,6 +161,21 @@ def solve_schur(ops: Sequence[dict], f_interior: np.ndarray) -> np.ndarray:
     for l in range(d):
         y = mode_product(y, Qs[l], l)
     return y.real
+
+
+def lift_rhs(ops: Sequence[dict], f_interior: np.ndarray, g_full: np.ndarray) -> np.ndarray:
+    """Interior right-hand side for Dirichlet data g (Eq. pblm:time:B): b = f - L_rows g_b,
+    g_b = g with interior values zeroed, L_rows = sum_l E_1 x .. M_l .. x E_d on all GLL columns."""
+    gb = np.array(g_full, dtype=np.float64).copy()
+    gb[tuple(slice(1, -1) for _ in ops)] = 0.0
+    d = len(ops)
+    out = None
+    for l in range(d):
+        t = gb
+        for k in range(d):
+            t = mode_product(t, ops[k]["M"] if k == l else ops[k]["E"], k)
+        out = t if out is None else out + t
+    return np.asarray(f_interior, dtype=np.float64) - out
 
 
 def embed_interior(u_int: np.ndarray) -> np.ndarray:

@@ -11,8 +11,11 @@
 * Compression ratio: TT storage over full storage (Results; Methods remark on
   storage O(d n r^2) vs O(n^d)).
 
-Pins: tests/test_oracle_metrics.py (counts on hand-made profiles; the
-paper's printed compression and storage arithmetic from tests/golden/).
+Pins: tests/test_oracle_tt.py -- test_metrics_sign_changes and
+test_mid_axis_profile_and_oscillation_count (counts on hand-made profiles),
+test_paper_compression_and_storage_arithmetic (the paper's printed
+compression and storage figures from tests/golden/); the oscillation test
+of the 2D collocation solve in tests/test_oracle_collocation.py.
 """
 from __future__ import annotations
 

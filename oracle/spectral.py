@@ -224,9 +224,3 @@ def closed_form_1d(x, eps: float, beta: float):
     # (e^{a(x+1)} - 1)/(e^{2a} - 1) = e^{a(x-1)} (1 - e^{-a(x+1)}) / (1 - e^{-2a})
     frac = np.exp(a * (x - 1.0)) * (-np.expm1(-a * (x + 1.0))) / (-np.expm1(-2.0 * a))
     return (x + 1.0) / beta - (2.0 / beta) * frac
-
-
-def interpolate(x_rep, values, y):
-    """Value at points y of the polynomial through (x_rep, values)."""
-    E, _, _ = lagrange_matrices(x_rep, np.asarray(y, dtype=np.float64))
-    return E @ np.asarray(values, dtype=np.float64)

@@ -18,7 +18,8 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 from . import _lib
-from ._lib import (PRECISION_FP64, PRECISION_MIXED, SCHEME_PLAIN, SCHEME_SC, T2S2_ENOTCONV, LibraryMissing,
+from ._lib import (PRECISION_FP64, PRECISION_MIXED, SCHEME_PLAIN, SCHEME_SC, T2S2_EFACTOR, T2S2_EINVAL,
+                   T2S2_ENOTCONV, LibraryMissing,
                    T2S2Error, check, lib)
 
 __all__ = ["nodes", "matrices_1d", "TT", "Problem", "SolveResult", "solve_batched", "local_solve", "SCHEME_PLAIN",
@@ -165,6 +166,8 @@ class SolveResult:
     warm_start_used: int = 0
     warm_residual: float = -1.0
     cold_residual: float = -1.0
+    refinement_capped: int = 0
+    phase_ms: dict = field(default_factory=dict)
 
     @property
     def converged(self) -> bool:
@@ -172,7 +175,7 @@ class SolveResult:
 
 
 class Problem:
-    """-eps Lap u + beta . grad u = f on [-1,1]^d, u = 0 on the boundary (t2s2_problem_create)."""
+    """-eps Lap u + beta . grad u = f on [-1,1]^d, u = g on the boundary (t2s2_problem_create)."""
 
     def __init__(self, d: int, N, eps: float, beta, scheme: int = SCHEME_SC, rank_cap: int = 64):
         Ns = [int(N)] * d if np.isscalar(N) else [int(v) for v in N]
@@ -240,10 +243,14 @@ class Problem:
         return x
 
     # ------------------------------------------------------------------ solve
-    def solve(self, f: TT, x0: Optional[TT] = None, *, tol: float = 1e-10, target: float = 1e-8,
-              max_sweeps: int = 40, kick: int = 8, rank_cap: Optional[int] = None, init_rank: int = 2,
-              seed: int = 0, check_every: int = 1, verbose: bool = False, out: Optional[TT] = None,
-              precision: int = PRECISION_FP64, warm_judge: bool = False) -> SolveResult:
+    def solve(self, f: TT, x0: Optional[TT] = None, *, g: Optional[TT] = None, tol: float = 1e-10,
+              target: float = 1e-8, max_sweeps: int = 40, kick: int = 8, rank_cap: Optional[int] = None,
+              init_rank: int = 2, seed: int = 0, check_every: int = 1, verbose: bool = False,
+              out: Optional[TT] = None, precision: int = PRECISION_FP64,
+              warm_judge: bool = False) -> SolveResult:
+        """t2s2_solve.  f on the collocation grid (modes N_l - 2); g optional
+        Dirichlet data on the GLL grid (modes N_l); the result holds the
+        interior values."""
         cap = int(rank_cap or self.rank_cap)
         x = out if out is not None else TT.empty(self.m, cap)
         o = _options(tol, target, max_sweeps, kick, cap, init_rank, seed, check_every, verbose, precision)
@@ -251,7 +258,9 @@ class Problem:
         rep = _lib.Report()
         fs, xs = f._struct(), x._struct()
         x0s = x0._struct() if x0 is not None else None
-        code = lib().t2s2_solve(self._h, C.byref(fs), C.byref(x0s) if x0s is not None else None, C.byref(o),
+        gs = g._struct() if g is not None else None
+        code = lib().t2s2_solve(self._h, C.byref(fs), C.byref(gs) if gs is not None else None,
+                                C.byref(x0s) if x0s is not None else None, C.byref(o),
                                 C.byref(xs), C.byref(rep), _stream())
         check(code, allow=(T2S2_ENOTCONV,))
         x._read_ranks()
@@ -278,10 +287,13 @@ def _result(x: TT, code: int, rep, d: int) -> SolveResult:
                        history_time_ms=list(rep.history_time_ms[:h]), precision=rep.precision,
                        local_systems=rep.local_systems, refinement_steps=rep.refinement_steps,
                        fp64_fallbacks=rep.fp64_fallbacks, warm_start_used=rep.warm_start_used,
-                       warm_residual=rep.warm_residual, cold_residual=rep.cold_residual)
+                       warm_residual=rep.warm_residual, cold_residual=rep.cold_residual,
+                       refinement_capped=rep.refinement_capped,
+                       phase_ms={n: rep.phase_ms[i] for i, n in enumerate(_lib.PHASE_NAMES)})
 
 
 def solve_batched(problems: Sequence["Problem"], fs: Sequence[TT], *, x0s: Optional[Sequence[Optional[TT]]] = None,
+                  gs: Optional[Sequence[Optional[TT]]] = None,
                   outs: Optional[Sequence[TT]] = None, workers: int = 16, tol: float = 1e-10,
                   target: float = 1e-8, max_sweeps: int = 40, kick: int = 8, rank_cap: Optional[int] = None,
                   init_rank: int = 2, seed: int = 0, check_every: int = 1,
@@ -289,8 +301,8 @@ def solve_batched(problems: Sequence["Problem"], fs: Sequence[TT], *, x0s: Optio
     """t2s2_solve_batched: every instance solved as Problem.solve would, up to
     `workers` at a time on their own streams.  rank_cap None: each problem's own."""
     count = len(problems)
-    if len(fs) != count or (x0s is not None and len(x0s) != count) or (outs is not None and len(outs) != count):
-        raise ValueError("problems, fs, x0s and outs must have the same length")
+    if len(fs) != count or any(v is not None and len(v) != count for v in (x0s, gs, outs)):
+        raise ValueError("problems, fs, gs, x0s and outs must have the same length")
     if count == 0:
         return []
     caps = [int(rank_cap or p.rank_cap) for p in problems]
@@ -308,14 +320,24 @@ def solve_batched(problems: Sequence["Problem"], fs: Sequence[TT], *, x0s: Optio
     if x0s is not None:
         x0st = [x0._struct() if x0 is not None else None for x0 in x0s]
         x0_arr = (ttp * count)(*[C.pointer(v) if v is not None else ttp() for v in x0st])
+    g_arr = None
+    if gs is not None:
+        gst = [g._struct() if g is not None else None for g in gs]
+        g_arr = (ttp * count)(*[C.pointer(v) if v is not None else ttp() for v in gst])
     h_arr = (C.c_void_p * count)(*[p._h.value for p in problems])
-    code = lib().t2s2_solve_batched(count, h_arr, f_arr, x0_arr, C.byref(o), x_arr, reps, int(workers), _stream())
+    code = lib().t2s2_solve_batched(count, h_arr, f_arr, g_arr, x0_arr, C.byref(o), x_arr, reps, int(workers),
+                                    _stream())
     check(code, allow=(T2S2_ENOTCONV,))
     out = []
     for i, x in enumerate(xs):
         x._read_ranks()
         out.append(_result(x, code, reps[i], problems[i].d))
     return out
+
+
+def debug_iteration_limits(francis_steps: int = 0, jacobi_sweeps: int = 0) -> None:
+    """t2s2_debug_iteration_limits (0 restores the defaults)."""
+    check(lib().t2s2_debug_iteration_limits(int(francis_steps), int(jacobi_sweeps)))
 
 
 LOCAL_EIG, LOCAL_HESS = 0, 1

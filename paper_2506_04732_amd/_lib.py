@@ -7,10 +7,11 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libt2s2.so")
 
-T2S2_OK, T2S2_EINVAL, T2S2_ENOMEM, T2S2_ENOTCONV, T2S2_EHIP = 0, 1, 2, 3, 4
+T2S2_OK, T2S2_EINVAL, T2S2_ENOMEM, T2S2_ENOTCONV, T2S2_EHIP, T2S2_EFACTOR = 0, 1, 2, 3, 4, 5
 SCHEME_PLAIN, SCHEME_SC = 0, 1
 PRECISION_FP64, PRECISION_MIXED = 0, 1
-MAX_DIM, MAX_HISTORY = 16, 128
+MAX_DIM, MAX_HISTORY, PHASES = 16, 128, 5
+PHASE_NAMES = ["setup", "local_solve", "split", "interfaces", "residual"]
 
 EXPORTED = [
     "t2s2_last_error", "t2s2_nodes", "t2s2_matrices_1d", "t2s2_problem_create", "t2s2_problem_destroy",
@@ -20,6 +21,7 @@ EXPORTED = [
     "t2s2_mlp_create", "t2s2_mlp_destroy", "t2s2_mlp_param_count", "t2s2_mlp_get_params", "t2s2_mlp_set_params",
     "t2s2_mlp_forward", "t2s2_mlp_backward", "t2s2_mlp_adam_step", "t2s2_mlp_infer_bf16", "t2s2_mlp_train",
     "t2s2_tt_fit_loss", "t2s2_tt_pack", "t2s2_tt_unpack", "t2s2_source_gaussians", "t2s2_source_manufactured",
+    "t2s2_debug_iteration_limits",
 ]
 TIMING_CLASSES = ["gemm_f64", "gemm_c128", "ttm_matvec", "schur_qr", "hessenberg", "jacobi_svd", "cholesky",
                   "trtri", "trevec", "kron_trisolve", "hess_solve", "other"]
@@ -50,7 +52,8 @@ class Report(C.Structure):
                 ("history_time_ms", C.c_double * MAX_HISTORY), ("precision", C.c_int),
                 ("local_systems", C.c_int), ("refinement_steps", C.c_int), ("fp64_fallbacks", C.c_int),
                 ("warm_start_used", C.c_int), ("warm_residual", C.c_double),
-                ("cold_residual", C.c_double)]
+                ("cold_residual", C.c_double), ("refinement_capped", C.c_int),
+                ("phase_ms", C.c_double * PHASES)]
 
 
 class LibraryMissing(RuntimeError):
@@ -85,11 +88,12 @@ def lib() -> C.CDLL:
     L.t2s2_tt_residual_norm.argtypes = [vp, C.POINTER(TTStruct), C.POINTER(TTStruct), dp, vp]
     L.t2s2_tt_round.argtypes = [vp, C.POINTER(TTStruct), C.c_double, C.c_int, vp]
     L.t2s2_local_solve.argtypes = [C.c_int, C.c_int, C.c_int, vp, vp, vp, vp, vp, C.c_int, vp]
-    L.t2s2_solve.argtypes = [vp, C.POINTER(TTStruct), C.POINTER(TTStruct), C.POINTER(Options),
-                             C.POINTER(TTStruct), C.POINTER(Report), vp]
+    L.t2s2_solve.argtypes = [vp, C.POINTER(TTStruct), C.POINTER(TTStruct), C.POINTER(TTStruct),
+                             C.POINTER(Options), C.POINTER(TTStruct), C.POINTER(Report), vp]
     ttp = C.POINTER(TTStruct)
-    L.t2s2_solve_batched.argtypes = [C.c_int, C.POINTER(vp), C.POINTER(ttp), C.POINTER(ttp), C.POINTER(Options),
-                                     C.POINTER(ttp), C.POINTER(Report), C.c_int, vp]
+    L.t2s2_solve_batched.argtypes = [C.c_int, C.POINTER(vp), C.POINTER(ttp), C.POINTER(ttp), C.POINTER(ttp),
+                                     C.POINTER(Options), C.POINTER(ttp), C.POINTER(Report), C.c_int, vp]
+    L.t2s2_debug_iteration_limits.argtypes = [C.c_int, C.c_int]
     fp, u64 = C.POINTER(C.c_float), C.c_ulonglong
     L.t2s2_mlp_create.argtypes = [C.c_int, ip, u64, C.POINTER(vp)]
     L.t2s2_mlp_destroy.argtypes = [vp]

@@ -77,8 +77,8 @@ t2s2::Ctx ctx_for(t2s2_problem* p, void* stream) {
 
 // One solve on stream s; throws on argument or runtime errors, returns
 // T2S2_OK or T2S2_ENOTCONV.
-int solve_one(t2s2_problem* p, const t2s2_tt* f, const t2s2_tt* x0, const t2s2_options* opts, t2s2_tt* x_out,
-              t2s2_report* rep, hipStream_t stream) {
+int solve_one(t2s2_problem* p, const t2s2_tt* f, const t2s2_tt* g, const t2s2_tt* x0, const t2s2_options* opts,
+              t2s2_tt* x_out, t2s2_report* rep, hipStream_t stream) {
   T2S2_CHECK(p && f && x_out, "NULL argument");
   t2s2::DTT fd = to_dtt(f);
   T2S2_CHECK(fd.d == p->P->d, "f has the wrong dimension");
@@ -107,13 +107,29 @@ int solve_one(t2s2_problem* p, const t2s2_tt* f, const t2s2_tt* x0, const t2s2_o
   xd.n = fd.n;
   xd.r.assign(fd.d + 1, 1);
   xd.c.assign(x_out->cores, x_out->cores + fd.d);
+  const int cap = o.rank_cap > 0 ? std::min(o.rank_cap, p->P->rank_cap) : p->P->rank_cap;
   t2s2::DTT x0d;
   const t2s2::DTT* x0p = nullptr;
   if (x0) {
+    // the start must be a TT of this problem's interior grid within the cap
+    // (checked before any device copy)
     x0d = to_dtt(x0);
+    T2S2_CHECK(x0d.d == p->P->d, "x0 has the wrong dimension");
+    for (int l = 0; l < x0d.d; ++l) {
+      T2S2_CHECK(x0d.n[l] == p->P->m[l], "x0 mode sizes must be N_l - 2");
+      T2S2_CHECK(x0d.r[l + 1] <= cap, "x0 ranks exceed the rank cap");
+    }
     x0p = &x0d;
   }
   t2s2::Ctx c = ctx_for(p, stream);
+  if (g) {
+    t2s2::DTT gd = to_dtt(g);
+    T2S2_CHECK(gd.d == p->P->d, "g has the wrong dimension");
+    for (int l = 0; l < gd.d; ++l) T2S2_CHECK(gd.n[l] == p->P->N[l], "g mode sizes must be N_l (GLL grid)");
+    t2s2::DTT bd;
+    t2s2::lift_rhs(*p->P, c, fd, gd, bd, cap);
+    fd = bd;
+  }
   t2s2::SolveReport r;
   const int st = t2s2::solve(*p->P, c, fd, x0p, o, xd, r);
   for (int l = 0; l <= fd.d; ++l) x_out->ranks[l] = xd.r[l];
@@ -134,6 +150,8 @@ int solve_one(t2s2_problem* p, const t2s2_tt* f, const t2s2_tt* x0, const t2s2_o
     rep->warm_start_used = r.warm_start_used;
     rep->warm_residual = r.warm_residual;
     rep->cold_residual = r.cold_residual;
+    rep->refinement_capped = r.refinement_capped;
+    for (int i = 0; i < T2S2_PHASES; ++i) rep->phase_ms[i] = r.phase_ms[i];
     for (int i = 0; i < h; ++i) {
       rep->history_residual[i] = r.hist_res[i];
       rep->history_local[i] = r.hist_local[i];
@@ -343,14 +361,22 @@ void t2s2_default_options(t2s2_options* o) {
   o->warm_judge = 0;
 }
 
-int t2s2_solve(t2s2_problem* p, const t2s2_tt* f, const t2s2_tt* x0, const t2s2_options* opts, t2s2_tt* x_out,
-               t2s2_report* rep, void* stream) {
-  return guarded([&] { return solve_one(p, f, x0, opts, x_out, rep, static_cast<hipStream_t>(stream)); });
+int t2s2_solve(t2s2_problem* p, const t2s2_tt* f, const t2s2_tt* g, const t2s2_tt* x0, const t2s2_options* opts,
+               t2s2_tt* x_out, t2s2_report* rep, void* stream) {
+  return guarded([&] { return solve_one(p, f, g, x0, opts, x_out, rep, static_cast<hipStream_t>(stream)); });
 }
 
-int t2s2_solve_batched(int count, t2s2_problem* const* probs, const t2s2_tt* const* f, const t2s2_tt* const* x0,
-                       const t2s2_options* opts, t2s2_tt* const* x_out, t2s2_report* reps, int workers,
-                       void* stream) {
+int t2s2_debug_iteration_limits(int francis_steps, int jacobi_sweeps) {
+  return guarded([&] {
+    T2S2_CHECK(francis_steps >= 0 && jacobi_sweeps >= 0, "iteration limits must be >= 0");
+    t2s2::set_iteration_limits(francis_steps, jacobi_sweeps);
+    return T2S2_OK;
+  });
+}
+
+int t2s2_solve_batched(int count, t2s2_problem* const* probs, const t2s2_tt* const* f, const t2s2_tt* const* g,
+                       const t2s2_tt* const* x0, const t2s2_options* opts, t2s2_tt* const* x_out,
+                       t2s2_report* reps, int workers, void* stream) {
   return guarded([&] {
     T2S2_CHECK(count >= 0, "count must be >= 0");
     if (count == 0) return T2S2_OK;
@@ -399,7 +425,8 @@ int t2s2_solve_batched(int count, t2s2_problem* const* probs, const t2s2_tt* con
           continue;
         }
         codes[i] = guarded([&] {
-          return solve_one(ps[i], f[i], x0 ? x0[i] : nullptr, opts, x_out[i], reps ? &reps[i] : nullptr, s);
+          return solve_one(ps[i], f[i], g ? g[i] : nullptr, x0 ? x0[i] : nullptr, opts, x_out[i],
+                           reps ? &reps[i] : nullptr, s);
         });
         if (codes[i] != T2S2_OK) msgs[i] = t2s2_last_error();
       }

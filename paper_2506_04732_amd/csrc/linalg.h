@@ -35,6 +35,9 @@ class Scratch {
 struct Ctx {
   hipStream_t s = nullptr;
   Scratch* sc = nullptr;
+  // optional device flag (one int): set to 1 by a Francis QR that stopped at
+  // its step limit; read by the caller at its next synchronisation
+  int* fail = nullptr;
   void sync() const { T2S2_HIP(hipStreamSynchronize(s)); }
   template <class T>
   void d2h(T* h, const T* d, size_t n) const {
@@ -96,5 +99,15 @@ void hessenberg(const Ctx& c, int n, double* A, double* QT);
 
 // A (n x n real) = Z T Z^H; outputs ZT = Z^T and upper-triangular T.
 void schur_real(const Ctx& c, int n, const double* A, double2* ZT, double2* T);
+
+// Iteration limits of the dense factorisations (0 restores the defaults:
+// 40 n + 100 Francis steps, 60 Jacobi sweeps).  Process-wide; lowering them
+// makes a factorisation give up and report it (tests of the error path).
+void set_iteration_limits(int francis_steps, int jacobi_sweeps);
+int francis_step_limit(int n);  // defined next to the Francis kernel
+int jacobi_sweep_limit();
+// c.fail <- 0 (on c's stream); whether c.fail is set (synchronises c's stream)
+void clear_fail(const Ctx& c);
+bool read_fail(const Ctx& c);
 
 }  // namespace t2s2

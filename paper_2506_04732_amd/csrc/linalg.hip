@@ -3,8 +3,47 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 
 namespace t2s2 {
+
+namespace {
+__global__ void flag_if_negative_kernel(const int* __restrict__ info, int* __restrict__ fail) {
+  if (threadIdx.x == 0 && info[0] < 0) fail[0] = 1;
+}
+__global__ void clear_int_kernel(int* __restrict__ x) {
+  if (threadIdx.x == 0) x[0] = 0;
+}
+// after a Francis QR: raise c.fail when it stopped at its step limit
+void flag_francis(const Ctx& c, const int* info) {
+  if (!c.fail) return;
+  hipLaunchKernelGGL(flag_if_negative_kernel, dim3(1), dim3(64), 0, c.s, info, c.fail);
+  T2S2_LAUNCH_CHECK();
+}
+int g_jacobi_sweeps = 0;
+}  // namespace
+
+void set_iteration_limits(int francis_steps, int jacobi_sweeps);
+void set_francis_step_limit(int steps);  // schur.hip
+
+void set_iteration_limits(int francis_steps, int jacobi_sweeps) {
+  set_francis_step_limit(std::max(0, francis_steps));
+  g_jacobi_sweeps = std::max(0, jacobi_sweeps);
+}
+int jacobi_sweep_limit() { return g_jacobi_sweeps > 0 ? g_jacobi_sweeps : 60; }
+
+void clear_fail(const Ctx& c) {
+  if (!c.fail) return;
+  hipLaunchKernelGGL(clear_int_kernel, dim3(1), dim3(64), 0, c.s, c.fail);
+  T2S2_LAUNCH_CHECK();
+}
+
+bool read_fail(const Ctx& c) {
+  if (!c.fail) return false;
+  int h = 0;
+  c.d2h(&h, c.fail, 1);
+  return h != 0;
+}
 
 Scratch::~Scratch() {
   for (auto& kv : bufs_)
@@ -224,11 +263,20 @@ int trunc_svd(const Ctx& c, int M, int n, const double* A, long lda, double delt
   double* JT = S.get<double>("ts.JT", (size_t)k * k);
   double* J = S.get<double>("ts.J", (size_t)k * k);
   double* Wt = S.get<double>("ts.Wt", (size_t)k * n);
-  double* sig = S.get<double>("ts.sig", k);
-  int* info = S.get<int>("ts.info", k + 1);
-  jacobi_rows(c.s, k, n, R, JT, J, Wt, sig, info);
-  std::vector<double> hs(k);
-  c.d2h(hs.data(), sig, k);
+  // sigma (k doubles) and the Jacobi info (k + 1 ints) share one buffer, so
+  // one copy returns both
+  double* sig = S.get<double>("ts.sig", (size_t)k + (k + 2) / 2 + 1);
+  int* info = reinterpret_cast<int*>(sig + k);
+  const int max_sw = jacobi_sweep_limit();
+  jacobi_rows(c.s, k, n, R, JT, J, Wt, sig, info, max_sw);
+  std::vector<double> hsi((size_t)k + 1);
+  c.d2h(hsi.data(), sig, (size_t)k + 1);
+  int sweeps_used = 0;
+  std::memcpy(&sweeps_used, hsi.data() + k, sizeof(int));
+  if (sweeps_used >= max_sw)
+    throw Error(5, "truncated SVD: one-sided Jacobi did not converge within " + std::to_string(max_sw) +
+                       " sweeps (k = " + std::to_string(k) + ")");
+  std::vector<double> hs(hsi.begin(), hsi.begin() + k);
   // smallest r with tail(r) = sqrt(sum_{j >= r} s_j^2) <= delta
   std::vector<double> tail(k + 1, 0.0);
   for (int j = k - 1; j >= 0; --j) tail[j] = tail[j + 1] + hs[j] * hs[j];
@@ -278,6 +326,7 @@ void schur_real(const Ctx& c, int n, const double* A, double2* ZT, double2* T) {
   c.d2d(H, A, (size_t)n * n);
   hessenberg(c, n, H, QT);
   schur_francis(c.s, n, H, Hw, QT, Tr, info);
+  flag_francis(c, info);
   rsf2csf(c.s, n, Tr, QT, T, ZT, bstart, U);
 }
 
@@ -323,6 +372,7 @@ void eig_nonsym(const Ctx& c, int n, const double* A, float2* lam, float2* V, fl
     to_float(c.s, QTd, QT, (long)n * n);
   }
   schur_francis(c.s, n, H, Hw, QT, Tr, info);
+  flag_francis(c, info);
   rsf2csf(c.s, n, Tr, QT, T, ZT, bstart, U);
   trevec(c.s, n, T, Y);
   trtri_upper(c.s, n, Y, Yi);

@@ -572,6 +572,10 @@ long francis_packed_doubles(int n) {
   return o;
 }
 
+static int g_francis_steps = 0;  // 0: default limit
+void set_francis_step_limit(int steps) { g_francis_steps = steps; }
+int francis_step_limit(int n) { return g_francis_steps > 0 ? g_francis_steps : 40 * n + 100; }
+
 template <class R>
 static void schur_francis_t(hipStream_t s, int n, const R* H, R* Hwork, R* ZT, R* T, int* info) {
   T2S2_CHECK(n >= 1 && n <= 512, "schur_francis: n must be in [1, 512]");
@@ -579,10 +583,10 @@ static void schur_francis_t(hipStream_t s, int n, const R* H, R* Hwork, R* ZT, R
   const long need = francis_packed_doubles(n) * (long)sizeof(R);
   if (need <= kMsLdsBytes<R, kMsBulges>)
     hipLaunchKernelGGL((francis_ms_kernel<true, R, kMsBulges>), dim3(1), dim3(kFqThreads), (size_t)need, s, n, H,
-                       Hwork, ZT, T, info, 40 * n + 100);
+                       Hwork, ZT, T, info, francis_step_limit(n));
   else
     hipLaunchKernelGGL((francis_ms_kernel<false, R, kMsBulges>), dim3(1), dim3(kFqThreads), 0, s, n, H, Hwork, ZT,
-                       T, info, 40 * n + 100);
+                       T, info, francis_step_limit(n));
   T2S2_LAUNCH_CHECK();
 }
 

@@ -34,6 +34,9 @@ struct Problem {
   // operator (I, K blocks), both as rank-2 TT-matrices
   DTTM opL, opK;
   std::vector<double*> dK, dEinv;
+  // the same blocks on all N_l GLL columns (m_l x N_l, boundary columns
+  // included) and on the interior columns (m_l x m_l): the lift of Dirichlet data
+  std::vector<double*> dEf, dMf, dEi, dMi;
   std::vector<double2*> dK_ZT, dK_T;  // Schur form of K_l
   std::vector<float2*> dK_ZT32, dK_T32;  // the same rounded to FP32
   std::vector<int> opR;
@@ -62,6 +65,12 @@ struct SolveReport {
   std::vector<double> hist_res, hist_local, hist_time;
   std::vector<int> hist_rank;
   int local_systems = 0, refinement_steps = 0, fp64_fallbacks = 0;
+  int refinement_capped = 0;  // local refinements stopped at the step cap above 0.1 tol / sqrt(d)
+  // device time per phase (events on the solve's stream): 0 set-up (start,
+  // orthogonalisation, first interfaces, warm-start judge), 1 local solves,
+  // 2 splits (truncated SVD, enrichment, QR), 3 interface updates and
+  // factorisations, 4 FP64 residual checks
+  double phase_ms[5] = {0, 0, 0, 0, 0};
   int warm_start_used = 0;
   double warm_residual = -1.0, cold_residual = -1.0;
 };
@@ -80,6 +89,13 @@ void tt_round(const Ctx& c, DTT& x, double tol, int rmax);
 // method 0: eigendecompositions of Lint and Rint, 1: Hessenberg form of Lint.
 void local_kron_solve(const Ctx& c, int r1, int m, int r2, const double* Lint, const double* K, const double* Rint,
                       const double* g, double* u, int method);
+// Right-hand side of the interior system for Dirichlet data g (a TT on the
+// N_l-point GLL grids; only its boundary values matter):
+//   b = f - L_full g + L_int g_int,
+// L_full the collocation operator on all GLL columns, g_int the interior
+// slices of g.  Exact TT sum (ranks s + 4 s_g), then rounded at relative
+// 1e-14 with rank <= rmax; b's cores are scratch of p.
+void lift_rhs(Problem& p, const Ctx& c, const DTT& f, const DTT& g, DTT& b, int rmax);
 // TT solve of the interior system; x holds the start (or is random) and
 // receives the solution; its cores need rank_cap * m * rank_cap doubles.
 int solve(Problem& p, const Ctx& c, const DTT& f, const DTT* x0, const SolveOptions& o, DTT& x, SolveReport& rep);

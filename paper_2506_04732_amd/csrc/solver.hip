@@ -37,6 +37,10 @@ Problem::~Problem() {
   for (auto p : opK.c) fr(p);
   for (auto p : dK) fr(p);
   for (auto p : dEinv) fr(p);
+  for (auto p : dEf) fr(p);
+  for (auto p : dMf) fr(p);
+  for (auto p : dEi) fr(p);
+  for (auto p : dMi) fr(p);
   for (auto p : dK_ZT) fr(p);
   for (auto p : dK_T) fr(p);
   for (auto p : dK_ZT32) fr(p);
@@ -144,12 +148,29 @@ Problem* problem_create(int d, const int* N, double eps, const double* beta, int
       std::vector<double> th = colloc_nodes(n, eps, beta[l], scheme);
       std::vector<double> Ef((size_t)m * Nl), D1((size_t)m * Nl), D2((size_t)m * Nl);
       lagrange_eval(x.data(), Nl, th.data(), m, Ef.data(), D1.data(), D2.data());
-      std::vector<double> E((size_t)m * m), M((size_t)m * m);
+      std::vector<double> E((size_t)m * m), M((size_t)m * m), Mf((size_t)m * Nl);
+      for (size_t e = 0; e < Mf.size(); ++e) Mf[e] = -eps * D2[e] + beta[l] * D1[e];
+      {
+        double* ef = dev_alloc<double>(Ef.size());
+        double* mf = dev_alloc<double>(Mf.size());
+        P->dEf.push_back(ef);
+        P->dMf.push_back(mf);
+        T2S2_HIP(hipMemcpy(ef, Ef.data(), Ef.size() * sizeof(double), hipMemcpyHostToDevice));
+        T2S2_HIP(hipMemcpy(mf, Mf.data(), Mf.size() * sizeof(double), hipMemcpyHostToDevice));
+      }
       for (int j = 0; j < m; ++j)
         for (int i = 0; i < m; ++i) {
           E[(size_t)j * m + i] = Ef[(size_t)j * Nl + i + 1];
           M[(size_t)j * m + i] = -eps * D2[(size_t)j * Nl + i + 1] + beta[l] * D1[(size_t)j * Nl + i + 1];
         }
+      {
+        double* ei = dev_alloc<double>(E.size());
+        double* mi = dev_alloc<double>(M.size());
+        P->dEi.push_back(ei);
+        P->dMi.push_back(mi);
+        T2S2_HIP(hipMemcpy(ei, E.data(), E.size() * sizeof(double), hipMemcpyHostToDevice));
+        T2S2_HIP(hipMemcpy(mi, M.data(), M.size() * sizeof(double), hipMemcpyHostToDevice));
+      }
       std::vector<double> Einv = host_inverse(m, E);
       std::vector<double> K((size_t)m * m, 0.0);
       for (int i = 0; i < m; ++i)
@@ -170,6 +191,8 @@ Problem* problem_create(int d, const int* N, double eps, const double* beta, int
     std::vector<int> Rk;
     build_kron_sum(d, P->m, Ieye, P->K, P->opK, Rk);
     Ctx c{nullptr, &P->sc};
+    c.fail = P->sc.get<int>("ctx.fail", 1);
+    clear_fail(c);
     for (int l = 0; l < d; ++l) {
       const int m = P->m[l];
       double* k = dev_alloc<double>((size_t)m * m);
@@ -191,6 +214,7 @@ Problem* problem_create(int d, const int* N, double eps, const double* beta, int
       P->dK_T32.push_back(t32);
     }
     T2S2_HIP(hipDeviceSynchronize());
+    if (read_fail(c)) throw Error(5, "problem set-up: Francis QR of a 1D operator K_l did not converge");
   } catch (...) {
     delete P;
     throw;
@@ -343,8 +367,132 @@ void tt_round(const Ctx& c, DTT& x, double tol, int rmax) {
   }
 }
 
+// sum_k coef[k] parts[k] by concatenation (ranks add); out's cores are
+// scratch named prefix + l, out.r written
+static void tt_concat(const Ctx& c, const std::vector<const DTT*>& parts, const std::vector<double>& coef,
+                      const std::string& prefix, DTT& out) {
+  const int d = parts[0]->d;
+  out.d = d;
+  out.n = parts[0]->n;
+  out.r.assign(d + 1, 1);
+  out.c.resize(d);
+  for (int l = 1; l < d; ++l) {
+    out.r[l] = 0;
+    for (auto* t : parts) out.r[l] += t->r[l];
+  }
+  for (int l = 0; l < d; ++l) {
+    const int n = out.n[l];
+    const long sz = (long)out.r[l] * n * out.r[l + 1];
+    out.c[l] = c.sc->get<double>(prefix + std::to_string(l), (size_t)sz);
+    fill(c.s, out.c[l], sz, 0.0);
+    if (d == 1) {
+      for (size_t k = 0; k < parts.size(); ++k) axpby(c.s, n, coef[k], parts[k]->c[0], 1.0, out.c[0]);
+      continue;
+    }
+    long o0 = 0, o1 = 0;
+    const long ld = out.r[l + 1];
+    for (size_t k = 0; k < parts.size(); ++k) {
+      const DTT& t = *parts[k];
+      const int a0 = t.r[l], a1 = t.r[l + 1];
+      if (l == 0) {
+        copy2d(c.s, n, a1, t.c[l], a1, out.c[l] + o1, ld, coef[k]);
+      } else if (l == d - 1) {
+        copy2d(c.s, (long)a0 * n, 1, t.c[l], 1, out.c[l] + o0 * n, 1);
+      } else {
+        copy2d(c.s, (long)a0 * n, a1, t.c[l], a1, out.c[l] + o0 * n * ld + o1, ld);
+      }
+      o0 += a0;
+      o1 += a1;
+    }
+  }
+}
+
+// y = (sum_l A_1 x .. x B_l x .. x A_d) x with per-dimension blocks A_l (E),
+// B_l (M) of mo_l rows and mi_l columns (leading dimension mi_l), applied to
+// mode indices off .. off + mi_l - 1 of x's cores (x's mode sizes nx_l): the
+// rank-2 Kronecker-sum TT-matrix, block by block (one strided GEMM each)
+static void kron_sum_apply(const Ctx& c, const std::vector<int>& mo, const std::vector<int>& mi, int off,
+                           const std::vector<double*>& A, const std::vector<double*>& B, const DTT& x,
+                           const std::string& prefix, DTT& y) {
+  const int d = x.d;
+  y.d = d;
+  y.n = mo;
+  y.r.assign(d + 1, 1);
+  y.c.resize(d);
+  for (int l = 1; l < d; ++l) y.r[l] = 2 * x.r[l];
+  for (int l = 0; l < d; ++l) {
+    const int R0 = (l == 0) ? 1 : 2, R1 = (l == d - 1) ? 1 : 2;
+    const int r0 = x.r[l], r1 = x.r[l + 1], nx = x.n[l];
+    const long sz = (long)R0 * r0 * mo[l] * R1 * r1;
+    y.c[l] = c.sc->get<double>(prefix + std::to_string(l), (size_t)sz);
+    fill(c.s, y.c[l], sz, 0.0);
+    auto block = [&](int a, int b, const double* Blk) {
+      gemm<double>(c.s, OpN, OpN, mo[l], r1, mi[l], 1.0, Blk, mi[l], 0, x.c[l] + (long)off * r1, r1, (long)nx * r1,
+                   0.0, y.c[l] + (long)a * r0 * mo[l] * R1 * r1 + (long)b * r1, (long)R1 * r1,
+                   (long)mo[l] * R1 * r1, r0);
+    };
+    if (d == 1) {
+      block(0, 0, B[l]);
+    } else if (l == 0) {
+      block(0, 0, B[l]);
+      block(0, 1, A[l]);
+    } else if (l == d - 1) {
+      block(0, 0, A[l]);
+      block(1, 0, B[l]);
+    } else {
+      block(0, 0, A[l]);
+      block(1, 0, B[l]);
+      block(1, 1, A[l]);
+    }
+  }
+}
+
+void lift_rhs(Problem& p, const Ctx& c, const DTT& f, const DTT& g, DTT& b, int rmax) {
+  const int d = p.d;
+  T2S2_CHECK(f.d == d && g.d == d, "lift: dimension mismatch");
+  for (int l = 0; l < d; ++l) {
+    T2S2_CHECK(f.n[l] == p.m[l], "lift: f mode sizes must be N_l - 2");
+    T2S2_CHECK(g.n[l] == p.N[l], "lift: g mode sizes must be N_l (GLL grid)");
+  }
+  DTT y1, y2;
+  kron_sum_apply(c, p.m, p.N, 0, p.dEf, p.dMf, g, "lift.y1_", y1);   // L_full g
+  kron_sum_apply(c, p.m, p.m, 1, p.dEi, p.dMi, g, "lift.y2_", y2);   // L_int g_int
+  tt_concat(c, {&f, &y1, &y2}, {1.0, -1.0, 1.0}, "lift.b", b);
+  tt_round(c, b, 1e-14, std::max(1, rmax));
+}
+
 // ================================================================ solver
 namespace {
+
+// Device time per solve phase: an event on the solve's stream at every phase
+// change; the time between two events is charged to the earlier phase.
+struct PhaseClock {
+  hipStream_t s = nullptr;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> ph;
+  size_t used = 0;
+  ~PhaseClock() {
+    for (auto e : ev) (void)hipEventDestroy(e);
+  }
+  void mark(int phase) {
+    if (used == ev.size()) {
+      hipEvent_t e;
+      T2S2_HIP(hipEventCreate(&e));
+      ev.push_back(e);
+      ph.push_back(0);
+    }
+    T2S2_HIP(hipEventRecord(ev[used], s));
+    ph[used] = phase;
+    ++used;
+  }
+  // after the stream has completed every marked event
+  void collect(double* out) {
+    for (size_t i = 0; i + 1 < used; ++i) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess) out[ph[i]] += ms;
+    }
+  }
+};
 
 // Interface factorisation L = V diag(lam) V^{-1} (complex), FP64 or FP32.
 template <class C>
@@ -429,6 +577,7 @@ struct Amen {
   std::vector<HessF> hf;
   std::vector<char> lhess;        // L[pos] is held as HessF (else as eig / eig32)
   bool mixed = false;
+  PhaseClock pc;
   std::vector<int> xr, zr, sr;  // ranks of x, z, f~ per bond
   std::vector<double*> xc, zc, bc;  // cores
   std::vector<int> maxrank;     // structural bound per bond
@@ -602,6 +751,8 @@ struct Amen {
 
   int run(const DTT& fin, const DTT* x0, DTT& xout, SolveReport& rep) {
     auto t_start = std::chrono::steady_clock::now();
+    pc.s = c.s;
+    pc.mark(0);
     d = p.d;
     m = p.m;
     cap = o.rank_cap > 0 ? std::min(o.rank_cap, p.rank_cap) : p.rank_cap;
@@ -737,6 +888,7 @@ struct Amen {
       sweeps = sw + 1;
       double max_res = 0.0;
       for (int step = 0; step < d; ++step) {
+        pc.mark(1);
         const int l = direction > 0 ? step : d - 1 - step;
         const int r1 = xr[l], r2 = xr[l + 1], ml = m[l], s0 = sr[l], s1 = sr[l + 1];
         const long n = (long)r1 * ml * r2;
@@ -789,6 +941,7 @@ struct Amen {
             }
             prev = rn;
           }
+          if (rn > 0.1 * loc_tol * fn) ++rep.refinement_capped;
         }
         const bool last = (direction > 0 && l == d - 1) || (direction < 0 && l == 0);
         if (last) {
@@ -797,6 +950,7 @@ struct Amen {
         }
         const double unorm = c.nrm2(u, n);
         const double delta = o.tol * unorm / std::sqrt((double)d);
+        pc.mark(2);
         if (direction > 0) step_right(l, delta);
         else step_left(l, delta);
       }
@@ -812,6 +966,7 @@ struct Amen {
       const bool check = (o.check_every == 1) || (o.check_every > 1 && sweeps % o.check_every == 0) ||
                          (o.check_every == 0 && near) || (sweeps == o.max_sweeps);
       if (check) {
+        pc.mark(4);
         DTT xd;
         xd.d = d;
         xd.n = m;
@@ -820,6 +975,9 @@ struct Amen {
         gres = tt_residual_norm(p, c, xd, fin);
         last_res = gres;
       }
+      if (read_fail(c))
+        throw Error(5, "solve: Francis QR of an interface matrix did not converge (sweep " +
+                           std::to_string(sweeps) + ")");
       rep.hist_res.push_back(gres);
       const double ms =
           std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
@@ -833,6 +991,7 @@ struct Amen {
       }
     }
     if (last_res < 0.0) {
+      pc.mark(4);
       DTT xd;
       xd.d = d;
       xd.n = m;
@@ -847,7 +1006,9 @@ struct Amen {
     rep.residual = last_res;
     rep.ranks = xr;
     rep.max_rank = *std::max_element(xr.begin(), xr.end());
+    pc.mark(0);
     c.sync();
+    pc.collect(rep.phase_ms);
     rep.time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     return status;
   }
@@ -908,6 +1069,7 @@ struct Amen {
     if (kk > 0) fill(c.s, xc[l + 1] + (size_t)r * m1 * r3, (long)kk * m1 * r3, 0.0);
     xr[l + 1] = rn;
     // the next z core's left rank follows z_l; its content is rebuilt at l+1
+    pc.mark(3);
     update_left(l);
   }
 
@@ -976,20 +1138,24 @@ struct Amen {
       copy2d(c.s, (long)r0 * mp, kk, zcol, kk, xc[l - 1] + r, rn);
     }
     xr[l] = rn;
+    pc.mark(3);
     update_right(l);
   }
 };
 
 }  // namespace
 
-void local_kron_solve(const Ctx& c, int r1, int m, int r2, const double* Lint, const double* K, const double* Rint,
+void local_kron_solve(const Ctx& c0, int r1, int m, int r2, const double* Lint, const double* K, const double* Rint,
                       const double* g, double* u, int method) {
   T2S2_CHECK(r1 >= 1 && m >= 1 && r2 >= 1, "local_solve: sizes must be positive");
   T2S2_CHECK(r1 <= 512 && r2 <= 512 && m <= 64, "local_solve: r1, r2 <= 512 and m <= 64 required");
   T2S2_CHECK(method == 0 || method == 1, "local_solve: method must be 0 (eigen) or 1 (Hessenberg)");
   T2S2_CHECK(method == 0 || kron_hess_fits(r1, m, (int)sizeof(double2)),
              "local_solve: method 1 needs r1 <= 256 and the m right-hand sides of a chain in LDS");
-  Scratch& S = *c.sc;
+  Scratch& S = *c0.sc;
+  Ctx c = c0;
+  c.fail = S.get<int>("ctx.fail", 1);
+  clear_fail(c);
   const long n = (long)r1 * m * r2;
   double2* ZT = S.get<double2>("loc.ZT", (size_t)m * m);
   double2* T = S.get<double2>("loc.T", (size_t)m * m);
@@ -1019,9 +1185,13 @@ void local_kron_solve(const Ctx& c, int r1, int m, int r2, const double* Lint, c
     kron_inverse_hess<double2, double>(c, r1, m, r2, ZT, T, QT, Hc, eR, g, u, w0, w1, wr);
   }
   c.sync();
+  if (read_fail(c)) throw Error(5, "local_solve: Francis QR did not converge");
 }
 
-int solve(Problem& p, const Ctx& c, const DTT& f, const DTT* x0, const SolveOptions& o, DTT& x, SolveReport& rep) {
+int solve(Problem& p, const Ctx& c0, const DTT& f, const DTT* x0, const SolveOptions& o, DTT& x, SolveReport& rep) {
+  Ctx c = c0;
+  c.fail = c.sc->get<int>("ctx.fail", 1);
+  clear_fail(c);
   Amen a(p, c, o);
   return a.run(f, x0, x, rep);
 }

@@ -43,7 +43,7 @@ def test_batched_equals_single_solves_and_dense():
     _say("batched small", [q.name for q in insts])
     cap = 40
     pf = [_gpu(q, cap) for q in insts]
-    opts = dict(tol=1e-12, target=1e-11, max_sweeps=20, kick=4, init_rank=2)
+    opts = dict(tol=1e-12, target=1e-12, max_sweeps=30, kick=4, init_rank=2)
     single = [p.solve(f, **opts) for p, f in pf]
     batch = t2s2.solve_batched([p for p, _ in pf], [f for _, f in pf], workers=4, **opts)
     for q, s, b in zip(insts, single, batch):
@@ -55,7 +55,9 @@ def test_batched_equals_single_solves_and_dense():
         u = col.solve_dense(ops, col.separable_full(col.gauss_rhs_factors(ops, q.gauss.amp, q.gauss.centre,
                                                                            q.gauss.width)))
         u = u[tuple(slice(1, -1) for _ in range(q.d))]
-        assert metrics.rel_frobenius(ott.full(b.x.to_numpy()), u) <= 1e-9, q.name
+        err = metrics.rel_frobenius(ott.full(b.x.to_numpy()), u)
+        _say(q.name, f"rel. L2 error {err:.2e}, residual {b.residual:.2e}")
+        assert err <= 1e-10, q.name
 
 
 def test_batched_workload_sample_meets_target_by_oracle_residual():

@@ -55,10 +55,12 @@ def test_mixed_6d_small_grid_matches_schur(seed):
     prob = workloads.gauss_problem(6, 8, 1e-2, 3, seed=seed, tol=1e-12, rank_cap=64)
     _say("mixed", prob.name)
     p, f, ops, A, terms = _setup(prob)
-    r = p.solve(f, tol=1e-12, target=1e-11, max_sweeps=30, kick=8, precision=MIXED)
+    r = p.solve(f, tol=1e-12, target=1e-12, max_sweeps=40, kick=8, precision=MIXED)
     assert r.converged, (r.residual, r.history_residual)
     u = col.solve_schur(ops, col.separable_full(terms))
-    assert metrics.rel_frobenius(ott.full(r.x.to_numpy()), u) <= 1e-9
+    err = metrics.rel_frobenius(ott.full(r.x.to_numpy()), u)
+    _say(f"rel. L2 error {err:.2e}, residual {r.residual:.2e}, sweeps {r.sweeps}")
+    assert err <= 1e-10
 
 
 @pytest.mark.parametrize("case", ["d1", "ragged"])
@@ -69,10 +71,12 @@ def test_mixed_edge_cases_match_dense(case):
     else:
         prob = workloads.gauss_problem(4, [7, 12, 5, 10], 5e-3, 3, seed=7, tol=1e-12, rank_cap=48)
     p, f, ops, A, terms = _setup(prob)
-    r = p.solve(f, tol=1e-12, target=1e-11, max_sweeps=20, kick=4, precision=MIXED)
+    r = p.solve(f, tol=1e-12, target=1e-12, max_sweeps=30, kick=4, precision=MIXED)
     u = col.solve_dense(ops, col.separable_full(terms))[tuple(slice(1, -1) for _ in range(prob.d))]
     assert r.converged, (r.residual, r.history_residual)
-    assert metrics.rel_frobenius(ott.full(r.x.to_numpy()), u) <= 1e-9
+    err = metrics.rel_frobenius(ott.full(r.x.to_numpy()), u)
+    _say(f"rel. L2 error {err:.2e}, residual {r.residual:.2e}, sweeps {r.sweeps}")
+    assert err <= 1e-10
 
 
 def test_mixed_6d_N32_meets_target_by_oracle_residual():

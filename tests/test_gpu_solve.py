@@ -80,11 +80,13 @@ def test_6d_small_grid_matches_schur(seed):
     _say(prob.name)
     p = _gpu_problem(prob)
     f = _gpu_source(p, prob)
-    r = p.solve(f, tol=1e-12, target=1e-11, max_sweeps=30, kick=8)
+    r = p.solve(f, tol=1e-12, target=1e-12, max_sweeps=40, kick=8)
     ops, A, terms = _oracle_system(prob)
     u = col.solve_schur(ops, col.separable_full(terms))
     assert r.converged, (r.residual, r.history_residual)
-    assert metrics.rel_frobenius(ott.full(r.x.to_numpy()), u) <= 1e-9
+    err = metrics.rel_frobenius(ott.full(r.x.to_numpy()), u)
+    _say(f"rel. L2 error {err:.2e}, residual {r.residual:.2e}, sweeps {r.sweeps}")
+    assert err <= 1e-10
 
 
 @pytest.mark.parametrize("case", ["d1", "N3", "ragged", "plain"])
@@ -100,11 +102,13 @@ def test_edge_cases_match_dense(case):
         prob = workloads.gauss_problem(3, 10, 1e-1, 2, seed=8, tol=1e-12, rank_cap=16, scheme=0)
     p = _gpu_problem(prob)
     f = _gpu_source(p, prob)
-    r = p.solve(f, tol=1e-12, target=1e-11, max_sweeps=20, kick=4)
+    r = p.solve(f, tol=1e-12, target=1e-12, max_sweeps=30, kick=4)
     ops, A, terms = _oracle_system(prob)
     u = col.solve_dense(ops, col.separable_full(terms))[tuple(slice(1, -1) for _ in range(prob.d))]
     assert r.converged, (r.residual, r.history_residual)
-    assert metrics.rel_frobenius(ott.full(r.x.to_numpy()), u) <= 1e-9
+    err = metrics.rel_frobenius(ott.full(r.x.to_numpy()), u)
+    _say(f"rel. L2 error {err:.2e}, residual {r.residual:.2e}, sweeps {r.sweeps}")
+    assert err <= 1e-10
 
 
 def test_not_converged_reports_status_and_keeps_iterate():

@@ -100,3 +100,39 @@ def test_superconsistent_has_no_oscillation_in_2d_transport_regime():
     ops_p, f_p, _ = _separable_boundary_layer(2, N, eps, beta, sp.SCHEME_PLAIN)
     u_plain = col.embed_interior(col.solve_schur(ops_p, f_p))
     assert metrics.is_oscillatory(u_plain, expected)
+
+
+# ---- non-zero Dirichlet data (Eq. pblm:time:B with g != 0) ----------------
+import dirichlet_data as dd  # noqa: E402
+
+
+@pytest.mark.parametrize("d,N", [(1, 9), (2, 8), (3, 6)])
+def test_dirichlet_polynomial_reproduced_exactly(d, N):
+    # u of degree <= N - 1 per dimension: E, D1, D2 are exact on it, so the
+    # collocation solution with g = u on the boundary is u itself
+    prob = workloads.dirichlet_problem(d, N, 2e-2, seed=11, kind="poly")
+    ops = col.build_ops(d, N, prob.eps, prob.beta)
+    f = col.separable_full(dd.rhs_terms(prob, [op["theta"] for op in ops]))
+    u_exact = dd.full(dd.boundary_factors(prob, [op["x"] for op in ops]))
+    u = col.solve_dense(ops, f, u_exact)
+    assert metrics.rel_frobenius(u, u_exact) < 1e-11
+    inner = tuple(slice(1, -1) for _ in range(d))
+    u_lift = col.solve_schur(ops, col.lift_rhs(ops, f, u_exact))
+    assert metrics.rel_frobenius(u_lift, u_exact[inner]) < 1e-11
+    # the boundary data matter: solving with g = 0 misses u by O(1)
+    assert metrics.rel_frobenius(col.solve_dense(ops, f), u_exact) > 1e-2
+
+
+def test_dirichlet_lift_and_schur_equal_dense_solve():
+    prob = workloads.dirichlet_problem(3, [10, 8, 9], 5e-3, seed=12, kind="exp")
+    ops = col.build_ops(3, prob.N, prob.eps, prob.beta)
+    f = col.separable_full(dd.rhs_terms(prob, [op["theta"] for op in ops]))
+    g = dd.full(dd.boundary_factors(prob, [op["x"] for op in ops]))
+    g_noisy = g.copy()
+    g_noisy[1:-1, 1:-1, 1:-1] += 1.0          # interior values of g are ignored
+    u = col.solve_dense(ops, f, g)
+    np.testing.assert_array_equal(col.solve_dense(ops, f, g_noisy), u)
+    u_lift = col.solve_schur(ops, col.lift_rhs(ops, f, g_noisy))
+    assert metrics.rel_frobenius(u_lift, u[1:-1, 1:-1, 1:-1]) < 1e-11
+    # boundary values of the dense solution are g
+    assert np.max(np.abs(u[0] - g[0])) < 1e-13 and np.max(np.abs(u[:, :, -1] - g[:, :, -1])) < 1e-13

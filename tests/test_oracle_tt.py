@@ -175,6 +175,35 @@ def test_paper_compression_and_storage_arithmetic():
     assert metrics.tt_storage(s["n"], s["r"], s["d"]) <= s["tt_storage"]
 
 
+def test_compression_ratio_of_paper_sized_tts():
+    # the paper's 7D space-time figure counts d cores of r x n x r entries
+    g = json.load(open(GOLDEN))
+    c7 = g["compression_7d_spacetime"]
+    d, n, r = c7["d"], c7["n"], c7["r"]
+    cores = [np.zeros((r, n, r)) for _ in range(d)]
+    v = tt.compression_ratio(cores)
+    assert abs(v / metrics.compression_bound(n, r, d) - 1.0) < 1e-14
+    assert abs(np.log10(v) - c7["order_of_magnitude"]) < 1.0
+    # with boundary ranks 1 it is the storage of metrics.tt_storage
+    s = g["storage_example"]
+    d, n, r = s["d"], s["n"], s["r"]
+    cores = [np.zeros((1 if l == 0 else r, n, 1 if l == d - 1 else r)) for l in range(d)]
+    assert tt.compression_ratio(cores) * float(n) ** d == metrics.tt_storage(n, r, d)
+    assert tt.compression_ratio(cores) * s["full_storage"] <= s["tt_storage"]
+
+
+def test_mid_axis_profile_and_oscillation_count():
+    # u[i, j, k] = w[i] with w monotone except one dip: one extra sign change
+    w = np.array([0.0, 1.0, 2.0, 1.5, 3.0, 4.0])
+    u = np.broadcast_to(w[:, None, None], (6, 5, 4)).copy()
+    u[:, 0, :] = -7.0                         # off the mid line: ignored
+    np.testing.assert_array_equal(metrics.mid_axis_profile(u, 0), w)
+    assert metrics.oscillation_count(u, 0) == 2
+    assert metrics.is_oscillatory(u, 0) and not metrics.is_oscillatory(u, 2)
+    # along axis 1 the line passes through index 3 of axis 0 (value 1.5)
+    assert metrics.oscillation_count(u, 1) == 0
+
+
 def test_metrics_sign_changes():
     assert metrics.sign_changes([0, 1, 2, 3, 2, 1, 0]) == 1
     assert metrics.sign_changes([0, 1, 0, 1, 0]) == 3

@@ -156,3 +156,25 @@ def warm_instance(seed: int, d: int = WARM_D, N: int = WARM_N) -> Problem:
     return Problem(name=f"warm{d}d_N{N}_{seed}", d=d, N=[N] * d, eps=q["eps"], beta=q["beta"], scheme=1,
                    tol=1e-10, rank_cap=128, source="gauss", gauss=gm, target_residual=1e-8, seed=seed,
                    meta={"params": q})
+
+
+def dirichlet_problem(d: int, N, eps: float, seed: int, kind: str = "exp", rank_cap: int = 32) -> Problem:
+    """Separable exact solution u = prod_l u_l(x_l) that does not vanish on the
+    boundary (Dirichlet data g = u there), drawn from a seed.
+
+    kind "poly": u_l a polynomial of degree N_l - 1 with Legendre coefficients
+    ~ U[-1, 1] (the collocation solution then equals u at the GLL nodes);
+    kind "exp":  u_l(x) = b_l exp(a_l x), a_l ~ U[-1.5, 1.5], b_l ~ U[0.5, 1.5].
+    beta is uniform on the unit sphere.  Parameters only: the source and the
+    boundary values are evaluated by each side on its own grids."""
+    rng = np.random.default_rng(seed)
+    Ns = [int(N)] * d if np.isscalar(N) else [int(v) for v in N]
+    beta = unit_vector(rng, d)
+    if kind == "poly":
+        meta = {"kind": "poly", "coef": [rng.uniform(-1.0, 1.0, size=n) for n in Ns]}
+    elif kind == "exp":
+        meta = {"kind": "exp", "a": rng.uniform(-1.5, 1.5, size=d), "b": rng.uniform(0.5, 1.5, size=d)}
+    else:
+        raise ValueError(kind)
+    return Problem(name=f"{d}d_N{Ns[0]}_dirichlet_{kind}_seed{seed}", d=d, N=Ns, eps=eps, beta=beta, scheme=1,
+                   tol=1e-12, rank_cap=rank_cap, source="dirichlet", seed=seed, meta=meta)
