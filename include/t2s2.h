@@ -201,6 +201,19 @@ int t2s2_problem_colloc(const t2s2_problem* p, int l, double* theta_out);
  * y->ranks is written.  Asynchronous on stream. */
 int t2s2_tt_matvec(const t2s2_ttm* A, const t2s2_tt* x, t2s2_tt* y, void* stream);
 
+/* y = A x exactly as t2s2_tt_matvec, allocating nothing: for callers that
+ * cannot call hipMalloc (code under HIP graph capture, serving loops or
+ * harnesses that forbid allocation).  The caller passes x and y as for
+ * t2s2_tt_matvec; the only scratch, the permuted operator core, lives in a
+ * static device array of 131072 doubles (1 MiB) that each GPU holds until
+ * the process ends, so every core must satisfy R_l n_l^2 R_{l+1} <= 131072
+ * (and n_l <= 64), else T2S2_EINVAL before any work is queued.  The array's
+ * device address is looked up on the first call on each device.  Calls that
+ * overlap on one GPU share that array and race: serialise them (one stream,
+ * or events).  Results are bitwise those of t2s2_tt_matvec.  Asynchronous on
+ * stream. */
+int t2s2_tt_matvec_noalloc(const t2s2_ttm* A, const t2s2_tt* x, t2s2_tt* y, void* stream);
+
 /* ||x||_2 (Frobenius) by the Gram recursion G_l = sum_i X_l(i)^T G_{l-1}
  * X_l(i) carried in double-double arithmetic (error-free products and
  * two-sum accumulation), so ||x||^2 is resolved to ~1e-16 of itself; uses

@@ -224,6 +224,12 @@ class Problem:
         y._read_ranks()
         return y
 
+    def tt_matvec_noalloc(self, x: TT, out: Optional[TT] = None) -> TT:
+        """t2s2_tt_matvec_noalloc with this problem's operator (out: caller's
+        buffers, e.g. preallocated for graph capture)."""
+        op = self.operator()
+        return ttm_matvec(op, x, out=out, noalloc=True)
+
     def tt_norm(self, x: TT) -> float:
         out = C.c_double()
         xs = x._struct()
@@ -333,6 +339,18 @@ def solve_batched(problems: Sequence["Problem"], fs: Sequence[TT], *, x0s: Optio
         x._read_ranks()
         out.append(_result(x, code, reps[i], problems[i].d))
     return out
+
+
+def ttm_matvec(op: "_lib.TTMStruct", x: TT, out: Optional[TT] = None, noalloc: bool = False) -> TT:
+    """y = A x for a TT-matrix descriptor (t2s2_tt_matvec / _noalloc)."""
+    d = x.d
+    R = [int(op.ranks[i]) for i in range(d + 1)]
+    y = out if out is not None else TT.empty_like_ranks(x.n, [R[i] * x.ranks[i] for i in range(d + 1)])
+    xs, ys = x._struct(), y._struct()
+    fn = lib().t2s2_tt_matvec_noalloc if noalloc else lib().t2s2_tt_matvec
+    check(fn(C.byref(op), C.byref(xs), C.byref(ys), _stream()))
+    y._read_ranks()
+    return y
 
 
 def debug_iteration_limits(francis_steps: int = 0, jacobi_sweeps: int = 0) -> None:

@@ -21,7 +21,7 @@ EXPORTED = [
     "t2s2_mlp_create", "t2s2_mlp_destroy", "t2s2_mlp_param_count", "t2s2_mlp_get_params", "t2s2_mlp_set_params",
     "t2s2_mlp_forward", "t2s2_mlp_backward", "t2s2_mlp_adam_step", "t2s2_mlp_infer_bf16", "t2s2_mlp_train",
     "t2s2_tt_fit_loss", "t2s2_tt_pack", "t2s2_tt_unpack", "t2s2_source_gaussians", "t2s2_source_manufactured",
-    "t2s2_debug_iteration_limits",
+    "t2s2_debug_iteration_limits", "t2s2_tt_matvec_noalloc",
 ]
 TIMING_CLASSES = ["gemm_f64", "gemm_c128", "ttm_matvec", "schur_qr", "hessenberg", "jacobi_svd", "cholesky",
                   "trtri", "trevec", "kron_trisolve", "hess_solve", "other"]
@@ -84,6 +84,7 @@ def lib() -> C.CDLL:
     L.t2s2_problem_operator.argtypes = [vp, C.POINTER(TTMStruct)]
     L.t2s2_problem_colloc.argtypes = [vp, C.c_int, dp]
     L.t2s2_tt_matvec.argtypes = [C.POINTER(TTMStruct), C.POINTER(TTStruct), C.POINTER(TTStruct), vp]
+    L.t2s2_tt_matvec_noalloc.argtypes = [C.POINTER(TTMStruct), C.POINTER(TTStruct), C.POINTER(TTStruct), vp]
     L.t2s2_tt_norm.argtypes = [vp, C.POINTER(TTStruct), dp, vp]
     L.t2s2_tt_residual_norm.argtypes = [vp, C.POINTER(TTStruct), C.POINTER(TTStruct), dp, vp]
     L.t2s2_tt_round.argtypes = [vp, C.POINTER(TTStruct), C.c_double, C.c_int, vp]

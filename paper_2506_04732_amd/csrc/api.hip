@@ -242,27 +242,37 @@ int t2s2_problem_colloc(const t2s2_problem* p, int l, double* theta_out) {
   });
 }
 
+static int tt_matvec_common(const t2s2_ttm* A, const t2s2_tt* x, t2s2_tt* y, void* stream, bool noalloc) {
+  T2S2_CHECK(A && A->cores && A->ranks && A->n, "invalid TT-matrix descriptor");
+  t2s2::DTT xd = to_dtt(x);
+  T2S2_CHECK(y && y->cores && y->ranks && y->d == xd.d, "invalid output TT descriptor");
+  T2S2_CHECK(A->d == xd.d, "operator and vector dimensions differ");
+  t2s2::DTTM Ad;
+  Ad.d = A->d;
+  Ad.n.assign(A->n, A->n + A->d);
+  Ad.R.assign(A->ranks, A->ranks + A->d + 1);
+  Ad.c.assign(A->cores, A->cores + A->d);
+  T2S2_CHECK(Ad.R[0] == 1 && Ad.R[Ad.d] == 1, "operator boundary ranks must be 1");
+  for (int l = 0; l < xd.d; ++l) {
+    T2S2_CHECK(Ad.n[l] == xd.n[l] && Ad.n[l] <= 64, "mode sizes must match, <= 64");
+    T2S2_CHECK(Ad.R[l + 1] >= 1 && Ad.c[l] != nullptr, "operator ranks must be positive, cores non-NULL");
+  }
+  t2s2::DTT yd;
+  yd.c.assign(y->cores, y->cores + y->d);
+  t2s2::Ctx c;
+  c.s = static_cast<hipStream_t>(stream);
+  if (noalloc) t2s2::tt_matvec_noalloc(c, Ad, xd, yd);
+  else t2s2::tt_matvec(c, Ad, xd, yd);
+  for (int l = 0; l <= xd.d; ++l) y->ranks[l] = yd.r[l];
+  return T2S2_OK;
+}
+
 int t2s2_tt_matvec(const t2s2_ttm* A, const t2s2_tt* x, t2s2_tt* y, void* stream) {
-  return guarded([&] {
-    T2S2_CHECK(A && A->cores && A->ranks && A->n, "invalid TT-matrix descriptor");
-    t2s2::DTT xd = to_dtt(x);
-    T2S2_CHECK(y && y->cores && y->ranks && y->d == xd.d, "invalid output TT descriptor");
-    T2S2_CHECK(A->d == xd.d, "operator and vector dimensions differ");
-    t2s2::DTTM Ad;
-    Ad.d = A->d;
-    Ad.n.assign(A->n, A->n + A->d);
-    Ad.R.assign(A->ranks, A->ranks + A->d + 1);
-    Ad.c.assign(A->cores, A->cores + A->d);
-    T2S2_CHECK(Ad.R[0] == 1 && Ad.R[Ad.d] == 1, "operator boundary ranks must be 1");
-    for (int l = 0; l < xd.d; ++l) T2S2_CHECK(Ad.n[l] == xd.n[l] && Ad.n[l] <= 64, "mode sizes must match, <= 64");
-    t2s2::DTT yd;
-    yd.c.assign(y->cores, y->cores + y->d);
-    t2s2::Ctx c;
-    c.s = static_cast<hipStream_t>(stream);
-    t2s2::tt_matvec(c, Ad, xd, yd);
-    for (int l = 0; l <= xd.d; ++l) y->ranks[l] = yd.r[l];
-    return T2S2_OK;
-  });
+  return guarded([&] { return tt_matvec_common(A, x, y, stream, false); });
+}
+
+int t2s2_tt_matvec_noalloc(const t2s2_ttm* A, const t2s2_tt* x, t2s2_tt* y, void* stream) {
+  return guarded([&] { return tt_matvec_common(A, x, y, stream, true); });
 }
 
 int t2s2_tt_norm(t2s2_problem* p, const t2s2_tt* x, double* out, void* stream) {

@@ -79,7 +79,12 @@ Problem* problem_create(int d, const int* N, double eps, const double* beta, int
 
 // y = A x, y's cores preallocated by the caller (ranks R r).
 void tt_matvec(const Ctx& c, const DTTM& A, const DTT& x, DTT& y);
-// ||x||_2 (left orthogonalisation of a scratch copy).
+// The same with the permuted operator core in a static device array (no
+// allocation; R_l n_l^2 R_{l+1} <= tt_matvec_noalloc_capacity() per core,
+// n_l <= 64).  Calls that overlap on one GPU share the array and race.
+void tt_matvec_noalloc(const Ctx& c, const DTTM& A, const DTT& x, DTT& y);
+long tt_matvec_noalloc_capacity();
+// ||x||_2 (double-double Gram recursion).
 double tt_norm(const Ctx& c, const DTT& x);
 // ||f - L x|| / ||f|| with the problem's original operator.
 double tt_residual_norm(Problem& p, const Ctx& c, const DTT& x, const DTT& f);

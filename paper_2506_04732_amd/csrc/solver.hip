@@ -21,6 +21,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <mutex>
 
 #include "ddnorm.h"
 #include "kron_hess.h"
@@ -249,14 +250,17 @@ thread_local CoreWork g_core;
 // Core product Y[(a, p), i', (b, q)] = sum_i A[a, i', i, b] X[p, i, q] as, for
 // each a, a GEMM batched over p: Y_p[(i', b), q] = Ahat_a[(i', b), i] X_p[i, q]
 // (rows (i', b) of the output are contiguous with stride r1).
+// Ah: room for the permuted core (R0 n n R1 doubles); NULL: this thread's
+// library-allocated buffer.  timed = false records no events.
 static void core_product(const Ctx& c, int R0, int R1, int n, int r0, int r1, const double* A, const double* X,
-                         double* Y) {
+                         double* Y, double* Ah = nullptr, bool timed = true) {
   const long asz = (long)R0 * n * n * R1;
   TimedScope ts(c.s, KC_TTMV, 8.0 * ((double)r0 * n * r1 + (double)asz + (double)R0 * r0 * n * R1 * r1),
-                2.0 * (double)R0 * R1 * n * n * r0 * r1);
-  double* Ah = g_core.get((size_t)asz);
+                2.0 * (double)R0 * R1 * n * n * r0 * r1, timed);
+  if (!Ah) Ah = g_core.get((size_t)asz);
   ttm_permute(c.s, R0, R1, n, A, Ah);
   const long co = (long)R1 * r1;
+  // K = n <= 64: never split-K, so the GEMM uses no workspace
   for (int a = 0; a < R0; ++a)
     gemm<double>(c.s, OpN, OpN, n * R1, r1, n, 1.0, Ah + (long)a * n * R1 * n, n, 0, X, r1, (long)n * r1, 0.0,
                  Y + (long)a * r0 * n * co, r1, (long)n * co, r0, false);
@@ -272,6 +276,51 @@ void tt_matvec(const Ctx& c, const DTTM& A, const DTT& x, DTT& y) {
     T2S2_CHECK(A.n[l] == x.n[l], "tt_matvec: mode size mismatch");
     core_product(c, A.R[l], A.R[l + 1], x.n[l], x.r[l], x.r[l + 1], A.c[l], x.c[l], y.c[l]);
   }
+}
+
+// ---- TT-matvec without allocation ------------------------------------------
+// The permuted operator core lives in `scratch`, a file-scope device array:
+// one copy per GPU, held until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in): its device
+// address is taken once per device with hipGetSymbolAddress and kept.
+constexpr long kNoAllocDoubles = 1L << 17;  // 1 MiB: R0 n n R1 <= 131072 per core
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+constexpr int kNoAllocMaxDevices = 64;
+static std::mutex g_noalloc_mu;
+static double* g_noalloc_ptr[kNoAllocMaxDevices] = {};
+
+static double* noalloc_scratch() {
+  int dev = 0;
+  T2S2_HIP(hipGetDevice(&dev));
+  T2S2_CHECK(dev >= 0 && dev < kNoAllocMaxDevices, "tt_matvec_noalloc: device index out of range");
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* ptr = nullptr;
+    T2S2_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    T2S2_CHECK(ptr != nullptr, "tt_matvec_noalloc: no device address for the scratch array");
+    g_noalloc_ptr[dev] = static_cast<double*>(ptr);
+  }
+  return g_noalloc_ptr[dev];
+}
+
+long tt_matvec_noalloc_capacity() { return kNoAllocDoubles; }
+
+void tt_matvec_noalloc(const Ctx& c, const DTTM& A, const DTT& x, DTT& y) {
+  T2S2_CHECK(A.d == x.d, "tt_matvec: dimension mismatch");
+  for (int l = 0; l < x.d; ++l) {
+    T2S2_CHECK(A.n[l] == x.n[l] && A.n[l] <= 64, "tt_matvec: mode sizes must match, <= 64");
+    const long asz = (long)A.R[l] * A.n[l] * A.n[l] * A.R[l + 1];
+    T2S2_CHECK(asz <= kNoAllocDoubles, "tt_matvec_noalloc: operator core " + std::to_string(l) + " needs " +
+                                           std::to_string(asz) + " doubles of scratch, more than the " +
+                                           std::to_string(kNoAllocDoubles) + " available");
+  }
+  double* ws = noalloc_scratch();
+  y.d = x.d;
+  y.n = x.n;
+  y.r.assign(x.d + 1, 1);
+  for (int l = 0; l <= x.d; ++l) y.r[l] = A.R[l] * x.r[l];
+  for (int l = 0; l < x.d; ++l)
+    core_product(c, A.R[l], A.R[l + 1], x.n[l], x.r[l], x.r[l + 1], A.c[l], x.c[l], y.c[l], ws, false);
 }
 
 double tt_norm(const Ctx& c, const DTT& x) { return tt_norm_dd(c, x); }
