@@ -278,6 +278,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=3)
     ap.add_argument("--no-oracle-check", action="store_true")
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="6d: every factorisation on the solve's stream (no side-stream eigendecompositions)")
     ap.add_argument("--workload", choices=["6d", "batched256", "warm7d"], default="6d",
                     help="6d: the 6D N=32 solve (default); batched256: 256 uneven instances solved concurrently; "
                          "warm7d: learned warm start on 7D N=24 (train on solver solutions, held-out cold vs warm)")
@@ -316,6 +318,8 @@ def main():
     from paper_2506_04732_amd import TT, sources
 
     prob = workloads.steady_6d(0, 32)
+    if args.no_overlap:
+        SOLVE_OPTS["overlap"] = False
     p = t2s2.Problem(prob.d, prob.N, prob.eps, prob.beta, prob.scheme, rank_cap=RANK_CAP)
     f = sources.gaussians(p, prob.gauss.amp, prob.gauss.centre, prob.gauss.width)
     x = TT.empty(p.m, RANK_CAP)
@@ -382,6 +386,8 @@ def main():
         "sweeps_warm": None,
         "final_ranks": last.ranks,
         "residual": last.residual,
+        "phase_ms": last.phase_ms,
+        "overlap": SOLVE_OPTS.get("overlap", True),
         "roofline": roof,
         "ttm_matvec_hbm": ttmv,
         "kernels": kernels,

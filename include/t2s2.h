@@ -116,6 +116,13 @@ typedef struct {
   int warm_judge;      /* 1: keep x0 only if its FP64 residual ||f - L x0|| /
                           ||f|| is below that of the seeded random start of a
                           cold solve, else start cold; 0: always use x0     */
+  int overlap;         /* FP64 precision: 1 (default) reduces each new
+                          interface to Hessenberg form on the solve's stream
+                          and computes its eigendecomposition (needed only by
+                          the opposite sweep) on a second stream owned by the
+                          problem, concurrently with the sweep; 0 computes
+                          every factorisation on the solve's stream.  Same
+                          arithmetic either way, up to rounding.           */
 } t2s2_options;
 
 /* Per-solve report (host struct filled by t2s2_solve). */
@@ -249,7 +256,10 @@ int t2s2_tt_round(t2s2_problem* p, t2s2_tt* x, double tol, int rmax, void* strea
  *             triangular solves along the mode index;
  *   method 1: Hessenberg form of Lint, eigendecomposition of Rint, Schur form
  *             of K, and per eigenvalue of Rint one Hessenberg-Schur chain
- *             (requires r1 <= 256 and m * ceil(r1/64) * 1024 <= 160000).
+ *             (requires r1 <= 256 and m * ceil(r1/64) * 1024 <= 160000);
+ *   method 2: the mirror image: Hessenberg form of Rint, eigendecomposition
+ *             of Lint, one chain per eigenvalue of Lint (requires r2 <= 256
+ *             and m * ceil(r2/64) * 1024 <= 160000).
  * All arrays are FP64 device buffers owned by the caller, row-major: Lint
  * (r1 x r1), K (m x m), Rint (r2 x r2), g and u (r1 * m * r2); u must not
  * alias g.  One application in FP64, no refinement.  Sizes: r1, r2 <= 512,
@@ -428,7 +438,8 @@ const char* t2s2_timing_class_name(int cls);
 int t2s2_debug_iteration_limits(int francis_steps, int jacobi_sweeps);
 
 /* Defaults: tol 1e-10, target 1e-8, max_sweeps 40, kick 8, rank_cap = the
- * problem's, init_rank 2, seed 0, check_every 1, verbose 0. */
+ * problem's, init_rank 2, seed 0, check_every 1, verbose 0, precision FP64,
+ * warm_judge 0, overlap 1. */
 void t2s2_default_options(t2s2_options* opts);
 
 #ifdef __cplusplus

@@ -28,9 +28,11 @@ residual-based enrichment, alternating sweep directions):
     singular vectors; a QR restores orthonormality and the coefficients move
     to the neighbouring core.  z's core is the residual projected on z's bases.
 5.  Interfaces of x and z are advanced; the direction alternates each sweep.
-6.  Stop when the largest local relative residual seen before the local
-    solves of a sweep is below ``tol`` and the exact TT residual
-    ||b - A x|| / ||b|| (``tt.residual_norm``) meets ``target``, or after
+6.  Stop when the exact TT residual ||b - A x|| / ||b|| (``tt.residual_norm``)
+    meets ``target`` and the largest local relative residual seen before the
+    local solves of a sweep is below 10 ``tol`` (or, with
+    ``stop_on_residual``, on the residual test alone: the stopping rule of
+    the GPU solve, which the timing of the same workload uses), or after
     ``max_sweeps``.
 
 What pins it: tests/test_oracle_amen.py checks the result against the
@@ -162,7 +164,7 @@ def _random_tt(rng, ns, r):
 def solve(A: Sequence[np.ndarray], b: Sequence[np.ndarray], x0: Optional[Sequence[np.ndarray]] = None,
           tol: float = 1e-10, target: float = 1e-8, max_sweeps: int = 30, kick: int = 4,
           rank_cap: int = 200, dense_max: int = 3000, seed: int = 0, verbose: bool = False,
-          local_solver: str = "auto", kron_factors=None):
+          local_solver: str = "auto", kron_factors=None, stop_on_residual: bool = False):
     """Solve A x = b in TT format.  Returns (x cores, info dict)."""
     rng = np.random.default_rng(seed)
     d = len(A)
@@ -277,7 +279,7 @@ def solve(A: Sequence[np.ndarray], b: Sequence[np.ndarray], x0: Optional[Sequenc
         if max_res < tol and res <= target:
             converged = True
             break
-        if res <= target and max_res < 10 * tol:
+        if res <= target and (max_res < 10 * tol or stop_on_residual):
             converged = True
             break
     return x, {"converged": converged, "sweeps": sweeps, "history": history,

@@ -253,7 +253,7 @@ class Problem:
               target: float = 1e-8, max_sweeps: int = 40, kick: int = 8, rank_cap: Optional[int] = None,
               init_rank: int = 2, seed: int = 0, check_every: int = 1, verbose: bool = False,
               out: Optional[TT] = None, precision: int = PRECISION_FP64,
-              warm_judge: bool = False) -> SolveResult:
+              warm_judge: bool = False, overlap: bool = True) -> SolveResult:
         """t2s2_solve.  f on the collocation grid (modes N_l - 2); g optional
         Dirichlet data on the GLL grid (modes N_l); the result holds the
         interior values."""
@@ -261,6 +261,7 @@ class Problem:
         x = out if out is not None else TT.empty(self.m, cap)
         o = _options(tol, target, max_sweeps, kick, cap, init_rank, seed, check_every, verbose, precision)
         o.warm_judge = int(bool(warm_judge))
+        o.overlap = int(bool(overlap))
         rep = _lib.Report()
         fs, xs = f._struct(), x._struct()
         x0s = x0._struct() if x0 is not None else None
@@ -358,7 +359,7 @@ def debug_iteration_limits(francis_steps: int = 0, jacobi_sweeps: int = 0) -> No
     check(lib().t2s2_debug_iteration_limits(int(francis_steps), int(jacobi_sweeps)))
 
 
-LOCAL_EIG, LOCAL_HESS = 0, 1
+LOCAL_EIG, LOCAL_HESS, LOCAL_HESS_RIGHT = 0, 1, 2
 
 
 def local_solve(Lint, K, Rint, g, method: int = LOCAL_HESS):

@@ -41,7 +41,7 @@ class Options(C.Structure):
     _fields_ = [("tol", C.c_double), ("target", C.c_double), ("max_sweeps", C.c_int), ("kick", C.c_int),
                 ("rank_cap", C.c_int), ("init_rank", C.c_int), ("seed", C.c_ulonglong),
                 ("check_every", C.c_int), ("verbose", C.c_int), ("precision", C.c_int),
-                ("warm_judge", C.c_int)]
+                ("warm_judge", C.c_int), ("overlap", C.c_int)]
 
 
 class Report(C.Structure):

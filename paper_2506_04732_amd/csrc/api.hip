@@ -101,6 +101,7 @@ int solve_one(t2s2_problem* p, const t2s2_tt* f, const t2s2_tt* g, const t2s2_tt
                "precision must be T2S2_PRECISION_FP64 or T2S2_PRECISION_MIXED");
     o.precision = opts->precision;
     o.warm_judge = opts->warm_judge;
+    o.overlap = opts->overlap;
   }
   t2s2::DTT xd;
   xd.d = fd.d;
@@ -369,6 +370,7 @@ void t2s2_default_options(t2s2_options* o) {
   o->verbose = 0;
   o->precision = T2S2_PRECISION_FP64;
   o->warm_judge = 0;
+  o->overlap = 1;
 }
 
 int t2s2_solve(t2s2_problem* p, const t2s2_tt* f, const t2s2_tt* g, const t2s2_tt* x0, const t2s2_options* opts,

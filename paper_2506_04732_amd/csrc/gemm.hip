@@ -15,6 +15,8 @@
 // order by a second kernel, so many short workgroups run at once.
 #include "gemm.h"
 
+#include <map>
+
 #include <algorithm>
 #include <type_traits>
 
@@ -201,22 +203,24 @@ struct SplitWork {
     if (p) (void)hipFree(p);
   }
 };
-// one workspace per host thread: concurrent solves (batched mode) drive
-// their own streams from their own threads
-thread_local SplitWork g_split;
+// one workspace per (host thread, stream): concurrent solves (batched mode)
+// drive their own streams from their own threads, and one solve drives a
+// second stream for its side work
+thread_local std::map<hipStream_t, SplitWork> g_split;
 
 template <class T>
-T* split_workspace(size_t count) {
+T* split_workspace(hipStream_t s, size_t count) {
+  SplitWork& w = g_split[s];
   const size_t want = count * sizeof(T);
-  if (g_split.bytes < want) {
-    if (g_split.p) T2S2_HIP(hipFree(g_split.p));
-    g_split.p = nullptr;
-    g_split.bytes = 0;
+  if (w.bytes < want) {
+    if (w.p) T2S2_HIP(hipFree(w.p));
+    w.p = nullptr;
+    w.bytes = 0;
     const size_t alloc = std::max(want, (size_t)1 << 24);
-    T2S2_HIP(hipMalloc(&g_split.p, alloc));
-    g_split.bytes = alloc;
+    T2S2_HIP(hipMalloc(&w.p, alloc));
+    w.bytes = alloc;
   }
-  return static_cast<T*>(g_split.p);
+  return static_cast<T*>(w.p);
 }
 
 template <class T> bool AR_beta_nonzero(T b) { return !Arith<T>::is_zero_host(b); }
@@ -258,7 +262,7 @@ void gemm(hipStream_t s, Op opA, Op opB, int M, int N, int K, T alpha,
     kchunk = ((kchunk + BK - 1) / BK) * BK;
     S = (K + kchunk - 1) / kchunk;
     const long MN = (long)M * N;
-    T* W = split_workspace<T>((size_t)S * MN);
+    T* W = split_workspace<T>(s, (size_t)S * MN);
     dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, S);
     hipLaunchKernelGGL(gemm_kernel<T>, grid, dim3(NT), 0, s, (int)opA, (int)opB, M, N, K, one_of<T>(),
                        A, lda, 0L, B, ldb, 0L, zero_of<T>(), W, (long)N, MN, kchunk);

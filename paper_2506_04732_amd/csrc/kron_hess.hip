@@ -70,7 +70,8 @@ struct TinyR<float> {
 template <class R, int RPL>
 __global__ void __launch_bounds__(64)
 kron_hess_kernel(int r1, int m, int r2, const R* __restrict__ Hc, const typename CxOf<R>::type* __restrict__ T,
-                 const typename CxOf<R>::type* __restrict__ lamR, typename CxOf<R>::type* __restrict__ h) {
+                 const typename CxOf<R>::type* __restrict__ lamR, typename CxOf<R>::type* __restrict__ h, long sa,
+                 long sj, long sb) {
   using C = typename CxOf<R>::type;
   using CX = CxOf<R>;
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -88,7 +89,7 @@ kron_hess_kernel(int r1, int m, int r2, const R* __restrict__ Hc, const typename
 #pragma unroll
     for (int t = 0; t < RPL; ++t) {
       const int a = 64 * t + lane;
-      G[(j * RPL + t) * 64 + lane] = a < r1 ? h[((long)a * m + j) * r2 + b] : zero;
+      G[(j * RPL + t) * 64 + lane] = a < r1 ? h[a * sa + j * sj + b * sb] : zero;
     }
   }
   const C lb = lamR[b];
@@ -214,7 +215,7 @@ kron_hess_kernel(int r1, int m, int r2, const R* __restrict__ Hc, const typename
 #pragma unroll
     for (int t = 0; t < RPL; ++t) {
       const int a = 64 * t + lane;
-      if (a < r1) h[((long)a * m + j) * r2 + b] = acc[t];
+      if (a < r1) h[a * sa + j * sj + b * sb] = acc[t];
     }
     for (int jp = 0; jp < j; ++jp) {
       const C tj = T[(long)jp * m + j];
@@ -230,7 +231,7 @@ kron_hess_kernel(int r1, int m, int r2, const R* __restrict__ Hc, const typename
 
 template <class R>
 static void kron_hess_t(hipStream_t s, int r1, int m, int r2, const R* Hc, const typename CxOf<R>::type* T,
-                        const typename CxOf<R>::type* lamR, typename CxOf<R>::type* h) {
+                        const typename CxOf<R>::type* lamR, typename CxOf<R>::type* h, long sa, long sj, long sb) {
   using C = typename CxOf<R>::type;
   T2S2_CHECK(r1 >= 1 && m >= 1 && r2 >= 1, "kron_hess_solve: sizes must be positive");
   T2S2_CHECK(kron_hess_fits(r1, m, (int)sizeof(C)), "kron_hess_solve: r1 or m too large for the kernel");
@@ -239,10 +240,10 @@ static void kron_hess_t(hipStream_t s, int r1, int m, int r2, const R* Hc, const
   const double cb = sizeof(C);
   TimedScope ts(s, KC_HESSSOLVE, cb * 2.0 * r1 * m * r2 + sizeof(R) * 0.5 * r1 * r1, 8.0 * r1 * r1 * (double)m * r2);
   switch (rpl) {
-    case 1: hipLaunchKernelGGL((kron_hess_kernel<R, 1>), dim3(r2), dim3(64), lds, s, r1, m, r2, Hc, T, lamR, h); break;
-    case 2: hipLaunchKernelGGL((kron_hess_kernel<R, 2>), dim3(r2), dim3(64), lds, s, r1, m, r2, Hc, T, lamR, h); break;
-    case 3: hipLaunchKernelGGL((kron_hess_kernel<R, 3>), dim3(r2), dim3(64), lds, s, r1, m, r2, Hc, T, lamR, h); break;
-    default: hipLaunchKernelGGL((kron_hess_kernel<R, 4>), dim3(r2), dim3(64), lds, s, r1, m, r2, Hc, T, lamR, h); break;
+    case 1: hipLaunchKernelGGL((kron_hess_kernel<R, 1>), dim3(r2), dim3(64), lds, s, r1, m, r2, Hc, T, lamR, h, sa, sj, sb); break;
+    case 2: hipLaunchKernelGGL((kron_hess_kernel<R, 2>), dim3(r2), dim3(64), lds, s, r1, m, r2, Hc, T, lamR, h, sa, sj, sb); break;
+    case 3: hipLaunchKernelGGL((kron_hess_kernel<R, 3>), dim3(r2), dim3(64), lds, s, r1, m, r2, Hc, T, lamR, h, sa, sj, sb); break;
+    default: hipLaunchKernelGGL((kron_hess_kernel<R, 4>), dim3(r2), dim3(64), lds, s, r1, m, r2, Hc, T, lamR, h, sa, sj, sb); break;
   }
   T2S2_LAUNCH_CHECK();
 }
@@ -257,11 +258,16 @@ bool kron_hess_fits(int r1, int m, int cbytes) {
 
 void kron_hess_solve(hipStream_t s, int r1, int m, int r2, const double* Hc, const double2* T, const double2* lamR,
                      double2* h) {
-  kron_hess_t<double>(s, r1, m, r2, Hc, T, lamR, h);
+  kron_hess_t<double>(s, r1, m, r2, Hc, T, lamR, h, (long)m * r2, r2, 1);
 }
 void kron_hess_solve(hipStream_t s, int r1, int m, int r2, const float* Hc, const float2* T, const float2* lamR,
                      float2* h) {
-  kron_hess_t<float>(s, r1, m, r2, Hc, T, lamR, h);
+  kron_hess_t<float>(s, r1, m, r2, Hc, T, lamR, h, (long)m * r2, r2, 1);
+}
+void kron_hess_solve_right(hipStream_t s, int r1, int m, int r2, const double* Hc, const double2* T,
+                           const double2* lamL, double2* h) {
+  // kernel rows = the Hessenberg index c (stride 1), shifts = the left index
+  kron_hess_t<double>(s, r2, m, r1, Hc, T, lamL, h, 1, r2, (long)m * r2);
 }
 
 }  // namespace t2s2

@@ -89,6 +89,10 @@ int trunc_svd(const Ctx& c, int M, int n, const double* A, long lda, double delt
 // form by shifted QR, triangular eigenvectors.  Outputs complex n x n V, Vinv
 // and n eigenvalues.
 void eig_nonsym(const Ctx& c, int n, const double* A, double2* lam, double2* V, double2* Vinv);
+// The same factorisation of A = Q H Q^T given its Hessenberg form (Hc: H
+// column-major, QT = Q^T row-major): Francis QR from H, no reduction.
+void eig_from_hessenberg(const Ctx& c, int n, const double* Hc, const double* QT, double2* lam, double2* V,
+                         double2* Vinv);
 // The same factorisation computed in FP32 from A rounded to FP32.
 void eig_nonsym(const Ctx& c, int n, const double* A, float2* lam, float2* V, float2* Vinv);
 

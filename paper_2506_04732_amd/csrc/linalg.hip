@@ -314,35 +314,63 @@ void hessenberg(const Ctx& c, int n, double* A, double* QT) {
   gemm<double>(c.s, OpN, OpT, n, n, n, -1.0, V, n, 0, W, n, 0, 1.0, QT, n, 0, 1);
 }
 
-void schur_real(const Ctx& c, int n, const double* A, double2* ZT, double2* T) {
+// real upper Hessenberg H = Q^T A Q (row-major) with QT = Q^T (overwritten)
+// -> complex Schur form A = Z T Z^H, ZT = Z^T
+static void schur_from_hess(const Ctx& c, int n, const double* H, double* QT, double2* ZT, double2* T) {
   Scratch& S = *c.sc;
-  double* H = S.get<double>("eig.H", (size_t)n * n);
-  double* QT = S.get<double>("eig.QT", (size_t)n * n);
   double* Hw = S.get<double>("eig.Hw", (size_t)n * n);
   double* Tr = S.get<double>("eig.Tr", (size_t)n * n);
   int* info = S.get<int>("eig.info", 1);
   int* bstart = S.get<int>("eig.bstart", n);
   double2* U = S.get<double2>("eig.U2", 2 * (size_t)n);
-  c.d2d(H, A, (size_t)n * n);
-  hessenberg(c, n, H, QT);
   schur_francis(c.s, n, H, Hw, QT, Tr, info);
   flag_francis(c, info);
   rsf2csf(c.s, n, Tr, QT, T, ZT, bstart, U);
 }
 
-void eig_nonsym(const Ctx& c, int n, const double* A, double2* lam, double2* V, double2* Vinv) {
+void schur_real(const Ctx& c, int n, const double* A, double2* ZT, double2* T) {
   Scratch& S = *c.sc;
-  double2* ZT = S.get<double2>("eig.ZT", (size_t)n * n);
-  double2* T = S.get<double2>("eig.T", (size_t)n * n);
+  double* H = S.get<double>("eig.H", (size_t)n * n);
+  double* QT = S.get<double>("eig.QT", (size_t)n * n);
+  c.d2d(H, A, (size_t)n * n);
+  hessenberg(c, n, H, QT);
+  schur_from_hess(c, n, H, QT, ZT, T);
+}
+
+// complex Schur form -> eigenvectors V = Z Y (Y unit upper triangular,
+// T Y = Y diag(T)), V^{-1} = Y^{-1} Z^H, eigenvalues diag(T)
+static void eig_from_schur(const Ctx& c, int n, const double2* ZT, const double2* T, double2* lam, double2* V,
+                           double2* Vinv) {
+  Scratch& S = *c.sc;
   double2* Y = S.get<double2>("eig.Y", (size_t)n * n);
   double2* Yi = S.get<double2>("eig.Yi", (size_t)n * n);
-  schur_real(c, n, A, ZT, T);
   trevec(c.s, n, T, Y);
   trtri_upper(c.s, n, Y, Yi);
   const double2 one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0);
   gemm<double2>(c.s, OpT, OpN, n, n, n, one, ZT, n, 0, Y, n, 0, zero, V, n, 0, 1);
   gemm<double2>(c.s, OpN, OpR, n, n, n, one, Yi, n, 0, ZT, n, 0, zero, Vinv, n, 0, 1);
   diag_complex(c.s, n, T, n, lam);
+}
+
+void eig_nonsym(const Ctx& c, int n, const double* A, double2* lam, double2* V, double2* Vinv) {
+  Scratch& S = *c.sc;
+  double2* ZT = S.get<double2>("eig.ZT", (size_t)n * n);
+  double2* T = S.get<double2>("eig.T", (size_t)n * n);
+  schur_real(c, n, A, ZT, T);
+  eig_from_schur(c, n, ZT, T, lam, V, Vinv);
+}
+
+void eig_from_hessenberg(const Ctx& c, int n, const double* Hc, const double* QT, double2* lam, double2* V,
+                         double2* Vinv) {
+  Scratch& S = *c.sc;
+  double* H = S.get<double>("eig.H", (size_t)n * n);
+  double* Q = S.get<double>("eig.QT", (size_t)n * n);
+  double2* ZT = S.get<double2>("eig.ZT", (size_t)n * n);
+  double2* T = S.get<double2>("eig.T", (size_t)n * n);
+  transpose(c.s, n, n, Hc, n, H, n);
+  c.d2d(Q, QT, (size_t)n * n);
+  schur_from_hess(c, n, H, Q, ZT, T);
+  eig_from_schur(c, n, ZT, T, lam, V, Vinv);
 }
 
 void eig_nonsym(const Ctx& c, int n, const double* A, float2* lam, float2* V, float2* Vinv) {

@@ -41,6 +41,14 @@ struct Problem {
   std::vector<float2*> dK_ZT32, dK_T32;  // the same rounded to FP32
   std::vector<int> opR;
   Scratch sc;
+  // side streams of the solves (eigendecompositions of interfaces, overlapped
+  // with the sweep), each with its own scratch; created on first use.
+  // side_done[k]: recorded after the last side work of a solve; the next
+  // solve waits for it before it rewrites what that work reads
+  static constexpr int kSides = 2;
+  hipStream_t side[kSides] = {};
+  hipEvent_t side_done[kSides] = {};
+  Scratch sc_side[kSides];
   ~Problem();
 };
 
@@ -56,6 +64,7 @@ struct SolveOptions {
   int verbose = 0;
   int precision = 0;  // 0 FP64, 1 mixed (FP32 factors inside FP64 refinement)
   int warm_judge = 0;  // 1: use x0 only if its FP64 residual beats the seeded cold start's
+  int overlap = 1;     // FP64: interface eigendecompositions on a side stream (0: on the solve's stream)
 };
 
 struct SolveReport {
@@ -91,7 +100,8 @@ double tt_residual_norm(Problem& p, const Ctx& c, const DTT& x, const DTT& f);
 // In-place rounding; x's cores must hold the input ranks.
 void tt_round(const Ctx& c, DTT& x, double tol, int rmax);
 // u = (Lint (+) K (+) Rint)^{-1} g on r1 x m x r2 tensors (device buffers),
-// method 0: eigendecompositions of Lint and Rint, 1: Hessenberg form of Lint.
+// method 0: eigendecompositions of Lint and Rint, 1: Hessenberg form of Lint,
+// 2: Hessenberg form of Rint (eigendecomposition of Lint).
 void local_kron_solve(const Ctx& c, int r1, int m, int r2, const double* Lint, const double* K, const double* Rint,
                       const double* g, double* u, int method);
 // Right-hand side of the interior system for Dirichlet data g (a TT on the

@@ -46,6 +46,13 @@ Problem::~Problem() {
   for (auto p : dK_T) fr(p);
   for (auto p : dK_ZT32) fr(p);
   for (auto p : dK_T32) fr(p);
+  for (int k = 0; k < kSides; ++k) {
+    if (side[k]) {
+      (void)hipStreamSynchronize(side[k]);
+      (void)hipStreamDestroy(side[k]);
+    }
+    if (side_done[k]) (void)hipEventDestroy(side_done[k]);
+  }
 }
 
 static std::vector<double> host_inverse(int n, std::vector<double> A) {
@@ -602,6 +609,26 @@ void kron_inverse_hess(const Ctx& c, int r1, int ml, int r2, const C* ZT, const 
   mode1<double>(c, r1, r1, ml, r2, QT, wr, out, 0.0, OpT);
 }
 
+// The same inverse with the right interface R = Q H Q^T (QT = Q^T row-major,
+// Hc = H column-major) and the left one L = VL diag(lamL) VL^{-1}: Q^T on the
+// real data along mode 3, the mode-1/2 transforms, one Hessenberg-Schur chain
+// per left eigenvalue, back again
+void kron_inverse_hess_right(const Ctx& c, int r1, int ml, int r2, const double2* ZT, const double2* T,
+                             const Eig& eL, const double* QT, const double* Hc, const double* g, double* out,
+                             double2* w0, double2* w1, double* wr) {
+  const long n = (long)r1 * ml * r2;
+  const double2 z0 = cx_zero<double2>();
+  mode3<double>(c, r1, ml, r2, r2, g, QT, wr, 0.0);
+  real_to_complex(c.s, wr, w0, n);
+  mode1<double2>(c, r1, r1, ml, r2, eL.Vi, w0, w1, z0);
+  mode2<double2>(c, r1, ml, ml, r2, ZT, w1, w0, z0, OpR);
+  kron_hess_solve_right(c.s, r1, ml, r2, Hc, T, eL.lam, w0);
+  mode2<double2>(c, r1, ml, ml, r2, ZT, w0, w1, z0, OpT);
+  mode1<double2>(c, r1, r1, ml, r2, eL.V, w1, w0, z0);
+  complex_real_part(c.s, w0, wr, n);
+  mode3<double>(c, r1, ml, r2, r2, wr, QT, out, 0.0, OpN);
+}
+
 struct Amen {
   Problem& p;
   const Ctx& c;
@@ -627,6 +654,18 @@ struct Amen {
   std::vector<char> lhess;        // L[pos] is held as HessF (else as eig / eig32)
   bool mixed = false;
   PhaseClock pc;
+  // FP64 overlap mode: each new interface is reduced to Hessenberg form on
+  // the solve's stream (the next local solve needs it at once) and
+  // eigendecomposed on one of the problem's side streams (only the opposite
+  // sweep needs that form), so Francis QR leaves the sweep's critical path
+  bool overlap = false;
+  Ctx cs[Problem::kSides];             // side-stream contexts
+  int next_side = 0;
+  std::vector<hipEvent_t> ev_eig;      // per bond: its eigendecomposition is done
+  hipEvent_t ev_main = nullptr;        // the interface an eigendecomposition reads is ready
+  std::vector<char> eig_pending;       // ev_eig recorded, the solve's stream has not waited yet
+  std::vector<char> has_eig, has_hess; // forms held for the current interface of each bond
+  enum { M_HL = 0, M_HR = 1, M_EIG = 2 };
   std::vector<int> xr, zr, sr;  // ranks of x, z, f~ per bond
   std::vector<double*> xc, zc, bc;  // cores
   std::vector<int> maxrank;     // structural bound per bond
@@ -637,6 +676,91 @@ struct Amen {
   double* hr;
 
   Amen(Problem& p_, const Ctx& c_, const SolveOptions& o_) : p(p_), c(c_), o(o_) {}
+  ~Amen() {
+    // side work may still run: the next solve on this problem waits for it
+    if (overlap)
+      for (int k = 0; k < Problem::kSides; ++k)
+        if (cs[k].s) (void)hipEventRecord(p.side_done[k], cs[k].s);
+    for (auto e : ev_eig)
+      if (e) (void)hipEventDestroy(e);
+    if (ev_main) (void)hipEventDestroy(ev_main);
+  }
+
+  // ---- overlap mode -------------------------------------------------------
+  // Hessenberg form of the interface at bond pos for the local solves of site
+  // `site` (false if the chain kernel cannot take it)
+  bool hess_into(int pos, int n, int site) {
+    if (site < 0 || site >= d || !kron_hess_fits(n, m[site], (int)sizeof(double2))) return false;
+    double* Hw = buf("hess.H", (size_t)n * n);
+    c.d2d(Hw, L[pos], (size_t)n * n);
+    hessenberg(c, n, Hw, hf[pos].QT);
+    transpose(c.s, n, n, Hw, n, hf[pos].Hc, n);
+    return true;
+  }
+  // eigendecomposition of the interface at bond pos on a side stream (from
+  // its Hessenberg form when it has one)
+  void eig_async(int pos, int n) {
+    const Ctx& x = cs[next_side];
+    next_side = (next_side + 1) % Problem::kSides;
+    T2S2_HIP(hipEventRecord(ev_main, c.s));
+    T2S2_HIP(hipStreamWaitEvent(x.s, ev_main, 0));
+    if (has_hess[pos])
+      eig_from_hessenberg(x, n, hf[pos].Hc, hf[pos].QT, eig[pos].lam, eig[pos].V, eig[pos].Vi);
+    else
+      eig_nonsym(x, n, L[pos], eig[pos].lam, eig[pos].V, eig[pos].Vi);
+    T2S2_HIP(hipEventRecord(ev_eig[pos], x.s));
+    eig_pending[pos] = 1;
+    has_eig[pos] = 1;
+  }
+  void wait_eig(int pos) {
+    if (!eig_pending[pos]) return;
+    T2S2_HIP(hipStreamWaitEvent(c.s, ev_eig[pos], 0));
+    eig_pending[pos] = 0;
+  }
+  void need_eig(int pos, int n) {
+    if (has_eig[pos]) {
+      wait_eig(pos);
+      return;
+    }
+    eig_nonsym(c, n, L[pos], eig[pos].lam, eig[pos].V, eig[pos].Vi);
+    has_eig[pos] = 1;
+  }
+  // a new interface at bond pos (size n), left or right of the sites that use
+  // it next; hess: reduce it now (the next site needs it)
+  void new_interface(int pos, int n, bool left, bool hess) {
+    has_hess[pos] = hess && hess_into(pos, n, left ? pos : pos - 1);
+    has_eig[pos] = 0;
+    // the opposite sweep uses the eigendecomposition, except of the left
+    // interface at bond d-1 (site d-1 is solved with its Hessenberg form)
+    if (left && pos == d - 1 && has_hess[pos]) return;
+    if (has_hess[pos] || !hess) eig_async(pos, n);
+    else need_eig(pos, n);
+  }
+  // form of the local solve at site l going in direction dir
+  int pick_mode(int l, int dir, int r1, int r2) {
+    const bool fwd = dir > 0 || l == d - 1;
+    if (fwd && has_hess[l]) {
+      need_eig(l + 1, r2);
+      return M_HL;
+    }
+    if (!fwd && has_hess[l + 1]) {
+      need_eig(l, r1);
+      return M_HR;
+    }
+    need_eig(l, r1);
+    need_eig(l + 1, r2);
+    return M_EIG;
+  }
+  void local_solve_ov(int mode, int l, int r1, int r2, const double* g, double* out) {
+    if (mode == M_HL)
+      kron_inverse_hess<double2, double>(c, r1, m[l], r2, p.dK_ZT[l], p.dK_T[l], hf[l].QT, hf[l].Hc, eig[l + 1], g,
+                                         out, h0, h1, hr);
+    else if (mode == M_HR)
+      kron_inverse_hess_right(c, r1, m[l], r2, p.dK_ZT[l], p.dK_T[l], eig[l], hf[l + 1].QT, hf[l + 1].Hc, g, out,
+                              h0, h1, hr);
+    else
+      kron_inverse_eig<double2>(c, r1, m[l], r2, p.dK_ZT[l], p.dK_T[l], eig[l], eig[l + 1], g, out, h0, h1);
+  }
 
   double* buf(const std::string& n, size_t cnt) { return c.sc->get<double>("am." + n, cnt); }
 
@@ -731,6 +855,9 @@ struct Amen {
       c.h2d(hf[pos].Hc32, &zf1, 1);
       lhess[pos] = 1;
     }
+    has_eig[pos] = 1;
+    has_hess[pos] = lhess[pos];
+    eig_pending[pos] = 0;
     c.sync();
   }
 
@@ -740,6 +867,7 @@ struct Amen {
     const int r0 = xr[l], r1 = xr[l + 1], q0 = zr[l], q1 = zr[l + 1], s0 = sr[l], s1 = sr[l + 1], ml = m[l];
     const double* X = xc[l];
     const double* Z = zc[l];
+    if (overlap) wait_eig(l + 1);  // the side stream may still read L[l+1]
     // L' = X^T (L x1 X + K x2 X)
     mode1<double>(c, r0, r0, ml, r1, L[l], X, T1, 0.0);
     mode2<double>(c, r0, ml, ml, r1, p.dK[l], X, T1, 1.0);
@@ -756,14 +884,17 @@ struct Amen {
     // ZB' = Z^T (ZB x1 b)
     mode1<double>(c, q0, s0, ml, s1, ZB[l], bc[l], T1, 0.0);
     gemm<double>(c.s, OpT, OpN, q1, s1, q0 * ml, 1.0, Z, q1, 0, T1, s1, 0, 0.0, ZB[l + 1], s1, 0, 1);
-    factor_left(l + 1, r1);
+    if (overlap) new_interface(l + 1, r1, true, true);
+    else factor_left(l + 1, r1);
   }
 
-  // right interfaces at pos l from pos l+1 and cores x_l, z_l
-  void update_right(int l) {
+  // right interfaces at pos l from pos l+1 and cores x_l, z_l; hess: also
+  // reduce L[l] to Hessenberg form for the next site (l-1) of a backward sweep
+  void update_right(int l, bool hess = true) {
     const int r0 = xr[l], r1 = xr[l + 1], q0 = zr[l], q1 = zr[l + 1], s0 = sr[l], s1 = sr[l + 1], ml = m[l];
     const double* X = xc[l];
     const double* Z = zc[l];
+    if (overlap) wait_eig(l);  // the side stream may still read L[l]
     // L' = X_mat (K x2 X + X x3 L)^T
     mode2<double>(c, r0, ml, ml, r1, p.dK[l], X, T1, 0.0);
     mode3<double>(c, r0, ml, r1, r1, X, L[l + 1], T1, 1.0);
@@ -780,7 +911,8 @@ struct Amen {
     // ZB' = Z_mat (b x3 ZB)^T  (q0 x s0)
     mode3<double>(c, s0, ml, s1, q1, bc[l], ZB[l + 1], T1, 0.0);
     gemm<double>(c.s, OpN, OpT, q0, s0, ml * q1, 1.0, Z, (long)ml * q1, 0, T1, (long)ml * q1, 0, 0.0, ZB[l], s0, 0, 1);
-    factor(l, r0);
+    if (overlap) new_interface(l, r0, false, hess);
+    else factor(l, r0);
   }
 
   // right-orthogonalise a TT held in cores (in place); ranks updated
@@ -846,6 +978,29 @@ struct Amen {
     hf.resize(d + 1);
     lhess.assign(d + 1, 0);
     mixed = (o.precision == 1);
+    overlap = !mixed && o.overlap != 0;
+    eig_pending.assign(d + 1, 0);
+    has_eig.assign(d + 1, 0);
+    has_hess.assign(d + 1, 0);
+    if (overlap) {
+      for (int k = 0; k < Problem::kSides; ++k) {
+        if (!p.side[k]) {
+          T2S2_HIP(hipStreamCreateWithFlags(&p.side[k], hipStreamNonBlocking));
+          T2S2_HIP(hipEventCreateWithFlags(&p.side_done[k], hipEventDisableTiming));
+          T2S2_HIP(hipEventRecord(p.side_done[k], p.side[k]));
+        }
+        cs[k].s = p.side[k];
+        cs[k].sc = &p.sc_side[k];
+        cs[k].fail = c.fail;
+        // side work of an earlier solve on this problem reads interfaces and
+        // writes factors and the failure flag, all rewritten from here on
+        T2S2_HIP(hipStreamWaitEvent(c.s, p.side_done[k], 0));
+      }
+      ev_eig.assign(d + 1, nullptr);
+      for (auto& e : ev_eig) T2S2_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      T2S2_HIP(hipEventCreateWithFlags(&ev_main, hipEventDisableTiming));
+    }
+    clear_fail(c);
     for (int l = 0; l <= d; ++l) {
       const std::string t = std::to_string(l);
       L[l] = buf("L" + t, (size_t)cap * cap);
@@ -926,7 +1081,9 @@ struct Amen {
     right_orth(zc, zr);
     set_boundary(0);
     set_boundary(d);
-    for (int l = d - 1; l >= 1; --l) update_right(l);
+    // the first sweep goes left to right: it needs the eigendecompositions
+    // of the right interfaces, not their Hessenberg forms
+    for (int l = d - 1; l >= 1; --l) update_right(l, false);
 
     const double loc_tol = o.tol / std::sqrt((double)d);
     int status = 3;
@@ -961,13 +1118,17 @@ struct Amen {
           // FP32 corrections need current FP32 factors on both sides; a bond
           // that keeps FP64 factors makes its neighbours' systems FP64 too
           bool use64 = !mixed || !(ok32[l] && ok32[l + 1]);
-          if (use64) {
+          const int mode = overlap ? pick_mode(l, direction, r1, r2) : -1;
+          if (use64 && !overlap) {
             ensure64(l, r1);
             ensure64(l + 1, r2);
           }
           double prev = rn;
           for (int it = 0, it32 = 0, it64 = 0; it < 14; ++it) {
-            if (use64) {
+            if (overlap) {
+              local_solve_ov(mode, l, r1, r2, res, y);
+              ++it64;
+            } else if (use64) {
               local_solve(l, r1, r2, eig[l], eig[l + 1], res, y);
               ++it64;
             } else {
@@ -1058,6 +1219,7 @@ struct Amen {
     pc.mark(0);
     c.sync();
     pc.collect(rep.phase_ms);
+    if (read_fail(c)) throw Error(5, "solve: Francis QR of an interface matrix did not converge");
     rep.time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     return status;
   }
@@ -1198,9 +1360,12 @@ void local_kron_solve(const Ctx& c0, int r1, int m, int r2, const double* Lint, 
                       const double* g, double* u, int method) {
   T2S2_CHECK(r1 >= 1 && m >= 1 && r2 >= 1, "local_solve: sizes must be positive");
   T2S2_CHECK(r1 <= 512 && r2 <= 512 && m <= 64, "local_solve: r1, r2 <= 512 and m <= 64 required");
-  T2S2_CHECK(method == 0 || method == 1, "local_solve: method must be 0 (eigen) or 1 (Hessenberg)");
-  T2S2_CHECK(method == 0 || kron_hess_fits(r1, m, (int)sizeof(double2)),
+  T2S2_CHECK(method >= 0 && method <= 2,
+             "local_solve: method must be 0 (eigen), 1 (Hessenberg left) or 2 (Hessenberg right)");
+  T2S2_CHECK(method != 1 || kron_hess_fits(r1, m, (int)sizeof(double2)),
              "local_solve: method 1 needs r1 <= 256 and the m right-hand sides of a chain in LDS");
+  T2S2_CHECK(method != 2 || kron_hess_fits(r2, m, (int)sizeof(double2)),
+             "local_solve: method 2 needs r2 <= 256 and the m right-hand sides of a chain in LDS");
   Scratch& S = *c0.sc;
   Ctx c = c0;
   c.fail = S.get<int>("ctx.fail", 1);
@@ -1209,13 +1374,31 @@ void local_kron_solve(const Ctx& c0, int r1, int m, int r2, const double* Lint, 
   double2* ZT = S.get<double2>("loc.ZT", (size_t)m * m);
   double2* T = S.get<double2>("loc.T", (size_t)m * m);
   schur_real(c, m, K, ZT, T);
+  double2* w0 = S.get<double2>("loc.w0", n);
+  double2* w1 = S.get<double2>("loc.w1", n);
+  if (method == 2) {
+    Eig eL;
+    eL.lam = S.get<double2>("loc.lamL", r1);
+    eL.V = S.get<double2>("loc.VL", (size_t)r1 * r1);
+    eL.Vi = S.get<double2>("loc.ViL", (size_t)r1 * r1);
+    eig_nonsym(c, r1, Lint, eL.lam, eL.V, eL.Vi);
+    double* Hw = S.get<double>("loc.H", (size_t)r2 * r2);
+    double* QT = S.get<double>("loc.QT", (size_t)r2 * r2);
+    double* Hc = S.get<double>("loc.Hc", (size_t)r2 * r2);
+    double* wr = S.get<double>("loc.wr", n);
+    c.d2d(Hw, Rint, (size_t)r2 * r2);
+    hessenberg(c, r2, Hw, QT);
+    transpose(c.s, r2, r2, Hw, r2, Hc, r2);
+    kron_inverse_hess_right(c, r1, m, r2, ZT, T, eL, QT, Hc, g, u, w0, w1, wr);
+    c.sync();
+    if (read_fail(c)) throw Error(5, "local_solve: Francis QR did not converge");
+    return;
+  }
   Eig eR;
   eR.lam = S.get<double2>("loc.lamR", r2);
   eR.V = S.get<double2>("loc.VR", (size_t)r2 * r2);
   eR.Vi = S.get<double2>("loc.ViR", (size_t)r2 * r2);
   eig_nonsym(c, r2, Rint, eR.lam, eR.V, eR.Vi);
-  double2* w0 = S.get<double2>("loc.w0", n);
-  double2* w1 = S.get<double2>("loc.w1", n);
   if (method == 0) {
     Eig eL;
     eL.lam = S.get<double2>("loc.lamL", r1);
@@ -1240,7 +1423,6 @@ void local_kron_solve(const Ctx& c0, int r1, int m, int r2, const double* Lint, 
 int solve(Problem& p, const Ctx& c0, const DTT& f, const DTT* x0, const SolveOptions& o, DTT& x, SolveReport& rep) {
   Ctx c = c0;
   c.fail = c.sc->get<int>("ctx.fail", 1);
-  clear_fail(c);
   Amen a(p, c, o);
   return a.run(f, x0, x, rep);
 }

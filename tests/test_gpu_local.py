@@ -8,8 +8,9 @@ advection-diffusion operators onto random orthonormal bases, K is a scaled 1D
 operator.  Sizes span 1..4 row slots of the Hessenberg-Schur kernel (r1 = 1,
 37, 70, 130, 200, 256), ragged m and r2.
 
-Bar: both methods (eigendecompositions of both interfaces; Hessenberg form
-of the left one) solve in FP64 through similarity transforms, so their
+Bar: the three methods (eigendecompositions of both interfaces; Hessenberg
+form of the left one; Hessenberg form of the right one) solve in FP64
+through similarity transforms, so their
 forward error is bounded by a modest multiple of the unit roundoff times
 cond(B) and the condition numbers of the eigenvector bases used:
 ||u - u*|| <= 64 eps cond(B) cond(V_L) cond(V_R) ||u*|| (cond(V_L) taken as 1
@@ -50,7 +51,11 @@ def _case(seed, r1, m, r2):
     N1 = max(18, int(np.ceil(np.sqrt(r1))) + 3)        # (N1 - 2)^2 >= r1
     KL = _interface(rng, r1, [_k1d(N1, 2e-3, 0.4), _k1d(N1, 2e-3, -0.7)]) if r1 > 1 else np.zeros((1, 1))
     K = _k1d(m + 2, 2e-3, 0.3)
-    KR = _interface(rng, r2, [_k1d(8, 2e-3, 0.5)]) if r2 > 1 else np.zeros((1, 1))
+    if r2 <= 6:
+        KR = _interface(rng, r2, [_k1d(8, 2e-3, 0.5)]) if r2 > 1 else np.zeros((1, 1))
+    else:
+        N2 = max(18, int(np.ceil(np.sqrt(r2))) + 3)
+        KR = _interface(rng, r2, [_k1d(N2, 2e-3, -0.3), _k1d(N2, 2e-3, 0.8)])
     g = rng.standard_normal((r1, m, r2))
     return KL, K, KR, g
 
@@ -59,7 +64,8 @@ def _cuda(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
 
 
-CASES = [(1, 6, 4), (37, 5, 3), (70, 6, 5), (130, 4, 3), (200, 3, 2), (256, 2, 2), (64, 9, 1)]
+CASES = [(1, 6, 4), (37, 5, 3), (70, 6, 5), (130, 4, 3), (200, 3, 2), (256, 2, 2), (64, 9, 1),
+         (3, 6, 130), (4, 5, 200), (2, 3, 256), (40, 7, 70)]
 
 
 @pytest.mark.parametrize("r1,m,r2", CASES)
@@ -70,14 +76,20 @@ def test_local_solve_matches_dense(r1, m, r2):
     cond = np.linalg.cond(B) * np.linalg.cond(np.linalg.eig(KL)[1]) * np.linalg.cond(np.linalg.eig(KR)[1])
     bar = 64 * np.finfo(np.float64).eps * cond
     outs = {}
-    for method in (t2s2.LOCAL_EIG, t2s2.LOCAL_HESS):
+    methods = [t2s2.LOCAL_EIG]
+    if r1 <= 256:
+        methods.append(t2s2.LOCAL_HESS)
+    if r2 <= 256:
+        methods.append(t2s2.LOCAL_HESS_RIGHT)
+    for method in methods:
         _say("local solve", r1, m, r2, "method", method)
         u = t2s2.local_solve(_cuda(KL), _cuda(K), _cuda(KR), _cuda(g), method=method).cpu().numpy()
         err = np.linalg.norm(u - ref) / np.linalg.norm(ref)
         _say(f"  rel err {err:.2e} (bar {bar:.2e})")
         assert err <= bar
         outs[method] = u
-    assert np.linalg.norm(outs[0] - outs[1]) <= 2 * bar * np.linalg.norm(ref)
+    for method in methods[1:]:
+        assert np.linalg.norm(outs[0] - outs[method]) <= 2 * bar * np.linalg.norm(ref)
 
 
 def test_local_solve_eigen_path_beyond_256_rows():
@@ -102,5 +114,8 @@ def test_local_solve_rejects_unsupported_sizes():
         # Hessenberg-Schur chains hold at most 256 rows
         big = np.eye(300)
         t2s2.local_solve(_cuda(big), _cuda(K), _cuda(KR), _cuda(np.zeros((300, 3, 2))), method=t2s2.LOCAL_HESS)
+    with pytest.raises(t2s2.T2S2Error):
+        t2s2.local_solve(_cuda(KR), _cuda(K), _cuda(big), _cuda(np.zeros((2, 3, 300))),
+                         method=t2s2.LOCAL_HESS_RIGHT)
     with pytest.raises(t2s2.T2S2Error):
         t2s2.local_solve(_cuda(KL), _cuda(K), _cuda(KR), _cuda(g), method=5)

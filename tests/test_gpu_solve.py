@@ -74,13 +74,13 @@ def test_3d_transport_matches_schur():
     assert metrics.rel_frobenius(ott.full(xg), u) <= 1e-10
 
 
-@pytest.mark.parametrize("seed", [1, 2])
-def test_6d_small_grid_matches_schur(seed):
+@pytest.mark.parametrize("seed,overlap", [(1, True), (2, True), (1, False)])
+def test_6d_small_grid_matches_schur(seed, overlap):
     prob = workloads.gauss_problem(6, 8, 1e-2, 3, seed=seed, tol=1e-12, rank_cap=64)
-    _say(prob.name)
+    _say(prob.name, "overlap" if overlap else "single stream")
     p = _gpu_problem(prob)
     f = _gpu_source(p, prob)
-    r = p.solve(f, tol=1e-12, target=1e-12, max_sweeps=40, kick=8)
+    r = p.solve(f, tol=1e-12, target=1e-12, max_sweeps=40, kick=8, overlap=overlap)
     ops, A, terms = _oracle_system(prob)
     u = col.solve_schur(ops, col.separable_full(terms))
     assert r.converged, (r.residual, r.history_residual)
