@@ -85,43 +85,61 @@ def load_traffic(kernel: str):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(prob, gpu_result, sweeps: int) -> dict:
-    """The oracle (NumPy FP64 AMEn with exact Kronecker local solves) on the
-    host cores: the first `sweeps` sweeps of the same workload, timed, then
-    scaled to the full solve by the GPU's own time ratio (full / first sweeps)."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_solve(prob, threads):
+    """The oracle's full solve of the bench workload (FP64 NumPy AMEn with
+    exact Kronecker local solves), stopped by the GPU solve's rule (FP64
+    residual <= target): (seconds, info, BLAS threads used)."""
     import numpy as np
+    from threadpoolctl import threadpool_info, threadpool_limits
     from oracle import amen as oamen
     from oracle import collocation as col
     from oracle import tt as ott
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count() or 1])
-    except Exception:
-        threads = os.cpu_count() or 1
     ops = col.build_ops(prob.d, prob.N, prob.eps, prob.beta, prob.scheme)
     Es, Ms = col.interior_factors(ops)
     A = ott.kron_sum_ttm(Es, Ms)
     b = ott.separable_to_tt(col.gauss_rhs_factors(ops, prob.gauss.amp, prob.gauss.centre, prob.gauss.width))
-    t0 = time.perf_counter()
     rng = np.random.default_rng(SOLVE_OPTS["seed"])
     r0 = SOLVE_OPTS["init_rank"]
     ms = [n - 2 for n in prob.N]
     rs = [1] + [min(r0, 30 ** min(l, prob.d - l)) for l in range(1, prob.d)] + [1]
     x0 = [rng.standard_normal((rs[l], ms[l], rs[l + 1])) for l in range(prob.d)]
-    _, info = oamen.solve(A, b, x0=x0, tol=SOLVE_OPTS["tol"], target=1e-30, max_sweeps=sweeps,
-                          kick=SOLVE_OPTS["kick"], rank_cap=RANK_CAP, local_solver="kron", kron_factors=(Es, Ms))
-    t_cpu = time.perf_counter() - t0
-    hist = gpu_result.history_time_ms
-    k = min(sweeps, len(hist))
-    gpu_prefix = hist[k - 1] / 1e3
-    gpu_total = gpu_result.time_ms / 1e3
-    est = t_cpu * gpu_total / gpu_prefix if gpu_prefix > 0 else None
-    return {"value": est, "unit": "s", "cores": int(threads), "kind": "oracle",
-            "sample": f"first {sweeps} sweeps of the same 6D N=32 solve (oracle max rank "
-                      f"{info['history'][-1]['max_rank']}, residual {info['history'][-1]['residual']:.2e}) "
-                      f"took {t_cpu:.1f} s; scaled by the GPU full/prefix time ratio "
-                      f"({gpu_total:.3f} s / {gpu_prefix:.3f} s)",
-            "measured_s": t_cpu, "measured_sweeps": sweeps}
+    with threadpool_limits(limits=threads):
+        used = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        t0 = time.perf_counter()
+        _, info = oamen.solve(A, b, x0=x0, tol=SOLVE_OPTS["tol"], target=SOLVE_OPTS["target"], max_sweeps=40,
+                              kick=SOLVE_OPTS["kick"], rank_cap=RANK_CAP, local_solver="kron",
+                              kron_factors=(Es, Ms), stop_on_residual=True)
+        t = time.perf_counter() - t0
+    return t, info, int(used)
+
+
+def cpu_baseline(prob, one_thread: bool = True) -> dict:
+    """The oracle as it stands, timed on the host cores on the whole bench
+    workload (not a sample): once with every BLAS thread, once with one."""
+    t_all, info, used = _oracle_solve(prob, None)
+    print(f"cpu baseline: oracle full solve {t_all:.1f} s on {used} threads, {info['sweeps']} sweeps",
+          file=sys.stderr, flush=True)
+    out = {"value": t_all, "unit": "s", "cores": used, "kind": "oracle",
+           "sample": f"the whole 6D N=32 solve (not a sample): oracle AMEn from a seeded rank-"
+                     f"{SOLVE_OPTS['init_rank']} NumPy start, stopped at FP64 residual <= {SOLVE_OPTS['target']}",
+           "sweeps": info["sweeps"], "residual": info["residual"], "ranks": info["ranks"],
+           "cpu_model": _cpu_model(), "logical_cpus": os.cpu_count()}
+    if one_thread:
+        t1, info1, used1 = _oracle_solve(prob, 1)
+        print(f"cpu baseline: oracle full solve {t1:.1f} s on {used1} thread", file=sys.stderr, flush=True)
+        out.update({"value_1thread": t1, "sweeps_1thread": info1["sweeps"], "residual_1thread": info1["residual"]})
+    return out
 
 
 BATCH_OPTS = dict(tol=1e-10, target=1e-8, max_sweeps=30, kick=8, init_rank=8, check_every=0, seed=0)
@@ -190,11 +208,11 @@ def bench_batched(args, rank: int):
 WARM_OPTS = dict(tol=1e-10, target=1e-8, max_sweeps=30, kick=8, init_rank=8, check_every=0, seed=0)
 
 
-def bench_warm(args, rank: int):
+def warm_leg(train: int, test: int, epochs: int, workers: int, log=True) -> dict:
     """Learned warm start, 7D N=24: solve train + test instances (batched),
     train the 3x256 network on the training solutions (rank-8 targets), then
     solve each held-out instance cold and warm (BF16 inference, residual
-    judge).  value = mean seconds per held-out warm solve (inference incl.)."""
+    judge)."""
     import numpy as np
     import torch
     import paper_2506_04732_amd as t2s2
@@ -202,7 +220,7 @@ def bench_warm(args, rank: int):
     from paper_2506_04732_amd import sources, warmstart
 
     d, N, r8, cap = 7, 24, 8, 128
-    ntr, nte = args.train, args.test
+    ntr, nte = train, test
     t0 = time.perf_counter()
     insts = [workloads.warm_instance(10 ** 6 + i) for i in range(ntr + nte)]
     probs = [t2s2.Problem(q.d, q.N, q.eps, q.beta, q.scheme, rank_cap=cap) for q in insts]
@@ -210,9 +228,10 @@ def bench_warm(args, rank: int):
           for p, q in zip(probs, insts)]
     res = []
     for k in range(0, len(probs), 64):
-        res += t2s2.solve_batched(probs[k:k + 64], fs[k:k + 64], workers=args.workers, **WARM_OPTS)
-        print(f"warm7d: solved {len(res)} / {len(probs)} in {time.perf_counter() - t0:.0f} s", file=sys.stderr,
-              flush=True)
+        res += t2s2.solve_batched(probs[k:k + 64], fs[k:k + 64], workers=workers, **WARM_OPTS)
+        if log:
+            print(f"warm7d: solved {len(res)} / {len(probs)} in {time.perf_counter() - t0:.0f} s", file=sys.stderr,
+                  flush=True)
     t_gen = time.perf_counter() - t0
     m = [N - 2] * d
     T = torch.stack([warmstart.solution_target(p, r.x, r8) for p, r in zip(probs, res)])
@@ -220,11 +239,12 @@ def bench_warm(args, rank: int):
     net = warmstart.Network([X.shape[1], 256, 256, 256, warmstart.flat_size(m, r8)], seed=0)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    hist = net.train(X[:ntr].contiguous(), T[:ntr].contiguous(), m, r8, epochs=args.epochs, batch=32, lr=1e-3, seed=1)
+    hist = net.train(X[:ntr].contiguous(), T[:ntr].contiguous(), m, r8, epochs=epochs, batch=32, lr=1e-3, seed=1)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
-    print(f"warm7d: trained {args.epochs} epochs in {t_train:.0f} s, loss {hist[0]:.3f} -> {hist[-1]:.3f}",
-          file=sys.stderr, flush=True)
+    if log:
+        print(f"warm7d: trained {epochs} epochs in {t_train:.0f} s, loss {hist[0]:.3f} -> {hist[-1]:.3f}",
+              file=sys.stderr, flush=True)
     Xte, Tte = X[ntr:].contiguous(), T[ntr:].contiguous()
     held, _ = warmstart.fit_loss(net.infer_bf16(Xte).contiguous(), Tte, m, r8)
     base, _ = warmstart.fit_loss(T[:ntr].mean(0, keepdim=True).expand(nte, -1).contiguous(), Tte, m, r8)
@@ -249,21 +269,32 @@ def bench_warm(args, rank: int):
         rho_w.append(rw.warm_residual)
         rho_c.append(rw.cold_residual)
         conv_w.append(rw.converged)
-    out = {
-        "metric": "learned warm start, 7D N=24: seconds per held-out solve to rel. resid 1e-8 (warm incl. BF16 "
-                  "inference)",
-        "value": float(np.mean(warm_s)), "unit": "s", "n_gpus": 1, "steps": nte, "warmup": 0,
-        "ms_per_step": float(np.mean(warm_s)) * 1e3, "higher_is_better": False, "scaling": "strong",
-        "vs_baseline": None, "dtype": "f64 solve, f32 train, bf16 infer", "data": "synthetic",
-        "config": {"workload": "warm7d_N24_eps1e-4-1e-2_gauss4x3", "train": ntr, "test": nte,
-                   "epochs": args.epochs, "rank": r8, "rank_cap": cap, **WARM_OPTS},
+    return {
+        "workload": "warm7d_N24_eps1e-4-1e-2_gauss4x3", "train": ntr, "test": nte, "epochs": epochs, "rank": r8,
+        "rank_cap": cap, **WARM_OPTS,
         "cold_s_mean": float(np.mean(cold_s)), "warm_s_mean": float(np.mean(warm_s)),
         "sweeps_cold_mean": float(np.mean(cold_sw)), "sweeps_warm_mean": float(np.mean(warm_sw)),
         "sweeps_cold": cold_sw, "sweeps_warm": warm_sw, "warm_used": int(sum(used)),
         "warm_converged": int(sum(conv_w)),
-        "heldout_fit_loss_median": float(held.median().item()), "mean_target_fit_loss_median": float(base.median().item()),
+        "heldout_fit_loss_median": float(held.median().item()),
+        "mean_target_fit_loss_median": float(base.median().item()),
         "warm_residual_median": float(np.median(rho_w)), "cold_residual_median": float(np.median(rho_c)),
         "train_loss_first_last": [hist[0], hist[-1]], "generate_s": t_gen, "train_s": t_train,
+    }
+
+
+def bench_warm(args, rank: int):
+    """The warm-start workload as its own line.  value = mean seconds per
+    held-out warm solve (inference incl.)."""
+    leg = warm_leg(args.train, args.test, args.epochs, args.workers)
+    out = {
+        "metric": "learned warm start, 7D N=24: seconds per held-out solve to rel. resid 1e-8 (warm incl. BF16 "
+                  "inference)",
+        "value": leg["warm_s_mean"], "unit": "s", "n_gpus": 1, "steps": args.test, "warmup": 0,
+        "ms_per_step": leg["warm_s_mean"] * 1e3, "higher_is_better": False, "scaling": "strong",
+        "vs_baseline": None, "dtype": "f64 solve, f32 train, bf16 infer", "data": "synthetic",
+        "config": {"workload": leg["workload"], "train": args.train, "test": args.test, "epochs": args.epochs},
+        **{k: v for k, v in leg.items() if k != "workload"},
         "roofline": None, "cpu_baseline": None,
     }
     if rank == 0:
@@ -276,7 +307,11 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sweeps", type=int, default=3)
+    ap.add_argument("--no-cpu-1thread", action="store_true", help="6d: skip the one-thread oracle run")
+    ap.add_argument("--no-warm", action="store_true", help="6d: skip the learned warm-start leg")
+    ap.add_argument("--warm-train", type=int, default=192, help="6d line's warm leg: training instances")
+    ap.add_argument("--warm-test", type=int, default=8, help="6d line's warm leg: held-out instances")
+    ap.add_argument("--warm-epochs", type=int, default=100, help="6d line's warm leg: epochs")
     ap.add_argument("--no-oracle-check", action="store_true")
     ap.add_argument("--no-overlap", action="store_true",
                     help="6d: every factorisation on the solve's stream (no side-stream eigendecompositions)")
@@ -384,6 +419,7 @@ def main():
                    "kick": SOLVE_OPTS["kick"], "init_rank": SOLVE_OPTS["init_rank"], "rank_cap": RANK_CAP},
         "sweeps_cold": last.sweeps,
         "sweeps_warm": None,
+        "warm_start": None,
         "final_ranks": last.ranks,
         "residual": last.residual,
         "phase_ms": last.phase_ms,
@@ -393,8 +429,16 @@ def main():
         "kernels": kernels,
         "check": check,
     }
+    if rank == 0 and not args.no_warm:
+        # the learned warm start is defined on its own family (7D N=24, the
+        # network's 20 inputs); sweeps warm vs cold are reported there
+        leg = warm_leg(args.warm_train, args.warm_test, args.warm_epochs, args.workers)
+        out["warm_start"] = leg
+        out["sweeps_warm"] = {"workload": leg["workload"], "cold": leg["sweeps_cold_mean"],
+                              "warm": leg["sweeps_warm_mean"], "time_cold_s": leg["cold_s_mean"],
+                              "time_warm_s": leg["warm_s_mean"]}
     if rank == 0 and not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, last, args.cpu_sweeps)
+        out["cpu_baseline"] = cpu_baseline(prob, one_thread=not args.no_cpu_1thread)
     else:
         out["cpu_baseline"] = None
     if rank == 0:
