@@ -191,7 +191,44 @@ int t2s2_matrices_1d(int N, double eps, double beta, int scheme,
  * EINVAL, ENOMEM or EHIP otherwise (*out untouched). */
 int t2s2_problem_create(int d, const int* N, double eps, const double* beta,
                         int scheme, int rank_cap, t2s2_problem** out);
+/* The same problem with a constant reaction term (paper: Eq. pblm:time:A,
+ * rho f):  -eps Lap u + beta . grad u + rho u = f.  Collocated, rho u is
+ * rho ((x)_l E_l) u = sum_l (x)_{k != l} E_k (x) (rho / d) E_l u, so the
+ * operator stays a rank-2 Kronecker sum with M_l = -eps D2_l + beta_l D1_l +
+ * (rho / d) E_l (and K_l = E_l^{-1} M_l shifted by rho / d).  rho finite;
+ * otherwise as t2s2_problem_create (rho = 0 gives the same problem). */
+int t2s2_problem_create_reaction(int d, const int* N, double eps, const double* beta, double rho, int scheme,
+                                 int rank_cap, t2s2_problem** out);
 int t2s2_problem_destroy(t2s2_problem* p);
+
+/* ------------------------------------------------------ method of lines ---
+ * Time stepping of du/dt - eps Lap u + beta . grad u + rho u = b with u = 0
+ * on the boundary (paper: Overview, the method-of-lines formulation; Eq.
+ * ttss-backward-Euler and Eq. ttss-Crank-Nicolson).  Both schemes are the
+ * theta-scheme (u^{k+1} - u^k)/dt + theta A u^{k+1} + (1 - theta) A u^k = b,
+ * theta = 1 backward Euler, theta = 1/2 Crank-Nicolson, A = -eps Lap +
+ * beta . grad + rho.  In collocation form
+ *   (E + theta dt (L + rho E)) u^{k+1} = (E - (1-theta) dt (L + rho E)) u^k + dt b
+ * (E = (x)_l E_l, L the interior collocation operator), i.e. per step the
+ * steady problem with reaction rho + 1/(theta dt) and right-hand side
+ *   f = (1/(theta dt)) E u^k - ((1-theta)/theta) (L + rho E) u^k + b / theta,
+ * solved by the alternating sweeps with the exact local solver (the identity
+ * only shifts K_l).
+ * t2s2_mol_create: such a problem (dt > 0, 0 < theta <= 1, rho finite; the
+ * rest as t2s2_problem_create); t2s2_solve on it solves the steady problem
+ * with reaction rho + 1/(theta dt).
+ * t2s2_mol_step: one step from u (interior values, mode sizes N_l - 2, ranks
+ * within the cap) to u_next (as x_out of t2s2_solve; it may alias u).  b:
+ * NULL or the step's source at the collocation nodes (theta b(t_{k+1}) +
+ * (1 - theta) b(t_k) for a time-dependent source).  f is formed as one
+ * rank-2 Kronecker-sum TT-matvec of u plus b (ranks 2 r + s), rounded at
+ * relative 1e-14; the solve starts from u.  Status and report as
+ * t2s2_solve (the residual is that of the step's system); EINVAL if p was
+ * not made by t2s2_mol_create. */
+int t2s2_mol_create(int d, const int* N, double eps, const double* beta, double rho, double dt, double theta,
+                    int scheme, int rank_cap, t2s2_problem** out);
+int t2s2_mol_step(t2s2_problem* p, const t2s2_tt* u, const t2s2_tt* b, const t2s2_options* opts,
+                  t2s2_tt* u_next, t2s2_report* rep, void* stream);
 
 /* Device pointers of the operator's TT-matrix cores (owned by p; valid until
  * destroy).  out->n and out->ranks point into p. */

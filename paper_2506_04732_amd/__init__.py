@@ -22,7 +22,8 @@ from ._lib import (PRECISION_FP64, PRECISION_MIXED, SCHEME_PLAIN, SCHEME_SC, T2S
                    T2S2_ENOTCONV, LibraryMissing,
                    T2S2Error, check, lib)
 
-__all__ = ["nodes", "matrices_1d", "TT", "Problem", "SolveResult", "solve_batched", "local_solve", "SCHEME_PLAIN",
+__all__ = ["nodes", "matrices_1d", "TT", "Problem", "MolProblem", "SolveResult", "solve_batched", "local_solve",
+           "SCHEME_PLAIN",
            "SCHEME_SC",
            "PRECISION_FP64", "PRECISION_MIXED",
            "LibraryMissing", "T2S2Error", "lib"]
@@ -175,17 +176,28 @@ class SolveResult:
 
 
 class Problem:
-    """-eps Lap u + beta . grad u = f on [-1,1]^d, u = g on the boundary (t2s2_problem_create)."""
+    """-eps Lap u + beta . grad u + rho u = f on [-1,1]^d, u = g on the boundary
+    (t2s2_problem_create, or t2s2_problem_create_reaction for rho != 0)."""
 
-    def __init__(self, d: int, N, eps: float, beta, scheme: int = SCHEME_SC, rank_cap: int = 64):
+    def __init__(self, d: int, N, eps: float, beta, scheme: int = SCHEME_SC, rank_cap: int = 64,
+                 rho: float = 0.0, _mol=None):
         Ns = [int(N)] * d if np.isscalar(N) else [int(v) for v in N]
         self.d, self.N, self.eps, self.scheme, self.rank_cap = d, Ns, float(eps), int(scheme), int(rank_cap)
         self.beta = np.asarray(beta, dtype=np.float64).copy()
+        self.rho = float(rho)
         self.m = [v - 2 for v in Ns]
         h = C.c_void_p()
         n_arr = (C.c_int * d)(*Ns)
         b_arr = self.beta.ctypes.data_as(C.POINTER(C.c_double))
-        check(lib().t2s2_problem_create(d, n_arr, self.eps, b_arr, self.scheme, self.rank_cap, C.byref(h)))
+        if _mol is not None:
+            dt, theta = _mol
+            check(lib().t2s2_mol_create(d, n_arr, self.eps, b_arr, self.rho, float(dt), float(theta), self.scheme,
+                                        self.rank_cap, C.byref(h)))
+        elif self.rho != 0.0:
+            check(lib().t2s2_problem_create_reaction(d, n_arr, self.eps, b_arr, self.rho, self.scheme,
+                                                     self.rank_cap, C.byref(h)))
+        else:
+            check(lib().t2s2_problem_create(d, n_arr, self.eps, b_arr, self.scheme, self.rank_cap, C.byref(h)))
         self._h = h
 
     def close(self):
@@ -269,6 +281,34 @@ class Problem:
         code = lib().t2s2_solve(self._h, C.byref(fs), C.byref(gs) if gs is not None else None,
                                 C.byref(x0s) if x0s is not None else None, C.byref(o),
                                 C.byref(xs), C.byref(rep), _stream())
+        check(code, allow=(T2S2_ENOTCONV,))
+        x._read_ranks()
+        return _result(x, code, rep, self.d)
+
+
+class MolProblem(Problem):
+    """Method of lines (t2s2_mol_create / t2s2_mol_step): theta-scheme steps of
+    du/dt - eps Lap u + beta . grad u + rho u = b, u = 0 on the boundary;
+    theta = 1 backward Euler, 1/2 Crank-Nicolson."""
+
+    def __init__(self, d: int, N, eps: float, beta, dt: float, theta: float = 0.5, rho: float = 0.0,
+                 scheme: int = SCHEME_SC, rank_cap: int = 64):
+        self.dt, self.theta = float(dt), float(theta)
+        super().__init__(d, N, eps, beta, scheme, rank_cap, rho=rho, _mol=(dt, theta))
+
+    def step(self, u: TT, b: Optional[TT] = None, *, tol: float = 1e-10, target: float = 1e-8,
+             max_sweeps: int = 40, kick: int = 8, rank_cap: Optional[int] = None, check_every: int = 1,
+             out: Optional[TT] = None, precision: int = PRECISION_FP64, overlap: bool = True) -> SolveResult:
+        """One step from u (interior values); b: the step's source at the collocation nodes."""
+        cap = int(rank_cap or self.rank_cap)
+        x = out if out is not None else TT.empty(self.m, cap)
+        o = _options(tol, target, max_sweeps, kick, cap, 1, 0, check_every, False, precision)
+        o.overlap = int(bool(overlap))
+        rep = _lib.Report()
+        us, xs = u._struct(), x._struct()
+        bs = b._struct() if b is not None else None
+        code = lib().t2s2_mol_step(self._h, C.byref(us), C.byref(bs) if bs is not None else None, C.byref(o),
+                                   C.byref(xs), C.byref(rep), _stream())
         check(code, allow=(T2S2_ENOTCONV,))
         x._read_ranks()
         return _result(x, code, rep, self.d)

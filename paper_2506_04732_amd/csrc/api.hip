@@ -75,15 +75,7 @@ t2s2::Ctx ctx_for(t2s2_problem* p, void* stream) {
   return c;
 }
 
-// One solve on stream s; throws on argument or runtime errors, returns
-// T2S2_OK or T2S2_ENOTCONV.
-int solve_one(t2s2_problem* p, const t2s2_tt* f, const t2s2_tt* g, const t2s2_tt* x0, const t2s2_options* opts,
-              t2s2_tt* x_out, t2s2_report* rep, hipStream_t stream) {
-  T2S2_CHECK(p && f && x_out, "NULL argument");
-  t2s2::DTT fd = to_dtt(f);
-  T2S2_CHECK(fd.d == p->P->d, "f has the wrong dimension");
-  for (int l = 0; l < fd.d; ++l) T2S2_CHECK(fd.n[l] == p->P->m[l], "f mode sizes must be N_l - 2");
-  T2S2_CHECK(x_out->d == fd.d && x_out->cores && x_out->ranks, "invalid x_out descriptor");
+t2s2::SolveOptions parse_options(const t2s2_options* opts) {
   t2s2::SolveOptions o;
   if (opts) {
     T2S2_CHECK(std::isfinite(opts->tol) && opts->tol > 0.0 && std::isfinite(opts->target), "bad tolerances");
@@ -103,63 +95,88 @@ int solve_one(t2s2_problem* p, const t2s2_tt* f, const t2s2_tt* g, const t2s2_tt
     o.warm_judge = opts->warm_judge;
     o.overlap = opts->overlap;
   }
-  t2s2::DTT xd;
-  xd.d = fd.d;
-  xd.n = fd.n;
-  xd.r.assign(fd.d + 1, 1);
-  xd.c.assign(x_out->cores, x_out->cores + fd.d);
+  return o;
+}
+
+// a TT of the problem's interior grid within the rank cap (checked before any device copy)
+t2s2::DTT interior_tt(t2s2_problem* p, const t2s2_tt* t, int cap, const char* what) {
+  t2s2::DTT x = to_dtt(t);
+  T2S2_CHECK(x.d == p->P->d, std::string(what) + " has the wrong dimension");
+  for (int l = 0; l < x.d; ++l) {
+    T2S2_CHECK(x.n[l] == p->P->m[l], std::string(what) + " mode sizes must be N_l - 2");
+    T2S2_CHECK(x.r[l + 1] <= cap, std::string(what) + " ranks exceed the rank cap");
+  }
+  return x;
+}
+
+void fill_report(t2s2_report* rep, const t2s2::SolveReport& r, int st, int d, int precision) {
+  if (!rep) return;
+  std::memset(rep, 0, sizeof(*rep));
+  rep->status = st == 0 ? T2S2_OK : T2S2_ENOTCONV;
+  rep->sweeps = r.sweeps;
+  rep->max_rank = r.max_rank;
+  for (int l = 0; l <= d && l <= T2S2_MAX_DIM; ++l) rep->ranks[l] = r.ranks[l];
+  rep->residual = r.residual;
+  rep->time_ms = r.time_ms;
+  const int h = std::min<int>((int)r.hist_res.size(), T2S2_MAX_HISTORY);
+  rep->history_len = h;
+  rep->precision = precision;
+  rep->local_systems = r.local_systems;
+  rep->refinement_steps = r.refinement_steps;
+  rep->fp64_fallbacks = r.fp64_fallbacks;
+  rep->warm_start_used = r.warm_start_used;
+  rep->warm_residual = r.warm_residual;
+  rep->cold_residual = r.cold_residual;
+  rep->refinement_capped = r.refinement_capped;
+  for (int i = 0; i < T2S2_PHASES; ++i) rep->phase_ms[i] = r.phase_ms[i];
+  for (int i = 0; i < h; ++i) {
+    rep->history_residual[i] = r.hist_res[i];
+    rep->history_local[i] = r.hist_local[i];
+    rep->history_max_rank[i] = r.hist_rank[i];
+    rep->history_time_ms[i] = r.hist_time[i];
+  }
+}
+
+// One solve on stream s; throws on argument or runtime errors, returns
+// T2S2_OK or T2S2_ENOTCONV.  mol_u: a time step from u (then g and x0 are NULL).
+int solve_one(t2s2_problem* p, const t2s2_tt* f, const t2s2_tt* g, const t2s2_tt* x0, const t2s2_options* opts,
+              t2s2_tt* x_out, t2s2_report* rep, hipStream_t stream, const t2s2_tt* mol_u = nullptr) {
+  T2S2_CHECK(p && x_out && (f || mol_u), "NULL argument");
+  const t2s2::SolveOptions o = parse_options(opts);
   const int cap = o.rank_cap > 0 ? std::min(o.rank_cap, p->P->rank_cap) : p->P->rank_cap;
-  t2s2::DTT x0d;
-  const t2s2::DTT* x0p = nullptr;
-  if (x0) {
-    // the start must be a TT of this problem's interior grid within the cap
-    // (checked before any device copy)
-    x0d = to_dtt(x0);
-    T2S2_CHECK(x0d.d == p->P->d, "x0 has the wrong dimension");
-    for (int l = 0; l < x0d.d; ++l) {
-      T2S2_CHECK(x0d.n[l] == p->P->m[l], "x0 mode sizes must be N_l - 2");
-      T2S2_CHECK(x0d.r[l + 1] <= cap, "x0 ranks exceed the rank cap");
-    }
-    x0p = &x0d;
-  }
+  t2s2::DTT fd;
+  if (f) fd = interior_tt(p, f, 1 << 30, "f");
+  T2S2_CHECK(x_out->d == p->P->d && x_out->cores && x_out->ranks, "invalid x_out descriptor");
+  t2s2::DTT xd;
+  xd.d = p->P->d;
+  xd.n = p->P->m;
+  xd.r.assign(xd.d + 1, 1);
+  xd.c.assign(x_out->cores, x_out->cores + xd.d);
   t2s2::Ctx c = ctx_for(p, stream);
-  if (g) {
-    t2s2::DTT gd = to_dtt(g);
-    T2S2_CHECK(gd.d == p->P->d, "g has the wrong dimension");
-    for (int l = 0; l < gd.d; ++l) T2S2_CHECK(gd.n[l] == p->P->N[l], "g mode sizes must be N_l (GLL grid)");
-    t2s2::DTT bd;
-    t2s2::lift_rhs(*p->P, c, fd, gd, bd, cap);
-    fd = bd;
-  }
   t2s2::SolveReport r;
-  const int st = t2s2::solve(*p->P, c, fd, x0p, o, xd, r);
-  for (int l = 0; l <= fd.d; ++l) x_out->ranks[l] = xd.r[l];
-  if (rep) {
-    std::memset(rep, 0, sizeof(*rep));
-    rep->status = st == 0 ? T2S2_OK : T2S2_ENOTCONV;
-    rep->sweeps = r.sweeps;
-    rep->max_rank = r.max_rank;
-    for (int l = 0; l <= fd.d && l <= T2S2_MAX_DIM; ++l) rep->ranks[l] = r.ranks[l];
-    rep->residual = r.residual;
-    rep->time_ms = r.time_ms;
-    const int h = std::min<int>((int)r.hist_res.size(), T2S2_MAX_HISTORY);
-    rep->history_len = h;
-    rep->precision = o.precision;
-    rep->local_systems = r.local_systems;
-    rep->refinement_steps = r.refinement_steps;
-    rep->fp64_fallbacks = r.fp64_fallbacks;
-    rep->warm_start_used = r.warm_start_used;
-    rep->warm_residual = r.warm_residual;
-    rep->cold_residual = r.cold_residual;
-    rep->refinement_capped = r.refinement_capped;
-    for (int i = 0; i < T2S2_PHASES; ++i) rep->phase_ms[i] = r.phase_ms[i];
-    for (int i = 0; i < h; ++i) {
-      rep->history_residual[i] = r.hist_res[i];
-      rep->history_local[i] = r.hist_local[i];
-      rep->history_max_rank[i] = r.hist_rank[i];
-      rep->history_time_ms[i] = r.hist_time[i];
+  int st;
+  if (mol_u) {
+    const t2s2::DTT ud = interior_tt(p, mol_u, cap, "u");
+    st = t2s2::mol_step(*p->P, c, ud, f ? &fd : nullptr, o, xd, r);
+  } else {
+    t2s2::DTT x0d;
+    const t2s2::DTT* x0p = nullptr;
+    if (x0) {
+      x0d = interior_tt(p, x0, cap, "x0");
+      x0p = &x0d;
     }
+    if (g) {
+      t2s2::DTT gd = to_dtt(g);
+      T2S2_CHECK(gd.d == p->P->d, "g has the wrong dimension");
+      for (int l = 0; l < gd.d; ++l) T2S2_CHECK(gd.n[l] == p->P->N[l], "g mode sizes must be N_l (GLL grid)");
+      t2s2::DTT bd;
+      t2s2::lift_rhs(*p->P, c, fd, gd, bd, cap);
+      fd = bd;
+    }
+    st = t2s2::solve(*p->P, c, fd, x0p, o, xd, r);
   }
+  for (int l = 0; l <= xd.d; ++l) x_out->ranks[l] = xd.r[l];
+  fill_report(rep, r, st, xd.d, o.precision);
   if (st != 0) t2s2::set_last_error("tolerance not met within max_sweeps");
   return st == 0 ? T2S2_OK : T2S2_ENOTCONV;
 }
@@ -197,19 +214,50 @@ int t2s2_matrices_1d(int N, double eps, double beta, int scheme, double* E, doub
   });
 }
 
+static t2s2_problem* wrap_problem(t2s2::Problem* P) {
+  t2s2_problem* h = new t2s2_problem();
+  h->P = P;
+  h->n = P->m;
+  h->R = P->opL.R;
+  h->cores = P->opL.c;
+  return h;
+}
+
 int t2s2_problem_create(int d, const int* N, double eps, const double* beta, int scheme, int rank_cap,
                         t2s2_problem** out) {
   return guarded([&] {
     T2S2_CHECK(out && N && beta, "NULL argument");
     T2S2_CHECK(d >= 1 && d <= T2S2_MAX_DIM, "d must be in [1, 16]");
-    t2s2::Problem* P = t2s2::problem_create(d, N, eps, beta, scheme, rank_cap);
-    t2s2_problem* h = new t2s2_problem();
-    h->P = P;
-    h->n = P->m;
-    h->R = P->opL.R;
-    h->cores = P->opL.c;
-    *out = h;
+    *out = wrap_problem(t2s2::problem_create(d, N, eps, beta, scheme, rank_cap));
     return T2S2_OK;
+  });
+}
+
+int t2s2_problem_create_reaction(int d, const int* N, double eps, const double* beta, double rho, int scheme,
+                                 int rank_cap, t2s2_problem** out) {
+  return guarded([&] {
+    T2S2_CHECK(out && N && beta, "NULL argument");
+    T2S2_CHECK(d >= 1 && d <= T2S2_MAX_DIM, "d must be in [1, 16]");
+    *out = wrap_problem(t2s2::problem_create(d, N, eps, beta, scheme, rank_cap, rho));
+    return T2S2_OK;
+  });
+}
+
+int t2s2_mol_create(int d, const int* N, double eps, const double* beta, double rho, double dt, double theta,
+                    int scheme, int rank_cap, t2s2_problem** out) {
+  return guarded([&] {
+    T2S2_CHECK(out && N && beta, "NULL argument");
+    T2S2_CHECK(d >= 1 && d <= T2S2_MAX_DIM, "d must be in [1, 16]");
+    *out = wrap_problem(t2s2::mol_create(d, N, eps, beta, rho, dt, theta, scheme, rank_cap));
+    return T2S2_OK;
+  });
+}
+
+int t2s2_mol_step(t2s2_problem* p, const t2s2_tt* u, const t2s2_tt* b, const t2s2_options* opts,
+                  t2s2_tt* u_next, t2s2_report* rep, void* stream) {
+  return guarded([&] {
+    T2S2_CHECK(u, "NULL argument");
+    return solve_one(p, b, nullptr, nullptr, opts, u_next, rep, static_cast<hipStream_t>(stream), u);
   });
 }
 

@@ -25,6 +25,12 @@ struct Problem {
   std::vector<int> N, m;        // nodes and interior unknowns per dimension
   double eps = 0.0;
   std::vector<double> beta;
+  double rho = 0.0;  // constant reaction of the operator solved (M_l carries rho / d E_l)
+  // method of lines (theta > 0): the solve operator is A + (1 / (theta dt)) I
+  // with A the operator of reaction rho_phys; dMx holds the explicit-part
+  // blocks (1/(theta dt d) - (1-theta)/theta rho_phys / d) E_l - (1-theta)/theta M0_l
+  double mol_dt = 0.0, mol_theta = 0.0, rho_phys = 0.0;
+  std::vector<double*> dMx;
   int scheme = 1;
   int rank_cap = 0;
   int device = 0;
@@ -84,7 +90,16 @@ struct SolveReport {
   double warm_residual = -1.0, cold_residual = -1.0;
 };
 
-Problem* problem_create(int d, const int* N, double eps, const double* beta, int scheme, int rank_cap);
+Problem* problem_create(int d, const int* N, double eps, const double* beta, int scheme, int rank_cap,
+                        double rho = 0.0);
+// A problem for theta-scheme time steps of du/dt + A u = b (A with reaction
+// rho): the operator solved per step has reaction rho + 1 / (theta dt).
+Problem* mol_create(int d, const int* N, double eps, const double* beta, double rho, double dt, double theta,
+                    int scheme, int rank_cap);
+// One step: f = (1/(theta dt)) E u - ((1-theta)/theta) (L + rho E) u + b / theta
+// (b nullable), rounded at relative 1e-14, then the solve from x0 = u.
+int mol_step(Problem& p, const Ctx& c, const DTT& u, const DTT* b, const SolveOptions& o, DTT& x,
+             SolveReport& rep);
 
 // y = A x, y's cores preallocated by the caller (ranks R r).
 void tt_matvec(const Ctx& c, const DTTM& A, const DTT& x, DTT& y);

@@ -42,6 +42,7 @@ Problem::~Problem() {
   for (auto p : dMf) fr(p);
   for (auto p : dEi) fr(p);
   for (auto p : dMi) fr(p);
+  for (auto p : dMx) fr(p);
   for (auto p : dK_ZT) fr(p);
   for (auto p : dK_T) fr(p);
   for (auto p : dK_ZT32) fr(p);
@@ -129,9 +130,11 @@ static void build_kron_sum(int d, const std::vector<int>& m, const std::vector<s
   }
 }
 
-Problem* problem_create(int d, const int* N, double eps, const double* beta, int scheme, int rank_cap) {
+Problem* problem_create(int d, const int* N, double eps, const double* beta, int scheme, int rank_cap,
+                        double rho) {
   T2S2_CHECK(d >= 1 && d <= 16, "d must be in [1, 16]");
   T2S2_CHECK(std::isfinite(eps) && eps > 0.0, "eps must be finite and > 0");
+  T2S2_CHECK(std::isfinite(rho), "rho must be finite");
   T2S2_CHECK(scheme == 0 || scheme == 1, "scheme must be 0 (plain) or 1 (superconsistent)");
   T2S2_CHECK(rank_cap >= 1 && rank_cap <= 1024, "rank_cap must be in [1, 1024]");
   for (int l = 0; l < d; ++l) {
@@ -142,6 +145,7 @@ Problem* problem_create(int d, const int* N, double eps, const double* beta, int
   try {
     P->d = d;
     P->eps = eps;
+    P->rho = rho;
     P->scheme = scheme;
     P->rank_cap = rank_cap;
     T2S2_HIP(hipGetDevice(&P->device));
@@ -157,7 +161,9 @@ Problem* problem_create(int d, const int* N, double eps, const double* beta, int
       std::vector<double> Ef((size_t)m * Nl), D1((size_t)m * Nl), D2((size_t)m * Nl);
       lagrange_eval(x.data(), Nl, th.data(), m, Ef.data(), D1.data(), D2.data());
       std::vector<double> E((size_t)m * m), M((size_t)m * m), Mf((size_t)m * Nl);
-      for (size_t e = 0; e < Mf.size(); ++e) Mf[e] = -eps * D2[e] + beta[l] * D1[e];
+      // reaction rho u at the collocation nodes is rho (x)E u = sum_l (x)_{k != l} E_k (x) (rho/d) E_l u
+      const double rd = rho / d;
+      for (size_t e = 0; e < Mf.size(); ++e) Mf[e] = -eps * D2[e] + beta[l] * D1[e] + rd * Ef[e];
       {
         double* ef = dev_alloc<double>(Ef.size());
         double* mf = dev_alloc<double>(Mf.size());
@@ -169,7 +175,7 @@ Problem* problem_create(int d, const int* N, double eps, const double* beta, int
       for (int j = 0; j < m; ++j)
         for (int i = 0; i < m; ++i) {
           E[(size_t)j * m + i] = Ef[(size_t)j * Nl + i + 1];
-          M[(size_t)j * m + i] = -eps * D2[(size_t)j * Nl + i + 1] + beta[l] * D1[(size_t)j * Nl + i + 1];
+          M[(size_t)j * m + i] = Mf[(size_t)j * Nl + i + 1];
         }
       {
         double* ei = dev_alloc<double>(E.size());
@@ -515,6 +521,36 @@ void lift_rhs(Problem& p, const Ctx& c, const DTT& f, const DTT& g, DTT& b, int 
   kron_sum_apply(c, p.m, p.m, 1, p.dEi, p.dMi, g, "lift.y2_", y2);   // L_int g_int
   tt_concat(c, {&f, &y1, &y2}, {1.0, -1.0, 1.0}, "lift.b", b);
   tt_round(c, b, 1e-14, std::max(1, rmax));
+}
+
+Problem* mol_create(int d, const int* N, double eps, const double* beta, double rho, double dt, double theta,
+                    int scheme, int rank_cap) {
+  T2S2_CHECK(std::isfinite(dt) && dt > 0.0, "dt must be finite and > 0");
+  T2S2_CHECK(std::isfinite(theta) && theta > 0.0 && theta <= 1.0, "theta must be in (0, 1]");
+  T2S2_CHECK(std::isfinite(rho), "rho must be finite");
+  const double cE = 1.0 / (theta * dt), cL = (1.0 - theta) / theta;
+  Problem* P = problem_create(d, N, eps, beta, scheme, rank_cap, rho + cE);
+  try {
+    P->mol_dt = dt;
+    P->mol_theta = theta;
+    P->rho_phys = rho;
+    for (int l = 0; l < d; ++l) {
+      const int m = P->m[l];
+      // M_l holds M0_l + (rho + cE)/d E_l; the explicit blocks are
+      // cE/d E_l - cL (M0_l + rho/d E_l) = (cE/d - cL rho/d) E_l - cL M0_l
+      //                                  = (cE/d + cL cE/d) E_l - cL M_l
+      std::vector<double> X((size_t)m * m);
+      const double a = (cE + cL * cE) / d;
+      for (size_t e = 0; e < X.size(); ++e) X[e] = a * P->E[l][e] - cL * P->M[l][e];
+      double* dx = dev_alloc<double>(X.size());
+      P->dMx.push_back(dx);
+      T2S2_HIP(hipMemcpy(dx, X.data(), X.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+  } catch (...) {
+    delete P;
+    throw;
+  }
+  return P;
 }
 
 // ================================================================ solver
@@ -1418,6 +1454,28 @@ void local_kron_solve(const Ctx& c0, int r1, int m, int r2, const double* Lint, 
   }
   c.sync();
   if (read_fail(c)) throw Error(5, "local_solve: Francis QR did not converge");
+}
+
+int mol_step(Problem& p, const Ctx& c, const DTT& u, const DTT* b, const SolveOptions& o, DTT& x,
+             SolveReport& rep) {
+  T2S2_CHECK(p.mol_theta > 0.0, "mol_step: the problem was not created for time stepping (t2s2_mol_create)");
+  T2S2_CHECK(u.d == p.d, "mol_step: u has the wrong dimension");
+  for (int l = 0; l < p.d; ++l) T2S2_CHECK(u.n[l] == p.m[l], "mol_step: u mode sizes must be N_l - 2");
+  DTT y;
+  kron_sum_apply(c, p.m, p.m, 0, p.dEi, p.dMx, u, "mol.y", y);
+  std::vector<const DTT*> parts{&y};
+  std::vector<double> coef{1.0};
+  if (b) {
+    T2S2_CHECK(b->d == p.d, "mol_step: b has the wrong dimension");
+    for (int l = 0; l < p.d; ++l) T2S2_CHECK(b->n[l] == p.m[l], "mol_step: b mode sizes must be N_l - 2");
+    parts.push_back(b);
+    coef.push_back(1.0 / p.mol_theta);
+  }
+  DTT f;
+  tt_concat(c, parts, coef, "mol.f", f);
+  const int cap = o.rank_cap > 0 ? std::min(o.rank_cap, p.rank_cap) : p.rank_cap;
+  tt_round(c, f, 1e-14, cap);
+  return solve(p, c, f, &u, o, x, rep);
 }
 
 int solve(Problem& p, const Ctx& c0, const DTT& f, const DTT* x0, const SolveOptions& o, DTT& x, SolveReport& rep) {
