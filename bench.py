@@ -301,6 +301,100 @@ def bench_warm(args, rank: int):
         print(json.dumps(out), flush=True)
 
 
+STAB_OPTS = dict(tol=1e-10, target=1e-8, max_sweeps=20, kick=4, init_rank=4, check_every=1, seed=0)
+
+
+def _transport_profile(x, eps, beta):
+    """Exact solution of beta phi' - eps phi'' = 1 on [-1, 1], phi(+-1) = 0, beta > 0
+    (written without overflow): (x + 1)/beta - (2/beta) (e^{a(x+1)} - 1)/(e^{2a} - 1), a = beta/eps."""
+    import numpy as np
+    a = beta / eps
+    frac = np.exp(a * (x - 1.0)) * (-np.expm1(-a * (x + 1.0))) / (-np.expm1(-2.0 * a))
+    return (x + 1.0) / beta - (2.0 / beta) * frac
+
+
+def _sign_changes(v, rel_floor=1e-12):
+    import numpy as np
+    dv = np.diff(v)
+    dv = dv[np.abs(dv) > rel_floor * np.max(np.abs(v))]
+    s = np.sign(dv)
+    return int(np.count_nonzero(s[1:] != s[:-1])) if s.size >= 2 else 0
+
+
+def stability_map(d=6, Ns=(8, 12, 16, 24, 32), ratios=(1e-1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6), workers=16,
+                  cap=64, log=True):
+    """Plain collocation vs superconsistent collocation on the transport-
+    dominated problem with the separable exact solution u = prod_l phi_l(x_l)
+    (f = sum_l prod_{k != l} phi_k): for every (N, eps / |beta L|) both
+    schemes are solved (batched) and the sign changes of the nodal differences
+    along the line through the grid centre in direction 1 are counted on the
+    GPU's fiber (the exact profile has one)."""
+    import numpy as np
+    import paper_2506_04732_amd as t2s2
+    from paper_2506_04732_amd import TT
+    beta = np.full(d, 1.0 / np.sqrt(d))
+    cases, probs, fs = [], [], []
+    for N in Ns:
+        for ratio in ratios:
+            eps = 2.0 * ratio          # |beta| = 1, L = 2
+            for scheme in (t2s2.SCHEME_SC, t2s2.SCHEME_PLAIN):
+                p = t2s2.Problem(d, N, eps, beta, scheme, rank_cap=cap)
+                th = [p.colloc(l) for l in range(d)]
+                phis = [_transport_profile(th[l], eps, beta[l]) for l in range(d)]
+                terms = [[np.ones(N - 2) if k == l else phis[k] for k in range(d)] for l in range(d)]
+                cores = []
+                for l in range(d):
+                    r0, r1 = (1 if l == 0 else d), (1 if l == d - 1 else d)
+                    c = np.zeros((r0, N - 2, r1))
+                    for t in range(d):
+                        c[0 if l == 0 else t, :, 0 if l == d - 1 else t] = terms[t][l]
+                    cores.append(c)
+                cases.append((N, ratio, scheme))
+                probs.append(p)
+                fs.append(TT.from_numpy(cores))
+    t0 = time.perf_counter()
+    res = []
+    for k in range(0, len(probs), 32):
+        res += t2s2.solve_batched(probs[k:k + 32], fs[k:k + 32], workers=workers, **STAB_OPTS)
+        if log:
+            print(f"stability: solved {len(res)} / {len(probs)} in {time.perf_counter() - t0:.0f} s",
+                  file=sys.stderr, flush=True)
+    t_solve = time.perf_counter() - t0
+    rows = []
+    for (N, ratio, scheme), p, r in zip(cases, probs, res):
+        eps = 2.0 * ratio
+        mid = N // 2 - 1                                   # interior index of GLL node N // 2
+        fib = p.tt_fiber(r.x, 0, [mid] * d)
+        prof = np.concatenate([[0.0], fib, [0.0]])         # boundary values g = 0
+        x = t2s2.nodes(N, eps, beta[0], scheme)[0]
+        xc = x[N // 2]
+        exact = _transport_profile(x, eps, beta[0]) * np.prod(
+            [_transport_profile(np.array([xc]), eps, beta[k])[0] for k in range(1, d)])
+        exact[0] = exact[-1] = 0.0
+        rows.append({"N": N, "eps_over_beta_L": ratio, "scheme": "SC" if scheme == t2s2.SCHEME_SC else "plain",
+                     "sign_changes": _sign_changes(prof), "exact_sign_changes": _sign_changes(exact),
+                     "line_max_err": float(np.max(np.abs(prof - exact)) / np.max(np.abs(exact))),
+                     "converged": bool(r.converged), "residual": r.residual, "max_rank": max(r.ranks),
+                     "sweeps": r.sweeps})
+    return {"d": d, "beta": "ones / sqrt(d)", "rows": rows, "solve_s": t_solve}
+
+
+def bench_stability(args, rank: int):
+    m = stability_map(workers=args.workers)
+    sc = [r for r in m["rows"] if r["scheme"] == "SC"]
+    pl = [r for r in m["rows"] if r["scheme"] == "plain"]
+    out = {"metric": "stability map, 6D: oscillation counts of plain vs superconsistent collocation",
+           "value": m["solve_s"], "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0,
+           "ms_per_step": m["solve_s"] * 1e3, "higher_is_better": False, "scaling": "strong",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "stability6d_transport_closed_form", **STAB_OPTS},
+           "sc_oscillatory": sum(r["sign_changes"] > r["exact_sign_changes"] for r in sc),
+           "plain_oscillatory": sum(r["sign_changes"] > r["exact_sign_changes"] for r in pl),
+           "cases_per_scheme": len(sc), "map": m["rows"], "roofline": None, "cpu_baseline": None}
+    if rank == 0:
+        print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -315,7 +409,7 @@ def main():
     ap.add_argument("--no-oracle-check", action="store_true")
     ap.add_argument("--no-overlap", action="store_true",
                     help="6d: every factorisation on the solve's stream (no side-stream eigendecompositions)")
-    ap.add_argument("--workload", choices=["6d", "batched256", "warm7d"], default="6d",
+    ap.add_argument("--workload", choices=["6d", "batched256", "warm7d", "stability"], default="6d",
                     help="6d: the 6D N=32 solve (default); batched256: 256 uneven instances solved concurrently; "
                          "warm7d: learned warm start on 7D N=24 (train on solver solutions, held-out cold vs warm)")
     ap.add_argument("--train", type=int, default=1024, help="warm7d: training instances")
@@ -346,6 +440,8 @@ def main():
         return bench_batched(args, rank)
     if args.workload == "warm7d":
         return bench_warm(args, rank)
+    if args.workload == "stability":
+        return bench_stability(args, rank)
 
     import torch
     import paper_2506_04732_amd as t2s2

@@ -258,6 +258,14 @@ int t2s2_tt_matvec(const t2s2_ttm* A, const t2s2_tt* x, t2s2_tt* y, void* stream
  * stream. */
 int t2s2_tt_matvec_noalloc(const t2s2_ttm* A, const t2s2_tt* x, t2s2_tt* y, void* stream);
 
+/* One fiber of a TT (paper: Fig. 2, an entry is the product of one slice
+ * per core): out[i] = x(idx_0, .., idx_{l-1}, i, idx_{l+1}, .., idx_{d-1})
+ * for i < n_l, the quantity behind the oscillation count along a line
+ * through the grid (Results: Superconsistent Stabilization).  idx: host
+ * array of d indices (idx[l] is ignored); out: device array of n_l doubles.
+ * Uses p's scratch; asynchronous on stream.  EINVAL for a bad mode or index. */
+int t2s2_tt_fiber(t2s2_problem* p, const t2s2_tt* x, int l, const int* idx, double* out, void* stream);
+
 /* ||x||_2 (Frobenius) by the Gram recursion G_l = sum_i X_l(i)^T G_{l-1}
  * X_l(i) carried in double-double arithmetic (error-free products and
  * two-sum accumulation), so ||x||^2 is resolved to ~1e-16 of itself; uses

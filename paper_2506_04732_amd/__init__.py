@@ -242,6 +242,15 @@ class Problem:
         op = self.operator()
         return ttm_matvec(op, x, out=out, noalloc=True)
 
+    def tt_fiber(self, x: TT, l: int, idx) -> np.ndarray:
+        """t2s2_tt_fiber: x along mode l through the indices idx (idx[l] ignored)."""
+        torch = _torch()
+        out = torch.empty(x.n[l], dtype=torch.float64, device="cuda")
+        arr = (C.c_int * x.d)(*[int(v) for v in idx])
+        xs = x._struct()
+        check(lib().t2s2_tt_fiber(self._h, C.byref(xs), int(l), arr, C.c_void_p(out.data_ptr()), _stream()))
+        return out.cpu().numpy()
+
     def tt_norm(self, x: TT) -> float:
         out = C.c_double()
         xs = x._struct()

@@ -22,7 +22,7 @@ EXPORTED = [
     "t2s2_mlp_forward", "t2s2_mlp_backward", "t2s2_mlp_adam_step", "t2s2_mlp_infer_bf16", "t2s2_mlp_train",
     "t2s2_tt_fit_loss", "t2s2_tt_pack", "t2s2_tt_unpack", "t2s2_source_gaussians", "t2s2_source_manufactured",
     "t2s2_debug_iteration_limits", "t2s2_tt_matvec_noalloc", "t2s2_problem_create_reaction",
-    "t2s2_mol_create", "t2s2_mol_step",
+    "t2s2_mol_create", "t2s2_mol_step", "t2s2_tt_fiber",
 ]
 TIMING_CLASSES = ["gemm_f64", "gemm_c128", "ttm_matvec", "schur_qr", "hessenberg", "jacobi_svd", "cholesky",
                   "trtri", "trevec", "kron_trisolve", "hess_solve", "other"]
@@ -93,6 +93,7 @@ def lib() -> C.CDLL:
     L.t2s2_tt_matvec.argtypes = [C.POINTER(TTMStruct), C.POINTER(TTStruct), C.POINTER(TTStruct), vp]
     L.t2s2_tt_matvec_noalloc.argtypes = [C.POINTER(TTMStruct), C.POINTER(TTStruct), C.POINTER(TTStruct), vp]
     L.t2s2_tt_norm.argtypes = [vp, C.POINTER(TTStruct), dp, vp]
+    L.t2s2_tt_fiber.argtypes = [vp, C.POINTER(TTStruct), C.c_int, ip, vp, vp]
     L.t2s2_tt_residual_norm.argtypes = [vp, C.POINTER(TTStruct), C.POINTER(TTStruct), dp, vp]
     L.t2s2_tt_round.argtypes = [vp, C.POINTER(TTStruct), C.c_double, C.c_int, vp]
     L.t2s2_local_solve.argtypes = [C.c_int, C.c_int, C.c_int, vp, vp, vp, vp, vp, C.c_int, vp]

@@ -324,6 +324,18 @@ int t2s2_tt_matvec_noalloc(const t2s2_ttm* A, const t2s2_tt* x, t2s2_tt* y, void
   return guarded([&] { return tt_matvec_common(A, x, y, stream, true); });
 }
 
+int t2s2_tt_fiber(t2s2_problem* p, const t2s2_tt* x, int l, const int* idx, double* out, void* stream) {
+  return guarded([&] {
+    T2S2_CHECK(p && idx && out, "NULL argument");
+    const t2s2::DTT xd = to_dtt(x);
+    T2S2_CHECK(l >= 0 && l < xd.d, "mode index out of range");
+    std::vector<int> iv(idx, idx + xd.d);
+    t2s2::Ctx c = ctx_for(p, stream);
+    t2s2::tt_fiber(c, xd, l, iv, out);
+    return T2S2_OK;
+  });
+}
+
 int t2s2_tt_norm(t2s2_problem* p, const t2s2_tt* x, double* out, void* stream) {
   return guarded([&] {
     T2S2_CHECK(p && out, "NULL argument");

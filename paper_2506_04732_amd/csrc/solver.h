@@ -108,6 +108,8 @@ void tt_matvec(const Ctx& c, const DTTM& A, const DTT& x, DTT& y);
 // n_l <= 64).  Calls that overlap on one GPU share the array and race.
 void tt_matvec_noalloc(const Ctx& c, const DTTM& A, const DTT& x, DTT& y);
 long tt_matvec_noalloc_capacity();
+// out (device, n_l doubles) = the fiber of x along mode l through idx.
+void tt_fiber(const Ctx& c, const DTT& x, int l, const std::vector<int>& idx, double* out);
 // ||x||_2 (double-double Gram recursion).
 double tt_norm(const Ctx& c, const DTT& x);
 // ||f - L x|| / ||f|| with the problem's original operator.

@@ -553,6 +553,42 @@ Problem* mol_create(int d, const int* N, double eps, const double* beta, double 
   return P;
 }
 
+// out[i] = x(idx_0, .., idx_{l-1}, i, idx_{l+1}, ..) for i < n_l: the row
+// vector of the slices left of l, the column vector of those right of l
+// (chains of slice products), then v X_l(:, i, :) w for every i
+void tt_fiber(const Ctx& c, const DTT& x, int l, const std::vector<int>& idx, double* out) {
+  const int d = x.d;
+  T2S2_CHECK(l >= 0 && l < d && (int)idx.size() == d, "tt_fiber: bad mode or index count");
+  for (int k = 0; k < d; ++k) T2S2_CHECK(k == l || (idx[k] >= 0 && idx[k] < x.n[k]), "tt_fiber: index out of range");
+  int rmax = 1;
+  for (int k = 0; k <= d; ++k) rmax = std::max(rmax, x.r[k]);
+  double* v = c.sc->get<double>("fib.v", (size_t)rmax);
+  double* v2 = c.sc->get<double>("fib.v2", (size_t)rmax);
+  double* w = c.sc->get<double>("fib.w", (size_t)rmax);
+  double* w2 = c.sc->get<double>("fib.w2", (size_t)rmax);
+  double* Z = c.sc->get<double>("fib.Z", (size_t)rmax * x.n[l]);
+  const double one = 1.0;
+  c.h2d(v, &one, 1);
+  c.h2d(w, &one, 1);
+  for (int k = 0; k < l; ++k) {
+    // v (1 x r_k) <- v X_k(:, idx_k, :): rows a of the slice at stride n_k r_{k+1}
+    const int r0 = x.r[k], n = x.n[k], r1 = x.r[k + 1];
+    gemm<double>(c.s, OpN, OpN, 1, r1, r0, 1.0, v, r0, 0, x.c[k] + (long)idx[k] * r1, (long)n * r1, 0, 0.0, v2, r1,
+                 0, 1);
+    std::swap(v, v2);
+  }
+  for (int k = d - 1; k > l; --k) {
+    // w (r_{k+1}) <- X_k(:, idx_k, :) w
+    const int r0 = x.r[k], n = x.n[k], r1 = x.r[k + 1];
+    gemm<double>(c.s, OpN, OpN, r0, 1, r1, 1.0, x.c[k] + (long)idx[k] * r1, (long)n * r1, 0, w, 1, 0, 0.0, w2, 1,
+                 0, 1);
+    std::swap(w, w2);
+  }
+  const int r0 = x.r[l], n = x.n[l], r1 = x.r[l + 1];
+  gemm<double>(c.s, OpN, OpN, r0 * n, 1, r1, 1.0, x.c[l], r1, 0, w, 1, 0, 0.0, Z, 1, 0, 1);   // Z[a][i]
+  gemm<double>(c.s, OpN, OpN, 1, n, r0, 1.0, v, r0, 0, Z, n, 0, 0.0, out, n, 0, 1);
+}
+
 // ================================================================ solver
 namespace {
 
