@@ -201,6 +201,41 @@ int t2s2_problem_create_reaction(int d, const int* N, double eps, const double* 
                                  int rank_cap, t2s2_problem** out);
 int t2s2_problem_destroy(t2s2_problem* p);
 
+/* General problem (paper: Eq. pblm:time:A-C and the unified space-time
+ * formulation of the Overview): per dimension a kind
+ *   T2S2_DIM_SPACE (0): x_l in [-1, 1], Dirichlet data at both ends (u = g),
+ *       N_l - 2 unknowns at the interior GLL nodes, rows at the n_l - 1
+ *       superconsistent (or plain) collocation nodes;
+ *   T2S2_DIM_TIME (1): t in [0, T], the value at t = 0 given (initial
+ *       condition, Eq. pblm:time:C), N_l - 1 unknowns at the GLL nodes
+ *       t_1 .. t_n, rows at the n_l Gauss points (zeros of P_n; the
+ *       superconsistent limit for a first-order operator: the paper applies
+ *       superconsistency to the spatial dimensions only); operator
+ *       (2 / T) d/ds of the reference coordinate s;
+ * and a variable separable advection beta_l(x_l) = sum_k c_{l,k} P_k(x_l)
+ * (Legendre series, nbeta[l] >= 1 coefficients per space dimension,
+ * concatenated over the space dimensions in beta_coef; nbeta is ignored for
+ * time dimensions), evaluated at the collocation nodes.  The node set of a
+ * space dimension follows one advection value: the largest |beta_l| over the
+ * GLL nodes, with its sign, or positive when beta_l changes sign there
+ * (the paper's variable-coefficient cases take positive directions).
+ * Operator: sum_l (x)_{k != l} E_k (x) M_l, M_l = -eps D2_l + diag(beta_l(theta))
+ * D1_l + (rho / d) E_l (space), (2/T) D1_l + (rho / d) E_l (time): still a
+ * rank-2 Kronecker sum, so t2s2_solve applies unchanged.  The initial
+ * condition (and spatial Dirichlet data) enter through t2s2_solve's g: a TT
+ * on the full grid (N_l values per dimension) whose values at t = 0 and on
+ * the spatial boundary are used, e.g. u0(x) (x) (1, .., 1)(t) for u0
+ * vanishing on the spatial boundary.  f and the solution live on the
+ * unknown grid (N_l - 2 per space, N_l - 1 per time dimension);
+ * t2s2_problem_colloc returns physical times for time dimensions.
+ * EINVAL: bad kinds or sizes, T <= 0 with a time dimension, non-finite
+ * coefficients. */
+#define T2S2_DIM_SPACE 0
+#define T2S2_DIM_TIME 1
+int t2s2_problem_create_general(int d, const int* N, const int* kind, double eps, const double* beta_coef,
+                                const int* nbeta, double rho, double T, int scheme, int rank_cap,
+                                t2s2_problem** out);
+
 /* ------------------------------------------------------ method of lines ---
  * Time stepping of du/dt - eps Lap u + beta . grad u + rho u = b with u = 0
  * on the boundary (paper: Overview, the method-of-lines formulation; Eq.

@@ -22,7 +22,8 @@ from ._lib import (PRECISION_FP64, PRECISION_MIXED, SCHEME_PLAIN, SCHEME_SC, T2S
                    T2S2_ENOTCONV, LibraryMissing,
                    T2S2Error, check, lib)
 
-__all__ = ["nodes", "matrices_1d", "TT", "Problem", "MolProblem", "SolveResult", "solve_batched", "local_solve",
+__all__ = ["nodes", "matrices_1d", "TT", "Problem", "MolProblem", "SpaceTimeProblem", "SolveResult", "solve_batched",
+           "local_solve",
            "SCHEME_PLAIN",
            "SCHEME_SC",
            "PRECISION_FP64", "PRECISION_MIXED",
@@ -293,6 +294,36 @@ class Problem:
         check(code, allow=(T2S2_ENOTCONV,))
         x._read_ranks()
         return _result(x, code, rep, self.d)
+
+
+class SpaceTimeProblem(Problem):
+    """t2s2_problem_create_general: space dimensions x_l in [-1, 1] with variable
+    separable advection beta_l(x_l) = sum_k coef[l][k] P_k(x_l) (Legendre
+    series) and optionally the time dimension t in [0, T] (kind 1, the value
+    at t = 0 given).  N, kinds: per dimension; beta_coefs: one coefficient
+    list per space dimension, in order."""
+
+    def __init__(self, N: Sequence[int], kinds: Sequence[int], eps: float, beta_coefs, T: float = 0.0,
+                 rho: float = 0.0, scheme: int = SCHEME_SC, rank_cap: int = 64):
+        d = len(N)
+        self.d, self.N, self.eps, self.scheme, self.rank_cap = d, [int(v) for v in N], float(eps), int(scheme), \
+            int(rank_cap)
+        self.kinds, self.T, self.rho = [int(k) for k in kinds], float(T), float(rho)
+        self.m = [n - 1 if k == 1 else n - 2 for n, k in zip(self.N, self.kinds)]
+        coefs = [np.asarray(c, dtype=np.float64).ravel() for c in beta_coefs]
+        nb = []
+        it = iter(coefs)
+        for k in self.kinds:
+            nb.append(len(next(it)) if k == 0 else 0)
+        flat = np.concatenate(coefs) if coefs else np.zeros(1)
+        self.beta = None
+        h = C.c_void_p()
+        n_arr = (C.c_int * d)(*self.N)
+        k_arr = (C.c_int * d)(*self.kinds)
+        nb_arr = (C.c_int * d)(*nb)
+        check(lib().t2s2_problem_create_general(d, n_arr, k_arr, self.eps, flat.ctypes.data_as(C.POINTER(C.c_double)),
+                                                nb_arr, self.rho, self.T, self.scheme, self.rank_cap, C.byref(h)))
+        self._h = h
 
 
 class MolProblem(Problem):

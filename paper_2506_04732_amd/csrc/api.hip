@@ -243,6 +243,17 @@ int t2s2_problem_create_reaction(int d, const int* N, double eps, const double* 
   });
 }
 
+int t2s2_problem_create_general(int d, const int* N, const int* kind, double eps, const double* beta_coef,
+                                const int* nbeta, double rho, double T, int scheme, int rank_cap,
+                                t2s2_problem** out) {
+  return guarded([&] {
+    T2S2_CHECK(out && N && kind && beta_coef && nbeta, "NULL argument");
+    T2S2_CHECK(d >= 1 && d <= T2S2_MAX_DIM, "d must be in [1, 16]");
+    *out = wrap_problem(t2s2::problem_create_general(d, N, kind, eps, beta_coef, nbeta, rho, T, scheme, rank_cap));
+    return T2S2_OK;
+  });
+}
+
 int t2s2_mol_create(int d, const int* N, double eps, const double* beta, double rho, double dt, double theta,
                     int scheme, int rank_cap, t2s2_problem** out) {
   return guarded([&] {

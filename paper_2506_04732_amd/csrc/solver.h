@@ -26,6 +26,8 @@ struct Problem {
   double eps = 0.0;
   std::vector<double> beta;
   double rho = 0.0;  // constant reaction of the operator solved (M_l carries rho / d E_l)
+  std::vector<int> kind;  // per dimension: 0 space (Dirichlet at both ends), 1 time (initial value)
+  double T = 0.0;         // final time of a time dimension (on [0, T])
   // method of lines (theta > 0): the solve operator is A + (1 / (theta dt)) I
   // with A the operator of reaction rho_phys; dMx holds the explicit-part
   // blocks (1/(theta dt d) - (1-theta)/theta rho_phys / d) E_l - (1-theta)/theta M0_l
@@ -92,6 +94,14 @@ struct SolveReport {
 
 Problem* problem_create(int d, const int* N, double eps, const double* beta, int scheme, int rank_cap,
                         double rho = 0.0);
+// General problem: per dimension a kind (0 space: Dirichlet data at both
+// ends, N_l - 2 unknowns, superconsistent or plain collocation nodes; 1 time
+// on [0, T]: the value at t = 0 given, N_l - 1 unknowns collocated at the
+// Gauss points), a variable separable advection beta_l(x_l) = sum_k
+// c_{l,k} P_k(x_l) (nbeta[l] Legendre coefficients per space dimension,
+// concatenated in beta_coef), constant eps and reaction rho.
+Problem* problem_create_general(int d, const int* N, const int* kind, double eps, const double* beta_coef,
+                                const int* nbeta, double rho, double T, int scheme, int rank_cap);
 // A problem for theta-scheme time steps of du/dt + A u = b (A with reaction
 // rho): the operator solved per step has reaction rho + 1 / (theta dt).
 Problem* mol_create(int d, const int* N, double eps, const double* beta, double rho, double dt, double theta,

@@ -130,17 +130,42 @@ static void build_kron_sum(int d, const std::vector<int>& m, const std::vector<s
   }
 }
 
+// sum_k c[k] P_k(x), Legendre series by the three-term recurrence
+static double legendre_series(const double* c, int nc, double x) {
+  double p0 = 1.0, p1 = x, s = c[0];
+  if (nc > 1) s += c[1] * x;
+  for (int k = 1; k + 1 < nc; ++k) {
+    const double p2 = ((2.0 * k + 1.0) * x * p1 - k * p0) / (k + 1.0);
+    s += c[k + 1] * p2;
+    p0 = p1;
+    p1 = p2;
+  }
+  return s;
+}
+
 Problem* problem_create(int d, const int* N, double eps, const double* beta, int scheme, int rank_cap,
                         double rho) {
+  T2S2_CHECK(d >= 1 && d <= 16, "d must be in [1, 16]");
+  for (int l = 0; l < d; ++l) T2S2_CHECK(std::isfinite(beta[l]), "beta must be finite");
+  const std::vector<int> kind(d, 0), nb(d, 1);
+  return problem_create_general(d, N, kind.data(), eps, beta, nb.data(), rho, 0.0, scheme, rank_cap);
+}
+
+Problem* problem_create_general(int d, const int* N, const int* kind, double eps, const double* beta_coef,
+                                const int* nbeta, double rho, double T, int scheme, int rank_cap) {
   T2S2_CHECK(d >= 1 && d <= 16, "d must be in [1, 16]");
   T2S2_CHECK(std::isfinite(eps) && eps > 0.0, "eps must be finite and > 0");
   T2S2_CHECK(std::isfinite(rho), "rho must be finite");
   T2S2_CHECK(scheme == 0 || scheme == 1, "scheme must be 0 (plain) or 1 (superconsistent)");
   T2S2_CHECK(rank_cap >= 1 && rank_cap <= 1024, "rank_cap must be in [1, 1024]");
+  bool has_time = false;
   for (int l = 0; l < d; ++l) {
+    T2S2_CHECK(kind[l] == 0 || kind[l] == 1, "dimension kind must be 0 (space) or 1 (time)");
     T2S2_CHECK(N[l] >= 3 && N[l] <= 66, "N must be in [3, 66]");
-    T2S2_CHECK(std::isfinite(beta[l]), "beta must be finite");
+    if (kind[l] == 1) has_time = true;
+    else T2S2_CHECK(nbeta[l] >= 1 && nbeta[l] <= 66, "each space dimension needs 1 .. 66 beta coefficients");
   }
+  T2S2_CHECK(!has_time || (std::isfinite(T) && T > 0.0), "a time dimension needs a final time T > 0");
   Problem* P = new Problem();
   try {
     P->d = d;
@@ -148,22 +173,59 @@ Problem* problem_create(int d, const int* N, double eps, const double* beta, int
     P->rho = rho;
     P->scheme = scheme;
     P->rank_cap = rank_cap;
+    P->T = has_time ? T : 0.0;
     T2S2_HIP(hipGetDevice(&P->device));
     P->N.assign(N, N + d);
-    P->beta.assign(beta, beta + d);
+    P->kind.assign(kind, kind + d);
+    P->beta.assign(d, 0.0);
     P->m.resize(d);
     std::vector<std::vector<double>> Ieye(d);
+    long coff = 0;
     for (int l = 0; l < d; ++l) {
-      const int n = N[l] - 1, Nl = N[l], m = N[l] - 2;
+      const int n = N[l] - 1, Nl = N[l];
+      const bool time = kind[l] == 1;
+      // space: Dirichlet data at both ends, N - 2 unknowns, n - 1 collocation
+      // nodes; time (on [0, T]): the value at t = 0 is given, N - 1 unknowns,
+      // collocated at the n Gauss points (zeros of P_n)
+      const int m = time ? N[l] - 1 : N[l] - 2;
       P->m[l] = m;
       std::vector<double> x = gll_nodes(n);
-      std::vector<double> th = colloc_nodes(n, eps, beta[l], scheme);
+      std::vector<double> th;
+      std::vector<double> bth(m, 0.0);
+      if (time) {
+        th = gauss_zeros(n);
+      } else {
+        const double* c = beta_coef + coff;
+        coff += nbeta[l];
+        for (int k = 0; k < nbeta[l]; ++k) T2S2_CHECK(std::isfinite(c[k]), "beta coefficients must be finite");
+        // the node set follows one advection value per dimension: the value
+        // of largest magnitude over the GLL nodes, taken positive when beta
+        // changes sign there (constant beta: beta itself)
+        double bmax = 0.0, bmin = 0.0, bbig = 0.0;
+        for (int i = 0; i < Nl; ++i) {
+          const double v = legendre_series(c, nbeta[l], x[i]);
+          bmax = std::max(bmax, v);
+          bmin = std::min(bmin, v);
+          if (std::fabs(v) > std::fabs(bbig)) bbig = v;
+        }
+        const double bnode = (bmax > 0.0 && bmin < 0.0) ? std::max(bmax, -bmin) : bbig;
+        P->beta[l] = bnode;
+        th = colloc_nodes(n, eps, bnode, scheme);
+        for (int j = 0; j < m; ++j) bth[j] = legendre_series(c, nbeta[l], th[j]);
+      }
       std::vector<double> Ef((size_t)m * Nl), D1((size_t)m * Nl), D2((size_t)m * Nl);
       lagrange_eval(x.data(), Nl, th.data(), m, Ef.data(), D1.data(), D2.data());
       std::vector<double> E((size_t)m * m), M((size_t)m * m), Mf((size_t)m * Nl);
-      // reaction rho u at the collocation nodes is rho (x)E u = sum_l (x)_{k != l} E_k (x) (rho/d) E_l u
+      // reaction rho u at the collocation nodes is rho (x)E u = sum_l (x)_{k != l} E_k (x) (rho/d) E_l u;
+      // time: d/dt = (2 / T) d/ds on [0, T]
       const double rd = rho / d;
-      for (size_t e = 0; e < Mf.size(); ++e) Mf[e] = -eps * D2[e] + beta[l] * D1[e] + rd * Ef[e];
+      for (int j = 0; j < m; ++j)
+        for (int i = 0; i < Nl; ++i) {
+          const size_t e = (size_t)j * Nl + i;
+          Mf[e] = (time ? (2.0 / T) * D1[e] : -eps * D2[e] + bth[j] * D1[e]) + rd * Ef[e];
+        }
+      if (time)
+        for (auto& t : th) t = 0.5 * T * (t + 1.0);  // reported in physical time
       {
         double* ef = dev_alloc<double>(Ef.size());
         double* mf = dev_alloc<double>(Mf.size());
