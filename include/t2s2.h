@@ -361,6 +361,28 @@ int t2s2_local_solve(int r1, int m, int r2, const double* Lint, const double* K,
 int t2s2_source_gaussians(t2s2_problem* p, int s, const double* amp,
                           const double* centre, const double* width,
                           t2s2_tt* f_out, void* stream);
+/* A non-separable source on the collocation grid by TT-cross approximation
+ * (paper: Methods, the closing paragraph on cross approximation: a TT from
+ * a few sampled entries, rows and columns chosen by MaxVol; Oseledets &
+ * Tyrtyshnikov and Goreinov et al. are cited there).  Built-in functions of
+ * x in R^d, params = {amp, aux, w_0..w_{d-1}, c_0..c_{d-1}} (host, 2 + 2d):
+ *   kind 0: amp / (1 + sum_l w_l (x_l - c_l)^2)
+ *   kind 1: amp exp(-sqrt(aux + sum_l w_l (x_l - c_l)^2)), aux >= 0
+ *   kind 2: amp sin(aux + sum_l w_l x_l)      (exact TT rank 2)
+ * Alternating cross with nested index sets: two pairs of half sweeps at
+ * ranks r0, 2 r0, ... <= rmax (<= 128); at each core the fiber tensor
+ * f(I_{l-1}, i, J_l) is evaluated on the device, orthonormalised, and a
+ * one-workgroup MaxVol kernel (start from pivoted elimination, swaps while
+ * an entry of Q Q[rows]^{-1} exceeds 1.01) gives the rows and the core.  It
+ * stops when the relative error on 1000 seeded random grid points is <= tol
+ * (or at rmax), then rounds at relative tol / 10.  f_out: cores with room for
+ * rmax * (N_l - 2) * rmax doubles; ranks written.  rank_out and
+ * sample_error_out (host, nullable) receive the last cross rank and its
+ * sampled error.  EINVAL for a bad kind, sizes or non-finite parameters or
+ * function values.  Synchronises stream. */
+int t2s2_source_cross(t2s2_problem* p, int kind, const double* params, double tol, int r0, int rmax,
+                      unsigned long long seed, t2s2_tt* f_out, int* rank_out, double* sample_error_out,
+                      void* stream);
 /* The source of the manufactured solution u = prod_l sin(pi x_l) exp(x_l):
  * f = sum_l (-eps u_l'' + beta_l u_l')(x_l) prod_{k != l} u_k(x_k), rank d. */
 int t2s2_source_manufactured(t2s2_problem* p, t2s2_tt* f_out, void* stream);

@@ -22,7 +22,7 @@ EXPORTED = [
     "t2s2_mlp_forward", "t2s2_mlp_backward", "t2s2_mlp_adam_step", "t2s2_mlp_infer_bf16", "t2s2_mlp_train",
     "t2s2_tt_fit_loss", "t2s2_tt_pack", "t2s2_tt_unpack", "t2s2_source_gaussians", "t2s2_source_manufactured",
     "t2s2_debug_iteration_limits", "t2s2_tt_matvec_noalloc", "t2s2_problem_create_reaction",
-    "t2s2_mol_create", "t2s2_mol_step", "t2s2_tt_fiber", "t2s2_problem_create_general",
+    "t2s2_mol_create", "t2s2_mol_step", "t2s2_tt_fiber", "t2s2_problem_create_general", "t2s2_source_cross",
 ]
 TIMING_CLASSES = ["gemm_f64", "gemm_c128", "ttm_matvec", "schur_qr", "hessenberg", "jacobi_svd", "cholesky",
                   "trtri", "trevec", "kron_trisolve", "hess_solve", "other"]
@@ -122,6 +122,8 @@ def lib() -> C.CDLL:
     L.t2s2_tt_unpack.argtypes = [C.c_int, ip, C.c_int, vp, C.POINTER(TTStruct), vp]
     L.t2s2_source_gaussians.argtypes = [vp, C.c_int, dp, dp, dp, C.POINTER(TTStruct), vp]
     L.t2s2_source_manufactured.argtypes = [vp, C.POINTER(TTStruct), vp]
+    L.t2s2_source_cross.argtypes = [vp, C.c_int, dp, C.c_double, C.c_int, C.c_int, u64, C.POINTER(TTStruct), ip, dp,
+                                    vp]
     L.t2s2_default_options.argtypes = [C.POINTER(Options)]
     L.t2s2_default_options.restype = None
     L.t2s2_timing_enable.argtypes = [C.c_int]

@@ -11,6 +11,7 @@
 #include <thread>
 #include <vector>
 
+#include "cross.h"
 #include "mlp.h"
 #include "solver.h"
 #include "sources.h"
@@ -554,6 +555,26 @@ static int source_common(t2s2_problem* p, int kind, int s, const double* amp, co
 int t2s2_source_gaussians(t2s2_problem* p, int s, const double* amp, const double* centre, const double* width,
                           t2s2_tt* f_out, void* stream) {
   return guarded([&] { return source_common(p, 0, s, amp, centre, width, f_out, stream); });
+}
+
+int t2s2_source_cross(t2s2_problem* p, int kind, const double* params, double tol, int r0, int rmax,
+                      unsigned long long seed, t2s2_tt* f_out, int* rank_out, double* sample_error_out,
+                      void* stream) {
+  return guarded([&] {
+    T2S2_CHECK(p && params && f_out && f_out->cores && f_out->ranks && f_out->d == p->P->d,
+               "invalid problem, parameters or output TT");
+    t2s2::CrossFunction fn;
+    fn.kind = kind;
+    fn.params.assign(params, params + 2 + 2 * p->P->d);
+    t2s2::DTT fd;
+    fd.c.assign(f_out->cores, f_out->cores + f_out->d);
+    t2s2::Ctx c = ctx_for(p, stream);
+    const t2s2::CrossInfo info = t2s2::source_cross(*p->P, c, fn, tol, r0, rmax, seed, 1000, fd);
+    for (int l = 0; l <= fd.d; ++l) f_out->ranks[l] = fd.r[l];
+    if (rank_out) *rank_out = info.rank;
+    if (sample_error_out) *sample_error_out = info.sample_error;
+    return T2S2_OK;
+  });
 }
 
 int t2s2_source_manufactured(t2s2_problem* p, t2s2_tt* f_out, void* stream) {

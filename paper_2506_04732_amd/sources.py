@@ -44,3 +44,26 @@ def manufactured(problem: Problem) -> TT:
     check(lib().t2s2_source_manufactured(problem._h, C.byref(fs), _stream()))
     f._read_ranks()
     return f
+
+
+CROSS_RATIONAL, CROSS_EXP_DIST, CROSS_SIN_LINEAR = 0, 1, 2
+
+
+def cross(problem: Problem, kind: int, amp: float, aux: float, w: Sequence[float], c: Sequence[float] = None,
+          tol: float = 1e-10, r0: int = 2, rmax: int = 64, seed: int = 0):
+    """t2s2_source_cross: a non-separable source sampled on the collocation
+    grid by TT-cross with MaxVol.  kind 0: amp / (1 + sum w_l (x_l - c_l)^2);
+    1: amp exp(-sqrt(aux + sum w_l (x_l - c_l)^2)); 2: amp sin(aux + sum w_l x_l).
+    Returns (TT, {"rank", "sample_error"})."""
+    d = problem.d
+    wv = np.ascontiguousarray(w, dtype=np.float64).reshape(d)
+    cv = np.zeros(d) if c is None else np.ascontiguousarray(c, dtype=np.float64).reshape(d)
+    par = np.concatenate([[float(amp), float(aux)], wv, cv])
+    f = TT.empty(problem.m, int(rmax))
+    fs = f._struct()
+    rk, err = C.c_int(), C.c_double()
+    check(lib().t2s2_source_cross(problem._h, int(kind), par.ctypes.data_as(C.POINTER(C.c_double)), float(tol),
+                                  int(r0), int(rmax), C.c_ulonglong(seed), C.byref(fs), C.byref(rk), C.byref(err),
+                                  _stream()))
+    f._read_ranks()
+    return f, {"rank": rk.value, "sample_error": err.value}
