@@ -142,7 +142,10 @@ def cpu_baseline(prob, one_thread: bool = True) -> dict:
     return out
 
 
-BATCH_OPTS = dict(tol=1e-10, target=1e-8, max_sweeps=30, kick=8, init_rank=8, check_every=0, seed=0)
+# overlap off: with many instances in flight the GPU is already full, and
+# overlap mode factors both interfaces (twice the Francis work) and adds two
+# streams per instance onto the same hardware queues
+BATCH_OPTS = dict(tol=1e-10, target=1e-8, max_sweeps=30, kick=8, init_rank=8, check_every=0, seed=0, overlap=False)
 
 
 def bench_batched(args, rank: int):
@@ -451,6 +454,8 @@ def main():
     ap.add_argument("--warm-test", type=int, default=8, help="6d line's warm leg: held-out instances")
     ap.add_argument("--warm-epochs", type=int, default=100, help="6d line's warm leg: epochs")
     ap.add_argument("--no-oracle-check", action="store_true")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
+                    help="6d: arithmetic of the local solves (mixed: FP32 factorisations inside FP64 refinement)")
     ap.add_argument("--no-overlap", action="store_true",
                     help="6d: every factorisation on the solve's stream (no side-stream eigendecompositions)")
     ap.add_argument("--workload", choices=["6d", "batched256", "warm7d", "stability", "spacetime7d"], default="6d",
@@ -497,6 +502,8 @@ def main():
     prob = workloads.steady_6d(0, 32)
     if args.no_overlap:
         SOLVE_OPTS["overlap"] = False
+    if args.precision == "mixed":
+        SOLVE_OPTS["precision"] = t2s2.PRECISION_MIXED
     p = t2s2.Problem(prob.d, prob.N, prob.eps, prob.beta, prob.scheme, rank_cap=RANK_CAP)
     f = sources.gaussians(p, prob.gauss.amp, prob.gauss.centre, prob.gauss.width)
     x = TT.empty(p.m, RANK_CAP)
@@ -566,6 +573,8 @@ def main():
         "residual": last.residual,
         "phase_ms": last.phase_ms,
         "overlap": SOLVE_OPTS.get("overlap", True),
+        "precision": args.precision,
+        "refinement_steps": last.refinement_steps, "fp64_fallbacks": last.fp64_fallbacks,
         "roofline": roof,
         "ttm_matvec_hbm": ttmv,
         "kernels": kernels,

@@ -384,7 +384,7 @@ def solve_batched(problems: Sequence["Problem"], fs: Sequence[TT], *, x0s: Optio
                   outs: Optional[Sequence[TT]] = None, workers: int = 16, tol: float = 1e-10,
                   target: float = 1e-8, max_sweeps: int = 40, kick: int = 8, rank_cap: Optional[int] = None,
                   init_rank: int = 2, seed: int = 0, check_every: int = 1,
-                  precision: int = PRECISION_FP64) -> List[SolveResult]:
+                  precision: int = PRECISION_FP64, overlap: bool = False) -> List[SolveResult]:
     """t2s2_solve_batched: every instance solved as Problem.solve would, up to
     `workers` at a time on their own streams.  rank_cap None: each problem's own."""
     count = len(problems)
@@ -397,6 +397,7 @@ def solve_batched(problems: Sequence["Problem"], fs: Sequence[TT], *, x0s: Optio
         raise ValueError("one rank_cap applies to every instance: pass rank_cap or use equal problem caps")
     xs = list(outs) if outs is not None else [TT.empty(p.m, caps[0]) for p in problems]
     o = _options(tol, target, max_sweeps, kick, caps[0], init_rank, seed, check_every, False, precision)
+    o.overlap = int(bool(overlap))
     reps = (_lib.Report * count)()
     fst = [f._struct() for f in fs]
     xst = [x._struct() for x in xs]

@@ -43,7 +43,7 @@ def test_batched_equals_single_solves_and_dense():
     _say("batched small", [q.name for q in insts])
     cap = 40
     pf = [_gpu(q, cap) for q in insts]
-    opts = dict(tol=1e-12, target=1e-12, max_sweeps=30, kick=4, init_rank=2)
+    opts = dict(tol=1e-12, target=1e-12, max_sweeps=30, kick=4, init_rank=2, overlap=False)
     single = [p.solve(f, **opts) for p, f in pf]
     batch = t2s2.solve_batched([p for p, _ in pf], [f for _, f in pf], workers=4, **opts)
     for q, s, b in zip(insts, single, batch):

@@ -78,7 +78,7 @@ def test_dirichlet_batched_equals_single():
     for q in probs:
         q.rank_cap = cap
     pfg = [_gpu(q) for q in probs]
-    opts = dict(tol=1e-12, target=1e-12, max_sweeps=30, kick=4)
+    opts = dict(tol=1e-12, target=1e-12, max_sweeps=30, kick=4, overlap=False)
     single = [p.solve(f, g=g, **opts) for p, f, g in pfg]
     batch = t2s2.solve_batched([p for p, _, _ in pfg], [f for _, f, _ in pfg], gs=[g for _, _, g in pfg],
                                workers=2, **opts)
