@@ -454,6 +454,8 @@ def main():
     ap.add_argument("--warm-test", type=int, default=8, help="6d line's warm leg: held-out instances")
     ap.add_argument("--warm-epochs", type=int, default=100, help="6d line's warm leg: epochs")
     ap.add_argument("--no-oracle-check", action="store_true")
+    ap.add_argument("--kick", type=int, default=None, help="6d: enrichment rank (default 24)")
+    ap.add_argument("--init-rank", type=int, default=None, help="6d: rank of the seeded random start (default 64)")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
                     help="6d: arithmetic of the local solves (mixed: FP32 factorisations inside FP64 refinement)")
     ap.add_argument("--no-overlap", action="store_true",
@@ -502,6 +504,10 @@ def main():
     prob = workloads.steady_6d(0, 32)
     if args.no_overlap:
         SOLVE_OPTS["overlap"] = False
+    if args.kick is not None:
+        SOLVE_OPTS["kick"] = args.kick
+    if args.init_rank is not None:
+        SOLVE_OPTS["init_rank"] = args.init_rank
     if args.precision == "mixed":
         SOLVE_OPTS["precision"] = t2s2.PRECISION_MIXED
     p = t2s2.Problem(prob.d, prob.N, prob.eps, prob.beta, prob.scheme, rank_cap=RANK_CAP)
@@ -575,6 +581,7 @@ def main():
         "overlap": SOLVE_OPTS.get("overlap", True),
         "precision": args.precision,
         "refinement_steps": last.refinement_steps, "fp64_fallbacks": last.fp64_fallbacks,
+        "refinement_capped": last.refinement_capped, "max_eig_cond": last.max_eig_cond,
         "roofline": roof,
         "ttm_matvec_hbm": ttmv,
         "kernels": kernels,

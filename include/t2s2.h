@@ -151,6 +151,12 @@ typedef struct {
   int refinement_capped;                        /* local refinements that
                                                    stopped at their step cap
                                                    above 0.1 tol / sqrt(d)  */
+  double max_eig_cond;                          /* largest ||V||_F ||V^-1||_F
+                                                   (>= cond_2(V)) of the FP64
+                                                   eigenvector bases of the
+                                                   interface matrices; the
+                                                   FP64 refinement absorbs
+                                                   the error they cause     */
   double phase_ms[T2S2_PHASES];                 /* device time per phase on
                                                    the solve's stream: 0 set-up
                                                    (Dirichlet lift, start,

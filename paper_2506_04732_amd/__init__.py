@@ -169,6 +169,7 @@ class SolveResult:
     warm_residual: float = -1.0
     cold_residual: float = -1.0
     refinement_capped: int = 0
+    max_eig_cond: float = 0.0
     phase_ms: dict = field(default_factory=dict)
 
     @property
@@ -375,7 +376,7 @@ def _result(x: TT, code: int, rep, d: int) -> SolveResult:
                        local_systems=rep.local_systems, refinement_steps=rep.refinement_steps,
                        fp64_fallbacks=rep.fp64_fallbacks, warm_start_used=rep.warm_start_used,
                        warm_residual=rep.warm_residual, cold_residual=rep.cold_residual,
-                       refinement_capped=rep.refinement_capped,
+                       refinement_capped=rep.refinement_capped, max_eig_cond=rep.max_eig_cond,
                        phase_ms={n: rep.phase_ms[i] for i, n in enumerate(_lib.PHASE_NAMES)})
 
 

@@ -53,7 +53,7 @@ class Report(C.Structure):
                 ("history_time_ms", C.c_double * MAX_HISTORY), ("precision", C.c_int),
                 ("local_systems", C.c_int), ("refinement_steps", C.c_int), ("fp64_fallbacks", C.c_int),
                 ("warm_start_used", C.c_int), ("warm_residual", C.c_double),
-                ("cold_residual", C.c_double), ("refinement_capped", C.c_int),
+                ("cold_residual", C.c_double), ("refinement_capped", C.c_int), ("max_eig_cond", C.c_double),
                 ("phase_ms", C.c_double * PHASES)]
 
 

@@ -129,6 +129,7 @@ void fill_report(t2s2_report* rep, const t2s2::SolveReport& r, int st, int d, in
   rep->warm_residual = r.warm_residual;
   rep->cold_residual = r.cold_residual;
   rep->refinement_capped = r.refinement_capped;
+  rep->max_eig_cond = r.max_eig_cond;
   for (int i = 0; i < T2S2_PHASES; ++i) rep->phase_ms[i] = r.phase_ms[i];
   for (int i = 0; i < h; ++i) {
     rep->history_residual[i] = r.hist_res[i];

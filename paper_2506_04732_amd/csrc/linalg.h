@@ -110,6 +110,9 @@ void schur_real(const Ctx& c, int n, const double* A, double2* ZT, double2* T);
 void set_iteration_limits(int francis_steps, int jacobi_sweeps);
 int francis_step_limit(int n);  // defined next to the Francis kernel
 int jacobi_sweep_limit();
+// *slot <- max(*slot, ||V||_F ||Vi||_F), an upper bound of cond_2(V) of an
+// eigenvector basis (n x n complex), on c's stream
+void cond_estimate(const Ctx& c, int n, const double2* V, const double2* Vi, double* slot);
 // c.fail <- 0 (on c's stream); whether c.fail is set (synchronises c's stream)
 void clear_fail(const Ctx& c);
 bool read_fail(const Ctx& c);

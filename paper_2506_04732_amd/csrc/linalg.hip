@@ -21,7 +21,37 @@ void flag_francis(const Ctx& c, const int* info) {
   T2S2_LAUNCH_CHECK();
 }
 int g_jacobi_sweeps = 0;
+
+// slot[0] = max(slot[0], ||V||_F ||Vi||_F), one workgroup of 256
+__global__ void cond_fro_kernel(long nn, const double2* __restrict__ V, const double2* __restrict__ Vi,
+                                double* __restrict__ slot) {
+  __shared__ double sa[256], sb[256];
+  double a = 0.0, b = 0.0;
+  for (long e = threadIdx.x; e < nn; e += blockDim.x) {
+    a += V[e].x * V[e].x + V[e].y * V[e].y;
+    b += Vi[e].x * Vi[e].x + Vi[e].y * Vi[e].y;
+  }
+  sa[threadIdx.x] = a;
+  sb[threadIdx.x] = b;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      sa[threadIdx.x] += sa[threadIdx.x + h];
+      sb[threadIdx.x] += sb[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double cnd = sqrt(sa[0]) * sqrt(sb[0]);
+    if (!(slot[0] >= cnd)) slot[0] = cnd;
+  }
+}
 }  // namespace
+
+void cond_estimate(const Ctx& c, int n, const double2* V, const double2* Vi, double* slot) {
+  hipLaunchKernelGGL(cond_fro_kernel, dim3(1), dim3(256), 0, c.s, (long)n * n, V, Vi, slot);
+  T2S2_LAUNCH_CHECK();
+}
 
 void set_iteration_limits(int francis_steps, int jacobi_sweeps);
 void set_francis_step_limit(int steps);  // schur.hip

@@ -83,6 +83,7 @@ struct SolveReport {
   std::vector<int> hist_rank;
   int local_systems = 0, refinement_steps = 0, fp64_fallbacks = 0;
   int refinement_capped = 0;  // local refinements stopped at the step cap above 0.1 tol / sqrt(d)
+  double max_eig_cond = 0.0;  // largest ||V||_F ||V^-1||_F of the FP64 interface eigenvector bases
   // device time per phase (events on the solve's stream): 0 set-up (start,
   // orthogonalisation, first interfaces, warm-start judge), 1 local solves,
   // 2 splits (truncated SVD, enrichment, QR), 3 interface updates and

@@ -805,6 +805,7 @@ struct Amen {
   std::vector<int> maxrank;     // structural bound per bond
   // work
   double *u, *f, *res, *y, *T1, *T2, *A1, *S, *kick_buf, *zbuf, *U, *W, *tmp, *Qk, *Rk;
+  double* cond = nullptr;  // per bond: largest ||V||_F ||V^-1||_F seen (device)
   double2 *h0, *h1;
   float2 *g0, *g1;
   double* hr;
@@ -842,6 +843,7 @@ struct Amen {
       eig_from_hessenberg(x, n, hf[pos].Hc, hf[pos].QT, eig[pos].lam, eig[pos].V, eig[pos].Vi);
     else
       eig_nonsym(x, n, L[pos], eig[pos].lam, eig[pos].V, eig[pos].Vi);
+    cond_estimate(x, n, eig[pos].V, eig[pos].Vi, cond + pos);
     T2S2_HIP(hipEventRecord(ev_eig[pos], x.s));
     eig_pending[pos] = 1;
     has_eig[pos] = 1;
@@ -857,6 +859,7 @@ struct Amen {
       return;
     }
     eig_nonsym(c, n, L[pos], eig[pos].lam, eig[pos].V, eig[pos].Vi);
+    cond_estimate(c, n, eig[pos].V, eig[pos].Vi, cond + pos);
     has_eig[pos] = 1;
   }
   // a new interface at bond pos (size n), left or right of the sites that use
@@ -951,6 +954,7 @@ struct Amen {
       ok64[pos] = 0;
     } else {
       eig_nonsym(c, n, L[pos], eig[pos].lam, eig[pos].V, eig[pos].Vi);
+      cond_estimate(c, n, eig[pos].V, eig[pos].Vi, cond + pos);
       ok64[pos] = 1;
       ok32[pos] = 0;
     }
@@ -958,6 +962,7 @@ struct Amen {
   void ensure64(int pos, int n) {
     if (!lhess[pos] && !ok64[pos]) {
       eig_nonsym(c, n, L[pos], eig[pos].lam, eig[pos].V, eig[pos].Vi);
+      cond_estimate(c, n, eig[pos].V, eig[pos].Vi, cond + pos);
       ok64[pos] = 1;
     }
   }
@@ -1172,6 +1177,8 @@ struct Amen {
     g0 = c.sc->get<float2>("am.g0", big);
     g1 = c.sc->get<float2>("am.g1", big);
     hr = buf("hr", big);
+    cond = buf("cond", (size_t)d + 1);
+    fill(c.s, cond, d + 1, 0.0);
     if (x0 && o.warm_judge) {
       // the given start is kept only if its FP64 residual beats that of the
       // seeded random start a cold solve would use (the fallback)
@@ -1353,6 +1360,12 @@ struct Amen {
     pc.mark(0);
     c.sync();
     pc.collect(rep.phase_ms);
+    {
+      // eigendecompositions still running on the side streams are left out
+      std::vector<double> hc(d + 1);
+      c.d2h(hc.data(), cond, d + 1);
+      for (double v : hc) rep.max_eig_cond = std::max(rep.max_eig_cond, v);
+    }
     if (read_fail(c)) throw Error(5, "solve: Francis QR of an interface matrix did not converge");
     rep.time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     return status;

@@ -108,3 +108,5 @@ def test_report_phases_and_refinement_counts():
     # device time of the phases is the stream's busy time inside the solve
     assert sum(ph.values()) <= r.time_ms * 1.05
     assert 0 <= r.refinement_capped <= r.local_systems
+    # the eigenvector bases of the interfaces: ||V|| ||V^-1|| >= cond(V) >= 1
+    assert np.isfinite(r.max_eig_cond) and r.max_eig_cond >= 1.0
