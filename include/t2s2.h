@@ -538,6 +538,19 @@ int t2s2_timing_classes(unsigned int mask);
 int t2s2_timing_read(int cls, double* total_ms, long long* launches, double* bytes, double* flops);
 const char* t2s2_timing_class_name(int cls);
 
+/* One strided-batched FP64 GEMM with the library's kernels, row-major:
+ * C_b = alpha op(A_b) op(B_b) + beta C_b, X_b = X + b * sX, op 0 = N, 1 = T,
+ * op(A) M x K, op(B) K x N.  variant: 0 the vector-ALU kernel, 1 the
+ * matrix-core kernel (V_MFMA_F64_16X16X4_F64), -1 the choice of the tuning
+ * table that every FP64 GEMM of the solver uses (written by
+ * paper_2506_04732_amd/autotune.py from timings of both kernels on the GPU;
+ * t2s2_gemm_tune_source names where it came from).  For tests and tuning;
+ * device buffers, asynchronous on stream; EINVAL for bad arguments. */
+int t2s2_debug_gemm(int variant, int opA, int opB, int M, int N, int K, int batch, double alpha, const double* A,
+                    long long lda, long long sA, const double* B, long long ldb, long long sB, double beta,
+                    double* C, long long ldc, long long sC, void* stream);
+const char* t2s2_gemm_tune_source(void);
+
 /* Iteration limits of the dense factorisations, process-wide (0 restores a
  * default: 40 n + 100 Francis double-shift steps for an n x n matrix, 60
  * one-sided Jacobi sweeps).  For tests of the error path: with a lowered

@@ -23,6 +23,7 @@ EXPORTED = [
     "t2s2_tt_fit_loss", "t2s2_tt_pack", "t2s2_tt_unpack", "t2s2_source_gaussians", "t2s2_source_manufactured",
     "t2s2_debug_iteration_limits", "t2s2_tt_matvec_noalloc", "t2s2_problem_create_reaction",
     "t2s2_mol_create", "t2s2_mol_step", "t2s2_tt_fiber", "t2s2_problem_create_general", "t2s2_source_cross",
+    "t2s2_debug_gemm", "t2s2_gemm_tune_source",
 ]
 TIMING_CLASSES = ["gemm_f64", "gemm_c128", "ttm_matvec", "schur_qr", "hessenberg", "jacobi_svd", "cholesky",
                   "trtri", "trevec", "kron_trisolve", "hess_solve", "other"]
@@ -105,6 +106,11 @@ def lib() -> C.CDLL:
     L.t2s2_solve_batched.argtypes = [C.c_int, C.POINTER(vp), C.POINTER(ttp), C.POINTER(ttp), C.POINTER(ttp),
                                      C.POINTER(Options), C.POINTER(ttp), C.POINTER(Report), C.c_int, vp]
     L.t2s2_debug_iteration_limits.argtypes = [C.c_int, C.c_int]
+    ll = C.c_longlong
+    L.t2s2_debug_gemm.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, vp, ll,
+                                  ll, vp, ll, ll, C.c_double, vp, ll, ll, vp]
+    L.t2s2_gemm_tune_source.argtypes = []
+    L.t2s2_gemm_tune_source.restype = C.c_char_p
     fp, u64 = C.POINTER(C.c_float), C.c_ulonglong
     L.t2s2_mlp_create.argtypes = [C.c_int, ip, u64, C.POINTER(vp)]
     L.t2s2_mlp_destroy.argtypes = [vp]
@@ -132,7 +138,8 @@ def lib() -> C.CDLL:
     L.t2s2_timing_class_name.argtypes = [C.c_int]
     L.t2s2_timing_class_name.restype = C.c_char_p
     for name in EXPORTED:
-        if name not in ("t2s2_last_error", "t2s2_default_options", "t2s2_timing_class_name", "t2s2_mlp_destroy"):
+        if name not in ("t2s2_last_error", "t2s2_default_options", "t2s2_timing_class_name", "t2s2_mlp_destroy",
+                        "t2s2_gemm_tune_source"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L

@@ -451,6 +451,29 @@ int t2s2_solve(t2s2_problem* p, const t2s2_tt* f, const t2s2_tt* g, const t2s2_t
   return guarded([&] { return solve_one(p, f, g, x0, opts, x_out, rep, static_cast<hipStream_t>(stream)); });
 }
 
+int t2s2_debug_gemm(int variant, int opA, int opB, int M, int N, int K, int batch, double alpha, const double* A,
+                    long long lda, long long sA, const double* B, long long ldb, long long sB, double beta,
+                    double* C, long long ldc, long long sC, void* stream) {
+  return guarded([&] {
+    T2S2_CHECK(variant >= -1 && variant <= 1, "variant must be -1, 0 or 1");
+    T2S2_CHECK((opA == 0 || opA == 1) && (opB == 0 || opB == 1), "opA, opB must be 0 (N) or 1 (T)");
+    T2S2_CHECK(M >= 1 && N >= 1 && K >= 1 && batch >= 1 && A && B && C, "bad sizes or NULL pointer");
+    T2S2_CHECK(lda >= (opA == 0 ? K : M) && ldb >= (opB == 0 ? N : K) && ldc >= N, "leading dimensions too small");
+    t2s2::gemm_force_variant(variant);
+    try {
+      t2s2::gemm<double>(static_cast<hipStream_t>(stream), static_cast<t2s2::Op>(opA), static_cast<t2s2::Op>(opB), M,
+                         N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, false);
+    } catch (...) {
+      t2s2::gemm_force_variant(-1);
+      throw;
+    }
+    t2s2::gemm_force_variant(-1);
+    return T2S2_OK;
+  });
+}
+
+const char* t2s2_gemm_tune_source(void) { return t2s2::gemm_tune_source(); }
+
 int t2s2_debug_iteration_limits(int francis_steps, int jacobi_sweeps) {
   return guarded([&] {
     T2S2_CHECK(francis_steps >= 0 && jacobi_sweeps >= 0, "iteration limits must be >= 0");

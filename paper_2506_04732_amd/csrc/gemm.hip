@@ -17,6 +17,8 @@
 
 #include <map>
 
+#include "gemm_tune.h"
+
 #include <algorithm>
 #include <type_traits>
 
@@ -179,6 +181,101 @@ gemm_kernel(int opA, int opB, int M, int N, int K, T alpha,
   }
 }
 
+// FP64 on the matrix cores: the same 64 x 64 tile and K staging as
+// gemm_kernel, each of the 4 wavefronts computing a 32 x 32 quarter as 2 x 2
+// blocks of V_MFMA_F64_16X16X4_F64 (lane l holds A[l % 16][k0 + l / 16] and
+// B[k0 + l / 16][l % 16]; output element (l / 16 + 4 i, l % 16) in slot i).
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(NT)
+gemm_mfma_f64_kernel(int opA, int opB, int M, int N, int K, double alpha,
+                     const double* __restrict__ A, long lda, long sA,
+                     const double* __restrict__ B, long ldb, long sB,
+                     double beta, double* __restrict__ C, long ldc, long sC, int kchunk) {
+  __shared__ double As[BK][BM + 1];
+  __shared__ double Bs[BK][BN + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const long bz = blockIdx.z;
+  int kbeg = 0, kend = K;
+  if (kchunk > 0) {
+    kbeg = (int)bz * kchunk;
+    kend = min(K, kbeg + kchunk);
+  } else {
+    A += bz * sA;
+    B += bz * sB;
+  }
+  C += bz * sC;
+  dbl4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+  constexpr int SA = (BM * BK) / NT, SB = (BN * BK) / NT;
+  const bool ta = (opA == 1), tb = (opB == 1);
+  double ra[SA], rb[SB];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int s = 0; s < SA; ++s) {
+      const int e = tid + NT * s;
+      int i, k;
+      if (!ta) { i = e / BK; k = e % BK; } else { k = e / BM; i = e % BM; }
+      const int gi = m0 + i, gk = k0 + k;
+      ra[s] = (gi < M && gk < kend) ? (!ta ? A[(long)gi * lda + gk] : A[(long)gk * lda + gi]) : 0.0;
+    }
+#pragma unroll
+    for (int s = 0; s < SB; ++s) {
+      const int e = tid + NT * s;
+      int j, k;
+      if (!tb) { k = e / BN; j = e % BN; } else { j = e / BK; k = e % BK; }
+      const int gj = n0 + j, gk = k0 + k;
+      rb[s] = (gj < N && gk < kend) ? (!tb ? B[(long)gk * ldb + gj] : B[(long)gj * ldb + gk]) : 0.0;
+    }
+  };
+  if (kbeg < kend) fetch(kbeg);
+  const int li = lane & 15, lk = lane >> 4;
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+#pragma unroll
+    for (int s = 0; s < SA; ++s) {
+      const int e = tid + NT * s;
+      if (!ta) As[e % BK][e / BK] = ra[s]; else As[e / BM][e % BM] = ra[s];
+    }
+#pragma unroll
+    for (int s = 0; s < SB; ++s) {
+      const int e = tid + NT * s;
+      if (!tb) Bs[e / BN][e % BN] = rb[s]; else Bs[e % BK][e / BK] = rb[s];
+    }
+    __syncthreads();
+    if (k0 + BK < kend) fetch(k0 + BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      const int kr = kk + lk;
+      const double a0 = As[kr][wr + li], a1 = As[kr][wr + 16 + li];
+      const double b0 = Bs[kr][wc + li], b1 = Bs[kr][wc + 16 + li];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  const bool beta_zero = (beta == 0.0);
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int gi = m0 + wr + bi * 16 + lk + 4 * i, gj = n0 + wc + bj * 16 + li;
+        if (gi >= M || gj >= N) continue;
+        double* c = C + (long)gi * ldc + gj;
+        double v = alpha * acc[bi][bj][i];
+        if (!beta_zero) v += beta * *c;
+        *c = v;
+      }
+}
+
 // C = alpha * sum_z W[z] + beta * C  (split-K epilogue, deterministic order)
 template <class T>
 __global__ void splitk_reduce_kernel(int M, int N, int S, const T* __restrict__ W, T alpha, T beta,
@@ -225,6 +322,14 @@ T* split_workspace(hipStream_t s, size_t count) {
 
 template <class T> bool AR_beta_nonzero(T b) { return !Arith<T>::is_zero_host(b); }
 
+thread_local int g_force_variant = -1;
+
+int tune_bucket(long x) {
+  int b = 0;
+  while ((1L << (b + 4)) < x && b < kGemmTuneB - 1) ++b;
+  return b;
+}
+
 template <class T> T one_of();
 template <> double one_of<double>() { return 1.0; }
 template <> float one_of<float>() { return 1.0f; }
@@ -253,6 +358,17 @@ void gemm(hipStream_t s, Op opA, Op opB, int M, int N, int K, T alpha,
                 elem * ((double)M * K + (double)K * N + (double)M * N * (AR_beta_nonzero(beta) ? 2.0 : 1.0)) * batch,
                 (cplx ? 8.0 : 2.0) * (double)M * N * K * batch, timed);
   const long tiles = (long)((N + BN - 1) / BN) * ((M + BM - 1) / BM);
+  // real FP64 without conjugation: the matrix-core kernel where the tuning
+  // table (or a forced choice) says it is faster
+  bool mfma = false;
+  if constexpr (std::is_same<T, double>::value) {
+    if ((opA == OpN || opA == OpT) && (opB == OpN || opB == OpT)) {
+      const int v = g_force_variant >= 0
+                        ? g_force_variant
+                        : kGemmTune[batch > 1 ? 1 : 0][tune_bucket(M)][tune_bucket(N)][tune_bucket(K)];
+      mfma = (v == 1);
+    }
+  }
   if (batch == 1 && tiles < 256 && K >= 256) {
     // few output tiles, long reduction: split K into slabs of ~128 (each
     // workgroup runs a short loop, many run at once), at most ~1024 slabs
@@ -264,8 +380,14 @@ void gemm(hipStream_t s, Op opA, Op opB, int M, int N, int K, T alpha,
     const long MN = (long)M * N;
     T* W = split_workspace<T>(s, (size_t)S * MN);
     dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, S);
-    hipLaunchKernelGGL(gemm_kernel<T>, grid, dim3(NT), 0, s, (int)opA, (int)opB, M, N, K, one_of<T>(),
-                       A, lda, 0L, B, ldb, 0L, zero_of<T>(), W, (long)N, MN, kchunk);
+    if constexpr (std::is_same<T, double>::value) {
+      if (mfma)
+        hipLaunchKernelGGL(gemm_mfma_f64_kernel, grid, dim3(NT), 0, s, (int)opA, (int)opB, M, N, K, 1.0, A, lda, 0L,
+                           B, ldb, 0L, 0.0, W, (long)N, MN, kchunk);
+    }
+    if (!mfma)
+      hipLaunchKernelGGL(gemm_kernel<T>, grid, dim3(NT), 0, s, (int)opA, (int)opB, M, N, K, one_of<T>(),
+                         A, lda, 0L, B, ldb, 0L, zero_of<T>(), W, (long)N, MN, kchunk);
     T2S2_LAUNCH_CHECK();
     const int rb = (int)std::min<long>((MN + 255) / 256, 2048);
     hipLaunchKernelGGL(splitk_reduce_kernel<T>, dim3(rb), dim3(256), 0, s, M, N, S, W, alpha, beta, C, ldc);
@@ -273,6 +395,14 @@ void gemm(hipStream_t s, Op opA, Op opB, int M, int N, int K, T alpha,
     return;
   }
   dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, batch);
+  if constexpr (std::is_same<T, double>::value) {
+    if (mfma) {
+      hipLaunchKernelGGL(gemm_mfma_f64_kernel, grid, dim3(NT), 0, s, (int)opA, (int)opB, M, N, K, alpha, A, lda,
+                         strideA, B, ldb, strideB, beta, C, ldc, strideC, 0);
+      T2S2_LAUNCH_CHECK();
+      return;
+    }
+  }
   hipLaunchKernelGGL(gemm_kernel<T>, grid, dim3(NT), 0, s, (int)opA, (int)opB, M, N, K, alpha,
                      A, lda, strideA, B, ldb, strideB, beta, C, ldc, strideC, 0);
   T2S2_LAUNCH_CHECK();
@@ -286,5 +416,8 @@ template void gemm<float>(hipStream_t, Op, Op, int, int, int, float, const float
                           const float*, long, long, float, float*, long, long, int, bool);
 template void gemm<float2>(hipStream_t, Op, Op, int, int, int, float2, const float2*, long, long,
                            const float2*, long, long, float2, float2*, long, long, int, bool);
+
+void gemm_force_variant(int v) { g_force_variant = v; }
+const char* gemm_tune_source() { return kGemmTuneSource; }
 
 }  // namespace t2s2
