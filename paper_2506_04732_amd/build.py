@@ -16,7 +16,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libt2s2.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["spectral_host.cpp", "timing.cpp", "gemm.hip", "tt_kernels.hip", "dense_small.hip", "schur.hip", "linalg.hip", "ddnorm.hip", "kron_hess.hip", "solver.hip", "mlp.hip", "sources.hip", "cross.hip", "api.hip"]
+SOURCES = ["spectral_host.cpp", "timing.cpp", "readback.hip", "gemm.hip", "tt_kernels.hip", "dense_small.hip", "schur.hip", "linalg.hip", "ddnorm.hip", "kron_hess.hip", "solver.hip", "mlp.hip", "sources.hip", "cross.hip", "api.hip"]
 
 ARCH = os.environ.get("T2S2_ARCH", "gfx950")
 # -packed-fp32-ops: hipcc must not emit packed FP32 instructions

@@ -9,6 +9,7 @@
 // memory otherwise.  Every kernel loops a bounded number of times and every
 // barrier is reached by all threads of the workgroup.
 #include "dense_small.h"
+#include "readback.h"
 
 #include <cfloat>
 #include <cstring>
@@ -1392,8 +1393,7 @@ void jacobi_rows(hipStream_t s, int k, int c, double* B, double* JT, double* U, 
                            blk, nblk, nplay, round, 1, info);
       T2S2_LAUNCH_CHECK();
       int st[2] = {0, 0};  // rotations, largest squared cosine (float bits)
-      T2S2_HIP(hipMemcpyAsync(st, info, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-      T2S2_HIP(hipStreamSynchronize(s));
+      host_read(s, st, info, 2 * sizeof(int));
       float cmax;
       std::memcpy(&cmax, &st[1], sizeof(float));
       if (st[0] == 0 || cmax <= kJacStop2) break;

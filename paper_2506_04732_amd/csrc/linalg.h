@@ -9,6 +9,7 @@
 #include "common.h"
 #include "dense_small.h"
 #include "gemm.h"
+#include "readback.h"
 #include "tt_kernels.h"
 
 namespace t2s2 {
@@ -39,16 +40,15 @@ struct Ctx {
   // its step limit; read by the caller at its next synchronisation
   int* fail = nullptr;
   void sync() const { T2S2_HIP(hipStreamSynchronize(s)); }
+  // after all earlier work on s (host_read: a pinned mailbox for small reads)
   template <class T>
   void d2h(T* h, const T* d, size_t n) const {
-    T2S2_HIP(hipMemcpyAsync(h, d, n * sizeof(T), hipMemcpyDeviceToHost, s));
-    sync();
+    host_read(s, h, d, n * sizeof(T));
   }
-  // synchronous, so the host buffer may be reused right after the call
+  // stream-ordered; the host buffer may be reused right after the call
   template <class T>
   void h2d(T* d, const T* h, size_t n) const {
-    T2S2_HIP(hipMemcpyAsync(d, h, n * sizeof(T), hipMemcpyHostToDevice, s));
-    sync();
+    host_write(s, d, h, n * sizeof(T));
   }
   template <class T>
   void d2d(T* d, const T* src, size_t n) const {
