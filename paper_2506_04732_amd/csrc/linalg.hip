@@ -155,6 +155,12 @@ template void mode3<float2>(const Ctx&, int, int, int, int, const float2*, const
 template void mode2<float2>(const Ctx&, int, int, int, int, const float2*, const float2*, float2*, float2, Op);
 
 // ------------------------------------------------------------ dcholqr
+// Host reads per level: one for the kept-pivot count and mask, one for the
+// two orthogonality passes' counts together with the remainder norm of the
+// deflation (both passes and, when the level leaves columns unrepresented,
+// the deflation run before that read, on the usual outcome that no column
+// becomes dependent in a pass).  If a pass did lose a column, the level's
+// passes are redone one at a time from their saved input.
 int dcholqr(const Ctx& c, int M, int n, const double* A, long lda, double* Qout, double* Rout, double drop) {
   T2S2_CHECK(M >= 1 && n >= 1, "dcholqr: empty matrix");
   const int kmax = std::min(M, n);
@@ -166,11 +172,17 @@ int dcholqr(const Ctx& c, int M, int n, const double* A, long lda, double* Qout,
   double* Rl = S.get<double>("dq.Rl", (size_t)n * n);
   double* Ak = S.get<double>("dq.Ak", (size_t)M * n);
   double* Qk = S.get<double>("dq.Qk", (size_t)M * n);
+  double* Qc = S.get<double>("dq.Qc", (size_t)M * n);
   double* R11 = S.get<double>("dq.R11", (size_t)n * n);
   double* R11i = S.get<double>("dq.R11i", (size_t)n * n);
   double* C = S.get<double>("dq.C", (size_t)kmax * n);
-  int* mask = S.get<int>("dq.mask", n);
-  int* cnt = S.get<int>("dq.cnt", 1);
+  double* partial = S.get<double>("dq.partial", kDotBlocks);
+  // status block read back in one piece: [0] ||A||^2, [1] remainder norm^2,
+  // then ints: level count, pass-0 count, pass-1 count, level mask (n)
+  double* st = S.get<double>("dq.st", 2 + ((size_t)n + 4) / 2 + 1);
+  int* sti = reinterpret_cast<int*>(st + 2);
+  int* mask = sti + 3;
+  int* pmask = S.get<int>("dq.pmask", n);
   int* idx = S.get<int>("dq.idx", n);
   // A (contiguous) is read in place
   const double* Ain = A;
@@ -179,14 +191,18 @@ int dcholqr(const Ctx& c, int M, int n, const double* A, long lda, double* Qout,
     Ain = Aw;
   }
   const double* Wk = Ain;      // the part of A not yet represented (level 0: A)
-  double normA2 = -1.0;        // ||A||^2, computed when a deflation test needs it
-  std::vector<int> hmask(n), hidx;
+  double normA2 = -1.0;        // ||A||^2, computed with the first deflation
+  std::vector<int> hlev(3 + (size_t)n), hidx;
+  struct {
+    double nrm[2];
+    int cnt[3];
+  } hst;
   int k = 0;
   for (int level = 0; level < 5 && k < kmax; ++level) {
     gemm<double>(c.s, OpT, OpN, n, n, M, 1.0, Wk, n, 0, Wk, n, 0, 0.0, G, n, 0, 1);
-    chol_skip(c.s, n, G, Rl, mask, cnt, 1e-11);
-    int kl = 0;
-    c.d2h(&kl, cnt, 1);
+    chol_skip(c.s, n, G, Rl, mask, sti, 1e-11);
+    c.d2h(hlev.data(), sti, 3 + (size_t)n);
+    int kl = hlev[0];
     if (kl == 0) break;
     const double* Ablk;   // the kept columns of Wk (M x kl)
     const double* Rblk;   // their Cholesky factor (kl x kl)
@@ -195,10 +211,9 @@ int dcholqr(const Ctx& c, int M, int n, const double* A, long lda, double* Qout,
       Ablk = Wk;
       Rblk = Rl;
     } else {
-      c.d2h(hmask.data(), mask, n);
       hidx.clear();
       for (int j = 0; j < n && (int)hidx.size() < kmax - k; ++j)
-        if (hmask[j]) hidx.push_back(j);
+        if (hlev[3 + j]) hidx.push_back(j);
       kl = (int)hidx.size();
       if (kl == 0) break;
       c.h2d(idx, hidx.data(), kl);
@@ -213,23 +228,70 @@ int dcholqr(const Ctx& c, int M, int n, const double* A, long lda, double* Qout,
     }
     trtri_upper(c.s, kl, Rblk, R11i);
     gemm<double>(c.s, OpN, OpN, M, kl, kl, 1.0, Ablk, kl, 0, R11i, kl, 0, 0.0, Qk, kl, 0, 1);
-    // orthogonality pass(es): reorthogonalise against earlier levels, then a
-    // Cholesky QR pass on the new block (results alternate between Qk and Ak)
+    // ---- both orthogonality passes (reorthogonalise against earlier levels,
+    // then a Cholesky QR pass on the new block): Qk -> Ak -> Qc
+    auto pass = [&](double* in, double* out, int* cnt) {
+      if (k > 0) {
+        gemm<double>(c.s, OpT, OpN, k, kl, M, 1.0, Q, kmax, 0, in, kl, 0, 0.0, C, kl, 0, 1);
+        gemm<double>(c.s, OpN, OpN, M, kl, k, -1.0, Q, kmax, 0, C, kl, 0, 1.0, in, kl, 0, 1);
+      }
+      gemm<double>(c.s, OpT, OpN, kl, kl, M, 1.0, in, kl, 0, in, kl, 0, 0.0, G, kl, 0, 1);
+      chol_skip(c.s, kl, G, R11, pmask, cnt, 1e-14);
+      trtri_upper(c.s, kl, R11, R11i);
+      gemm<double>(c.s, OpN, OpN, M, kl, kl, 1.0, in, kl, 0, R11i, kl, 0, 0.0, out, kl, 0, 1);
+    };
+    // Qk is kept for a redo; the reorthogonalisation against earlier levels
+    // works in place, so from the second level on pass 0 runs on a copy
+    if (k > 0) {
+      c.d2d(Ak, Qk, (size_t)M * kl);
+      pass(Ak, Qc, sti + 1);
+    } else {
+      pass(Qk, Qc, sti + 1);
+    }
+    pass(Qc, Ak, sti + 2);
+    const bool more = k + kl < kmax;  // columns left for a further level
+    if (more) {
+      // deflation: Work = A - Q Q^T A, ||Work||^2 (and ||A||^2 once)
+      copy2d(c.s, M, kl, Ak, kl, Q + k, kmax);
+      const int kn = k + kl;
+      gemm<double>(c.s, OpT, OpN, kn, n, M, 1.0, Q, kmax, 0, Ain, n, 0, 0.0, C, n, 0, 1);
+      c.d2d(Work, Ain, (size_t)M * n);
+      gemm<double>(c.s, OpN, OpN, M, n, kn, -1.0, Q, kmax, 0, C, n, 0, 1.0, Work, n, 0, 1);
+      dot_device(c.s, Work, Work, (long)M * n, partial, st + 1);
+      if (normA2 < 0.0) dot_device(c.s, Ain, Ain, (long)M * n, partial, st);
+    }
+    c.d2h(reinterpret_cast<unsigned char*>(&hst), reinterpret_cast<const unsigned char*>(st), sizeof(hst));
+    if (hst.cnt[1] == kl && hst.cnt[2] == kl) {
+      if (!more) {
+        copy2d(c.s, M, kl, Ak, kl, Q + k, kmax);
+        k += kl;
+        break;  // full rank: nothing left to represent
+      }
+      k += kl;
+      if (normA2 < 0.0) {
+        normA2 = hst.nrm[0];
+        T2S2_CHECK(std::isfinite(normA2), "dcholqr: non-finite input");
+      }
+      Wk = Work;
+      if (hst.nrm[1] <= drop * drop * normA2) break;
+      continue;
+    }
+    // ---- a pass lost a column: redo the passes one at a time from Qk
     double* qa = Qk;
     double* qb = Ak;
-    for (int pass = 0; pass < 2; ++pass) {
+    for (int p = 0; p < 2; ++p) {
       if (k > 0) {
         gemm<double>(c.s, OpT, OpN, k, kl, M, 1.0, Q, kmax, 0, qa, kl, 0, 0.0, C, kl, 0, 1);
         gemm<double>(c.s, OpN, OpN, M, kl, k, -1.0, Q, kmax, 0, C, kl, 0, 1.0, qa, kl, 0, 1);
       }
       gemm<double>(c.s, OpT, OpN, kl, kl, M, 1.0, qa, kl, 0, qa, kl, 0, 0.0, G, kl, 0, 1);
-      chol_skip(c.s, kl, G, R11, mask, cnt, 1e-14);
+      chol_skip(c.s, kl, G, R11, pmask, sti + 1, 1e-14);
       int k2 = 0;
-      c.d2h(&k2, cnt, 1);
+      c.d2h(&k2, sti + 1, 1);
       if (k2 < kl) {
         // a column became dependent after reorthogonalisation: keep the rest
         std::vector<int> m2(kl), id2;
-        c.d2h(m2.data(), mask, kl);
+        c.d2h(m2.data(), pmask, kl);
         for (int j = 0; j < kl; ++j)
           if (m2[j]) id2.push_back(j);
         if (id2.empty()) { kl = 0; break; }
@@ -237,7 +299,7 @@ int dcholqr(const Ctx& c, int M, int n, const double* A, long lda, double* Qout,
         gather_cols(c.s, M, (int)id2.size(), qa, kl, idx, qb, (long)id2.size());
         kl = (int)id2.size();
         std::swap(qa, qb);
-        --pass;  // redo this pass on the reduced block
+        --p;  // redo this pass on the reduced block
         continue;
       }
       trtri_upper(c.s, kl, R11, R11i);
