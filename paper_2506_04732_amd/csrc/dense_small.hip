@@ -673,12 +673,14 @@ __device__ inline bool jacobi_rotation(double a, double b, double g, double tol,
 }
 
 // Sweeps stop once no pair had a squared cosine g^2 / (a b) above kJacStop2
-// (cosine 1e-4) before its rotation: one-sided Jacobi converges
-// quadratically, so the cosines left are ~1e-8.  B = U Wt stays exact (U is a
-// product of rotations) and the error of dropping rows of Wt is their norm
-// whatever their orthogonality, so what is left only makes the kept rows
-// marginally less than optimal; a further sweep would rotate next to nothing.
-constexpr float kJacStop2 = 1e-8f;
+// (cosine 1e-2) before its rotation: cyclic one-sided Jacobi converges
+// quadratically, so the cosines left after that sweep are ~1e-4.  B = U Wt
+// stays exact (U is a product of rotations) and the error of dropping rows of
+// Wt is their Frobenius norm whatever their orthogonality, so what is left
+// only makes the kept rows marginally less than optimal (a rank at most a
+// little above the optimal one for the same error); the sweep that would
+// confirm it is not run.
+constexpr float kJacStop2 = 1e-4f;
 // g^2 / (a b) as the bits of a non-negative float (ordered like ints)
 __device__ inline int cos2_bits(double a, double b, double g) {
   const double ab = a * b;
@@ -862,6 +864,94 @@ __global__ void __launch_bounds__(kNT) jacobi_block_kernel(int k, int c, double*
   const int nrounds = cross ? MQ : RP - 1, npairs = cross ? pn : RP / 2;
   const int grp = threadIdx.x / LG, sub = threadIdx.x % LG, ngrp = blockDim.x / LG;
   const double tol = 1e-10;
+  constexpr int NJ = 8;  // Jl entries per lane of a register-resident row
+  if (cross && pn <= ngrp && rows <= NJ * LG) {
+    // group pi keeps row pi of block P and its Jl row in registers through
+    // every round; only the row of Q it meets passes through LDS (same
+    // operations in the same order as the loop below)
+    const bool own = grp < pn;
+    double xs[NR], jx[NJ];
+    if (own) {
+      const double* bp = Bw + (long)grp * c;
+      const double* jp = Jl + (long)grp * rows;
+#pragma unroll
+      for (int u = 0; u < NR; ++u) {
+        const int e = sub + u * LG;
+        xs[u] = (e < c) ? bp[e] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < NJ; ++u) {
+        const int e = sub + u * LG;
+        jx[u] = (e < rows) ? jp[e] : 0.0;
+      }
+    }
+    for (int rr = 0; rr < nrounds; ++rr) {
+      int q = own ? (grp + rr) % MQ : qn;
+      if (q < qn) {
+        q += pn;
+        double* bq = Bw + (long)q * c;
+        double ys[NR];
+        double a = 0.0, b = 0.0, g = 0.0;
+#pragma unroll
+        for (int u = 0; u < NR; ++u) {
+          const int e = sub + u * LG;
+          ys[u] = (e < c) ? bq[e] : 0.0;
+          a = fma(xs[u], xs[u], a);
+          b = fma(ys[u], ys[u], b);
+          g = fma(xs[u], ys[u], g);
+        }
+        if constexpr (LG == 16) {
+          a = row16_sum(a);
+          b = row16_sum(b);
+          g = row16_sum(g);
+        } else {
+          for (int off = LG / 2; off > 0; off >>= 1) {
+            a += __shfl_xor(a, off, LG);
+            b += __shfl_xor(b, off, LG);
+            g += __shfl_xor(g, off, LG);
+          }
+        }
+        if (sub == 0) atomicMax(&s_cmax, cos2_bits(a, b, g));
+        double cs, sn;
+        if (jacobi_rotation(a, b, g, tol, cs, sn)) {
+#pragma unroll
+          for (int u = 0; u < NR; ++u) {
+            const int e = sub + u * LG;
+            const double x = xs[u];
+            xs[u] = cs * x - sn * ys[u];
+            if (e < c) bq[e] = sn * x + cs * ys[u];
+          }
+          double* jq = Jl + (long)q * rows;
+#pragma unroll
+          for (int u = 0; u < NJ; ++u) {
+            const int e = sub + u * LG;
+            if (e < rows) {
+              const double x = jx[u], y = jq[e];
+              jx[u] = cs * x - sn * y;
+              jq[e] = sn * x + cs * y;
+            }
+          }
+          if (sub == 0) atomicAdd(&s_rot, 1);
+        }
+      }
+      __syncthreads();
+    }
+    if (own) {
+      double* bp = Bw + (long)grp * c;
+      double* jp = Jl + (long)grp * rows;
+#pragma unroll
+      for (int u = 0; u < NR; ++u) {
+        const int e = sub + u * LG;
+        if (e < c) bp[e] = xs[u];
+      }
+#pragma unroll
+      for (int u = 0; u < NJ; ++u) {
+        const int e = sub + u * LG;
+        if (e < rows) jp[e] = jx[u];
+      }
+    }
+    __syncthreads();
+  } else
   for (int rr = 0; rr < nrounds; ++rr) {
     for (int pi = grp; pi < npairs; pi += ngrp) {
       int p, q;
