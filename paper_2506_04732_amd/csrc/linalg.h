@@ -45,7 +45,7 @@ struct Ctx {
   void d2h(T* h, const T* d, size_t n) const {
     host_read(s, h, d, n * sizeof(T));
   }
-  // stream-ordered; the host buffer may be reused right after the call
+  // synchronous: the host buffer may be reused right after the call
   template <class T>
   void h2d(T* d, const T* h, size_t n) const {
     host_write(s, d, h, n * sizeof(T));

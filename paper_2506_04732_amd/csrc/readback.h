@@ -15,12 +15,10 @@ namespace t2s2 {
 // work on s are reported as Error, as a stream synchronisation would.
 void host_read(hipStream_t s, void* h, const void* d, size_t bytes);
 
-// Copy bytes from host memory h to device memory d in stream order; h may be
-// reused as soon as the call returns.  Up to kWriteArgMax bytes travel as a
-// kernel argument (no wait); larger copies wait for the stream.
+// Copy bytes from host memory h to device memory d after all earlier work
+// on stream s; returns once the copy is complete (h may be reused).
 void host_write(hipStream_t s, void* d, const void* h, size_t bytes);
 
 constexpr size_t kReadbackMax = 64 * 1024;
-constexpr size_t kWriteArgMax = 2048;
 
 }  // namespace t2s2

@@ -12,9 +12,7 @@
 // hipStreamQuery, so an error of earlier work on the stream is reported as a
 // synchronisation would report it, and a stream that completes without the
 // flag (not expected) falls back to the runtime copy.
-//
-// Host-to-device copies of at most kWriteArgMax bytes travel as a kernel
-// argument, which the runtime copies at launch, so the caller need not wait.
+
 #include "readback.h"
 
 #include <chrono>
@@ -48,14 +46,6 @@ __global__ void __launch_bounds__(256) readback_kernel(const unsigned char* __re
   __threadfence_system();
   __syncthreads();
   if (t == 0) __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-}
-
-struct WriteArg {
-  unsigned char b[kWriteArgMax];
-};
-
-__global__ void __launch_bounds__(256) write_arg_kernel(WriteArg a, unsigned char* __restrict__ dst, int bytes) {
-  for (int i = threadIdx.x; i < bytes; i += blockDim.x) dst[i] = a.b[i];
 }
 
 struct Mailbox {
@@ -159,15 +149,8 @@ void host_read(hipStream_t s, void* h, const void* d, size_t bytes) {
 
 void host_write(hipStream_t s, void* d, const void* h, size_t bytes) {
   if (bytes == 0) return;
-  if (bytes > kWriteArgMax) {
-    T2S2_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s));
-    T2S2_HIP(hipStreamSynchronize(s));
-    return;
-  }
-  WriteArg a;
-  std::memcpy(a.b, h, bytes);
-  hipLaunchKernelGGL(write_arg_kernel, dim3(1), dim3(256), 0, s, a, static_cast<unsigned char*>(d), (int)bytes);
-  T2S2_LAUNCH_CHECK();
+  T2S2_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s));
+  T2S2_HIP(hipStreamSynchronize(s));
 }
 
 }  // namespace t2s2
