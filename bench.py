@@ -226,18 +226,29 @@ def warm_leg(train: int, test: int, epochs: int, workers: int, log=True) -> dict
     ntr, nte = train, test
     t0 = time.perf_counter()
     insts = [workloads.warm_instance(10 ** 6 + i) for i in range(ntr + nte)]
-    probs = [t2s2.Problem(q.d, q.N, q.eps, q.beta, q.scheme, rank_cap=cap) for q in insts]
-    fs = [sources.gaussians(p, q.gauss.amp, q.gauss.centre, q.gauss.width)
-          for p, q in zip(probs, insts)]
-    res = []
-    for k in range(0, len(probs), 64):
-        res += t2s2.solve_batched(probs[k:k + 64], fs[k:k + 64], workers=workers, **WARM_OPTS)
+    # training instances are generated in chunks and released once their
+    # rank-8 targets are taken (each problem holds its own device buffers);
+    # the held-out problems are kept for the cold and warm solves
+    targets = []
+    probs, fs = [], []
+    for k in range(0, ntr + nte, 64):
+        chunk = insts[k:min(k + 64, ntr + nte)]
+        cp = [t2s2.Problem(q.d, q.N, q.eps, q.beta, q.scheme, rank_cap=cap) for q in chunk]
+        cf = [sources.gaussians(p, q.gauss.amp, q.gauss.centre, q.gauss.width) for p, q in zip(cp, chunk)]
+        res = t2s2.solve_batched(cp, cf, workers=workers, **WARM_OPTS)
+        targets += [warmstart.solution_target(p, r.x, r8) for p, r in zip(cp, res)]
+        for j in range(len(chunk)):
+            if k + j >= ntr:
+                probs.append(cp[j])
+                fs.append(cf[j])
+        del cp, cf, res
         if log:
-            print(f"warm7d: solved {len(res)} / {len(probs)} in {time.perf_counter() - t0:.0f} s", file=sys.stderr,
+            print(f"warm7d: solved {len(targets)} / {ntr + nte} in {time.perf_counter() - t0:.0f} s", file=sys.stderr,
                   flush=True)
     t_gen = time.perf_counter() - t0
     m = [N - 2] * d
-    T = torch.stack([warmstart.solution_target(p, r.x, r8) for p, r in zip(probs, res)])
+    T = torch.stack(targets)
+    del targets
     X = torch.from_numpy(warmstart.features([q.meta["params"] for q in insts])).cuda()
     net = warmstart.Network([X.shape[1], 256, 256, 256, warmstart.flat_size(m, r8)], seed=0)
     torch.cuda.synchronize()
@@ -253,7 +264,7 @@ def warm_leg(train: int, test: int, epochs: int, workers: int, log=True) -> dict
     base, _ = warmstart.fit_loss(T[:ntr].mean(0, keepdim=True).expand(nte, -1).contiguous(), Tte, m, r8)
     cold_s, warm_s, cold_sw, warm_sw, used, rho_w, rho_c, conv_w = [], [], [], [], [], [], [], []
     for i in range(nte):
-        p, f = probs[ntr + i], fs[ntr + i]
+        p, f = probs[i], fs[i]
         torch.cuda.synchronize()
         ta = time.perf_counter()
         rc = p.solve(f, **WARM_OPTS)
