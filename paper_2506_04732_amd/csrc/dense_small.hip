@@ -769,6 +769,9 @@ __global__ void __launch_bounds__(kNT) jacobi_rows_kernel(int k, int c, double* 
       s_cmax = 0;
     }
     __syncthreads();
+    // this group's rotation count and largest squared cosine of the sweep
+    // (one pair of shared atomics per group after the rounds, not per pair)
+    int my_rot = 0, my_cmax = 0;
     for (int round = 0; round < K - 1; ++round) {
       for (int pi = grp; pi < npairs; pi += ngrp) {
         // slots pi and K-1-pi; slot 0 is fixed, the others rotate
@@ -790,7 +793,7 @@ __global__ void __launch_bounds__(kNT) jacobi_rows_kernel(int k, int c, double* 
         a = row16_sum(a);
         b = row16_sum(b);
         g = row16_sum(g);
-        if (sub == 0) atomicMax(&s_cmax, cos2_bits(a, b, g));
+        my_cmax = max(my_cmax, cos2_bits(a, b, g));
         double cs, sn;
         if (!jacobi_rotation(a, b, g, tol, cs, sn)) continue;
         for (int e = sub; e < c; e += kJacG) {
@@ -805,10 +808,15 @@ __global__ void __launch_bounds__(kNT) jacobi_rows_kernel(int k, int c, double* 
           jp[e] = cs * x - sn * y;
           jq[e] = sn * x + cs * y;
         }
-        if (sub == 0) atomicAdd(&s_rot, 1);
+        ++my_rot;
       }
       __syncthreads();
     }
+    if (sub == 0) {
+      if (my_rot > 0) atomicAdd(&s_rot, my_rot);
+      if (my_cmax > 0) atomicMax(&s_cmax, my_cmax);
+    }
+    __syncthreads();
     const int rot = s_rot;
     const float cmax = __int_as_float(s_cmax);
     __syncthreads();
@@ -865,6 +873,9 @@ __global__ void __launch_bounds__(kNT) jacobi_block_kernel(int k, int c, double*
   const int grp = threadIdx.x / LG, sub = threadIdx.x % LG, ngrp = blockDim.x / LG;
   const double tol = 1e-10;
   constexpr int NJ = 8;  // Jl entries per lane of a register-resident row
+  // this group's rotation count and largest squared cosine (one pair of
+  // shared atomics per group after the rounds, not per pair)
+  int my_rot = 0, my_cmax = 0;
   if (cross && pn <= ngrp && rows <= NJ * LG) {
     // group pi keeps row pi of block P and its Jl row in registers through
     // every round; only the row of Q it meets passes through LDS (same
@@ -911,7 +922,7 @@ __global__ void __launch_bounds__(kNT) jacobi_block_kernel(int k, int c, double*
             g += __shfl_xor(g, off, LG);
           }
         }
-        if (sub == 0) atomicMax(&s_cmax, cos2_bits(a, b, g));
+        my_cmax = max(my_cmax, cos2_bits(a, b, g));
         double cs, sn;
         if (jacobi_rotation(a, b, g, tol, cs, sn)) {
 #pragma unroll
@@ -931,7 +942,7 @@ __global__ void __launch_bounds__(kNT) jacobi_block_kernel(int k, int c, double*
               jq[e] = sn * x + cs * y;
             }
           }
-          if (sub == 0) atomicAdd(&s_rot, 1);
+          ++my_rot;
         }
       }
       __syncthreads();
@@ -996,7 +1007,7 @@ __global__ void __launch_bounds__(kNT) jacobi_block_kernel(int k, int c, double*
           g += __shfl_xor(g, off, LG);
         }
       }
-      if (sub == 0) atomicMax(&s_cmax, cos2_bits(a, b, g));
+      my_cmax = max(my_cmax, cos2_bits(a, b, g));
       double cs, sn;
       if (!jacobi_rotation(a, b, g, tol, cs, sn)) continue;
 #pragma unroll
@@ -1014,9 +1025,13 @@ __global__ void __launch_bounds__(kNT) jacobi_block_kernel(int k, int c, double*
         jp[e] = cs * x - sn * y;
         jq[e] = sn * x + cs * y;
       }
-      if (sub == 0) atomicAdd(&s_rot, 1);
+      ++my_rot;
     }
     __syncthreads();
+  }
+  if (sub == 0) {
+    if (my_rot > 0) atomicAdd(&s_rot, my_rot);
+    if (my_cmax > 0) atomicMax(&s_cmax, my_cmax);
   }
   for (long e = threadIdx.x; e < (long)rows * c; e += blockDim.x) {
     const int r = (int)(e / c), col = (int)(e % c);
