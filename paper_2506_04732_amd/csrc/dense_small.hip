@@ -154,6 +154,9 @@ template <int NMAX>
 __global__ void __launch_bounds__(64) chol_skip_reg_kernel(int n, const double* __restrict__ G, double* R,
                                                           int* __restrict__ mask, int* __restrict__ count,
                                                           double tau) {
+  // row k of the matrix is broadcast through the wavefront's LDS row (one
+  // write per lane, then same-address reads) rather than by lane reads
+  __shared__ double row[64];
   const int j = threadIdx.x;
   double g[NMAX];
 #pragma unroll
@@ -164,7 +167,10 @@ __global__ void __launch_bounds__(64) chol_skip_reg_kernel(int n, const double* 
 #pragma unroll
   for (int k = 0; k < NMAX; ++k) {
     if (k < n) {
-      const double d = rdl(g[k], k);
+      __builtin_amdgcn_wave_barrier();
+      row[j] = g[k];
+      __builtin_amdgcn_wave_barrier();
+      const double d = row[k];
       const int keep = (d > tau * gmax) && (d > 0.0) && gmax > 0.0;
       if (j == 0) mask[k] = keep;
       cnt += keep;
@@ -178,7 +184,7 @@ __global__ void __launch_bounds__(64) chol_skip_reg_kernel(int n, const double* 
 #pragma unroll
         for (int i = k + 1; i < NMAX; ++i) {
           if (i < n) {
-            const double rki = rdl(g[k], i);
+            const double rki = row[i] * inv;
             if (j >= i && j < n) g[i] -= rki * g[k];
           }
         }
@@ -356,22 +362,23 @@ __global__ void __launch_bounds__(kCholNT) chol_blk_kernel(int n, const double* 
 template <int NMAX>
 __global__ void __launch_bounds__(64) trtri_reg_kernel(int n, const double* __restrict__ R,
                                                       double* __restrict__ Rinv) {
+  // R is staged in LDS; row i's entries are same-address reads for every lane
+  __shared__ double Rs[NMAX * NMAX];
   const int j = threadIdx.x;
-  double r[NMAX], x[NMAX];
+  double x[NMAX];
+  for (int e = j; e < n * n; e += 64) Rs[(e / n) * NMAX + e % n] = R[e];
 #pragma unroll
-  for (int i = 0; i < NMAX; ++i) {
-    r[i] = (i < n && j < n) ? R[i * n + j] : 0.0;
-    x[i] = 0.0;
-  }
+  for (int i = 0; i < NMAX; ++i) x[i] = 0.0;
+  __syncthreads();
 #pragma unroll
   for (int i = NMAX - 1; i >= 0; --i) {
     if (i < n) {
-      const double rii = rdl(r[i], i);
+      const double rii = Rs[i * NMAX + i];
       double p[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int t = i + 1; t < NMAX; ++t) {
         if (t < n) {
-          const double rit = rdl(r[i], t);
+          const double rit = Rs[i * NMAX + t];
           if (t <= j) p[(t - i - 1) & 7] = fma(rit, x[t], p[(t - i - 1) & 7]);
         }
       }
