@@ -5,16 +5,21 @@
 // back some fifteen hundred times per 6D solve.  A pageable hipMemcpyAsync +
 // hipStreamSynchronize costs ~22 us per read on MI355X (staging copy, then the
 // runtime's completion wait); here a one-block kernel copies the data into a
-// pinned, coherent, mapped host mailbox and then publishes a sequence number
-// with a system-scope release, and the host spins on that number (~9 us per
-// read).  Every host thread owns one mailbox (taken from a process-wide pool,
-// returned when the thread ends, never freed).  While it waits the host polls
-// hipStreamQuery, so an error of earlier work on the stream is reported as a
-// synchronisation would report it, and a stream that completes without the
-// flag (not expected) falls back to the runtime copy.
+// pinned, coherent, mapped host mailbox and the host spins on it (~9 us per
+// read).  Every 4-byte word of the data travels in one aligned 8-byte store
+// together with the read's 32-bit sequence number, and the host accepts the
+// data once every word carries the current number: stores of different
+// threads may reach host memory in any order, so no separate "ready" flag is
+// trusted to follow the data.  Every host thread owns one mailbox (taken from
+// a process-wide pool, returned when the thread ends, never freed).  While it
+// waits the host polls hipStreamQuery, so an error of earlier work on the
+// stream is reported as a synchronisation would report it, and a stream that
+// completes before every word is seen (not expected) falls back to the
+// runtime copy.
 
 #include "readback.h"
 
+#include <algorithm>
 #include <chrono>
 #include <cstdint>
 #include <cstring>
@@ -26,34 +31,30 @@ namespace t2s2 {
 
 namespace {
 
+// word i of the data (4 bytes, zero-padded at the end) -> dst[i] = seq << 32 | word
 __global__ void __launch_bounds__(256) readback_kernel(const unsigned char* __restrict__ src, size_t bytes,
-                                                       unsigned char* __restrict__ dst, unsigned* flag,
-                                                       unsigned seq) {
-  const size_t t = threadIdx.x;
-  const uintptr_t align = (uintptr_t)src | (uintptr_t)dst | (uintptr_t)bytes;
-  if ((align & 7) == 0) {
-    const unsigned long long* s8 = reinterpret_cast<const unsigned long long*>(src);
-    unsigned long long* d8 = reinterpret_cast<unsigned long long*>(dst);
-    for (size_t i = t; i < bytes / 8; i += blockDim.x) d8[i] = s8[i];
-  } else if ((align & 3) == 0) {
-    const unsigned* s4 = reinterpret_cast<const unsigned*>(src);
-    unsigned* d4 = reinterpret_cast<unsigned*>(dst);
-    for (size_t i = t; i < bytes / 4; i += blockDim.x) d4[i] = s4[i];
-  } else {
-    for (size_t i = t; i < bytes; i += blockDim.x) dst[i] = src[i];
+                                                       unsigned long long* __restrict__ dst, unsigned seq) {
+  const size_t nw = (bytes + 3) / 4;
+  const bool aligned = ((uintptr_t)src & 3) == 0;
+  for (size_t i = threadIdx.x; i < nw; i += blockDim.x) {
+    unsigned w = 0;
+    if (aligned && 4 * i + 4 <= bytes) {
+      w = reinterpret_cast<const unsigned*>(src)[i];
+    } else {
+      for (int b = 0; b < 4; ++b)
+        if (4 * i + b < bytes) w |= (unsigned)src[4 * i + b] << (8 * b);
+    }
+    const unsigned long long v = ((unsigned long long)seq << 32) | w;
+    __hip_atomic_store(dst + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }
-  // every thread's stores reach host memory before the flag does
-  __threadfence_system();
-  __syncthreads();
-  if (t == 0) __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
+constexpr size_t kMailWords = kReadbackMax / 4;  // tagged 8-byte words
+
 struct Mailbox {
-  unsigned char* host = nullptr;  // kReadbackMax bytes, then the flag
-  unsigned char* dev = nullptr;   // the same memory as the device sees it
+  unsigned long long* host = nullptr;  // kMailWords words
+  unsigned long long* dev = nullptr;   // the same memory as the device sees it
   unsigned seq = 0;
-  unsigned* hflag() const { return reinterpret_cast<unsigned*>(host + kReadbackMax); }
-  unsigned* dflag() const { return reinterpret_cast<unsigned*>(dev + kReadbackMax); }
 };
 
 std::mutex g_pool_m;
@@ -83,8 +84,8 @@ Mailbox* my_mailbox() {
     }
   }
   void* p = nullptr;
-  if (hipHostMalloc(&p, kReadbackMax + 64, hipHostMallocMapped | hipHostMallocPortable | hipHostMallocCoherent) !=
-      hipSuccess) {
+  const size_t mbytes = kMailWords * sizeof(unsigned long long);
+  if (hipHostMalloc(&p, mbytes, hipHostMallocMapped | hipHostMallocPortable | hipHostMallocCoherent) != hipSuccess) {
     (void)hipGetLastError();
     h.failed = true;
     return nullptr;
@@ -97,9 +98,9 @@ Mailbox* my_mailbox() {
     return nullptr;
   }
   auto* mb = new Mailbox;
-  mb->host = static_cast<unsigned char*>(p);
-  mb->dev = static_cast<unsigned char*>(dp);
-  std::memset(mb->host, 0, kReadbackMax + 64);
+  mb->host = static_cast<unsigned long long*>(p);
+  mb->dev = static_cast<unsigned long long*>(dp);
+  std::memset(mb->host, 0, mbytes);
   h.mb = mb;
   return mb;
 }
@@ -109,11 +110,23 @@ void runtime_read(hipStream_t s, void* h, const void* d, size_t bytes) {
   T2S2_HIP(hipStreamSynchronize(s));
 }
 
-// true once the flag shows seq; false if the stream completed without it
-bool wait_flag(hipStream_t s, const unsigned* flag, unsigned seq) {
+// words [0, nw) whose tag is not yet seq are counted from *from on; true
+// once every word carries seq (the data is then whole), false if the stream
+// completed first
+bool all_tagged(const unsigned long long* w, size_t nw, unsigned seq, size_t& from) {
+  while (from < nw) {
+    const unsigned long long v = __atomic_load_n(w + from, __ATOMIC_ACQUIRE);
+    if ((unsigned)(v >> 32) != seq) return false;
+    ++from;
+  }
+  return true;
+}
+
+bool wait_tagged(hipStream_t s, const unsigned long long* w, size_t nw, unsigned seq) {
   const auto t0 = std::chrono::steady_clock::now();
+  size_t from = 0;
   for (unsigned long it = 1;; ++it) {
-    if (__atomic_load_n(flag, __ATOMIC_ACQUIRE) == seq) return true;
+    if (all_tagged(w, nw, seq, from)) return true;
     if ((it & 255) != 0) {
       __builtin_ia32_pause();
       continue;
@@ -121,7 +134,7 @@ bool wait_flag(hipStream_t s, const unsigned* flag, unsigned seq) {
     const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
     if (us < 20.0) continue;
     const hipError_t q = hipStreamQuery(s);
-    if (q == hipSuccess) return __atomic_load_n(flag, __ATOMIC_ACQUIRE) == seq;
+    if (q == hipSuccess) return all_tagged(w, nw, seq, from);
     if (q != hipErrorNotReady) T2S2_HIP(q);
     if (us > 100.0) std::this_thread::yield();
   }
@@ -136,15 +149,22 @@ void host_read(hipStream_t s, void* h, const void* d, size_t bytes) {
     runtime_read(s, h, d, bytes);
     return;
   }
-  const unsigned seq = ++mb->seq;
+  unsigned seq = ++mb->seq;
+  if (seq == 0) seq = ++mb->seq;  // 0 is the tag of a fresh mailbox
+  const size_t nw = (bytes + 3) / 4;
   hipLaunchKernelGGL(readback_kernel, dim3(1), dim3(256), 0, s, static_cast<const unsigned char*>(d), bytes, mb->dev,
-                     mb->dflag(), seq);
+                     seq);
   T2S2_LAUNCH_CHECK();
-  if (!wait_flag(s, mb->hflag(), seq)) {
+  if (!wait_tagged(s, mb->host, nw, seq)) {
     runtime_read(s, h, d, bytes);
     return;
   }
-  std::memcpy(h, mb->host, bytes);
+  unsigned char* out = static_cast<unsigned char*>(h);
+  for (size_t i = 0; i < nw; ++i) {
+    const unsigned w = (unsigned)(mb->host[i] & 0xffffffffULL);
+    const size_t nb = std::min<size_t>(4, bytes - 4 * i);
+    std::memcpy(out + 4 * i, &w, nb);
+  }
 }
 
 void host_write(hipStream_t s, void* d, const void* h, size_t bytes) {
