@@ -551,6 +551,14 @@ int t2s2_debug_gemm(int variant, int opA, int opB, int M, int N, int K, int batc
                     double* C, long long ldc, long long sC, void* stream);
 const char* t2s2_gemm_tune_source(void);
 
+/* Copy `bytes` bytes from device memory `dev` to host memory `host` after all
+ * earlier work on `stream`, through the library's read-back path (the path
+ * that returns pivot counts, ranks, flags and norms to the host during a
+ * solve: a pinned mailbox for up to 64 KiB, the runtime's copy beyond).
+ * Synchronous; no alignment required; EINVAL for NULL pointers or a negative
+ * size.  For tests. */
+int t2s2_debug_readback(const void* dev, void* host, long long bytes, void* stream);
+
 /* Iteration limits of the dense factorisations, process-wide (0 restores a
  * default: 40 n + 100 Francis double-shift steps for an n x n matrix, 60
  * one-sided Jacobi sweeps).  For tests of the error path: with a lowered

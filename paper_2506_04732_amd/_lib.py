@@ -23,7 +23,7 @@ EXPORTED = [
     "t2s2_tt_fit_loss", "t2s2_tt_pack", "t2s2_tt_unpack", "t2s2_source_gaussians", "t2s2_source_manufactured",
     "t2s2_debug_iteration_limits", "t2s2_tt_matvec_noalloc", "t2s2_problem_create_reaction",
     "t2s2_mol_create", "t2s2_mol_step", "t2s2_tt_fiber", "t2s2_problem_create_general", "t2s2_source_cross",
-    "t2s2_debug_gemm", "t2s2_gemm_tune_source",
+    "t2s2_debug_gemm", "t2s2_gemm_tune_source", "t2s2_debug_readback",
 ]
 TIMING_CLASSES = ["gemm_f64", "gemm_c128", "ttm_matvec", "schur_qr", "hessenberg", "jacobi_svd", "cholesky",
                   "trtri", "trevec", "kron_trisolve", "hess_solve", "other"]
@@ -111,6 +111,7 @@ def lib() -> C.CDLL:
                                   ll, vp, ll, ll, C.c_double, vp, ll, ll, vp]
     L.t2s2_gemm_tune_source.argtypes = []
     L.t2s2_gemm_tune_source.restype = C.c_char_p
+    L.t2s2_debug_readback.argtypes = [vp, vp, ll, vp]
     fp, u64 = C.POINTER(C.c_float), C.c_ulonglong
     L.t2s2_mlp_create.argtypes = [C.c_int, ip, u64, C.POINTER(vp)]
     L.t2s2_mlp_destroy.argtypes = [vp]

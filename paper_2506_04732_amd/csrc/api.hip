@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "cross.h"
+#include "readback.h"
 #include "mlp.h"
 #include "solver.h"
 #include "sources.h"
@@ -473,6 +474,14 @@ int t2s2_debug_gemm(int variant, int opA, int opB, int M, int N, int K, int batc
 }
 
 const char* t2s2_gemm_tune_source(void) { return t2s2::gemm_tune_source(); }
+
+int t2s2_debug_readback(const void* dev, void* host, long long bytes, void* stream) {
+  return guarded([&] {
+    T2S2_CHECK(bytes >= 0 && (bytes == 0 || (dev && host)), "t2s2_debug_readback: NULL pointer or negative size");
+    t2s2::host_read(static_cast<hipStream_t>(stream), host, dev, (size_t)bytes);
+    return T2S2_OK;
+  });
+}
 
 int t2s2_debug_iteration_limits(int francis_steps, int jacobi_sweeps) {
   return guarded([&] {
