@@ -252,7 +252,11 @@ __global__ void __launch_bounds__(kFqThreads) francis_ms_kernel(int n, const R* 
   const R ulp = sizeof(R) == 8 ? (R)1e-13 : (R)FLT_EPSILON;
   int total = 0, its = 0;
   while (true) {
-    // ---- deflation: largest l <= hi with a negligible subdiagonal
+    // ---- deflation: largest l <= hi with a negligible subdiagonal.  Every
+    // thread has read the previous iteration's s_l before thread 0 resets it
+    // (a wave released late from the last barrier would otherwise read the
+    // reset value and take the other branch)
+    __syncthreads();
     if (threadIdx.x == 0) s_l = 0;
     __syncthreads();
     int hi = s_hi;
