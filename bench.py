@@ -47,7 +47,10 @@ def roofline_entry(name: str, st: dict, traffic=None) -> dict:
                 "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "launches": st["launches"],
                 "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": per_launch_bytes}
     achieved = per_launch_flops / avg_s / 1e12 if avg_s > 0 else 0.0
-    return {"kernel": name, "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+    # the real FP64 GEMM runs on the matrix cores (V_MFMA_F64_16X16X4_F64);
+    # the other classes on the vector ALUs
+    bound = "mfma" if name == "gemm_f64" else "alu"
+    return {"kernel": name, "bound": bound, "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic, "launches": st["launches"],
             "avg_launch_us": avg_s * 1e6, "algorithmic_flops_per_launch": per_launch_flops}
 
@@ -96,10 +99,13 @@ def _cpu_model() -> str:
     return "unknown"
 
 
-def _oracle_solve(prob, threads):
-    """The oracle's full solve of the bench workload (FP64 NumPy AMEn with
-    exact Kronecker local solves), stopped by the GPU solve's rule (FP64
-    residual <= target): (seconds, info, BLAS threads used)."""
+def _oracle_solve(prob, threads, opts=None, cap=None):
+    """The oracle's full solve of one instance (FP64 NumPy AMEn with exact
+    Kronecker local solves), stopped by the GPU solve's rule (FP64 residual
+    <= target): (seconds, info, BLAS threads used).  opts / cap: the solve
+    options and rank cap (default: the 6D bench workload's)."""
+    opts = SOLVE_OPTS if opts is None else opts
+    cap = RANK_CAP if cap is None else cap
     import numpy as np
     from threadpoolctl import threadpool_info, threadpool_limits
     from oracle import amen as oamen
@@ -109,17 +115,17 @@ def _oracle_solve(prob, threads):
     Es, Ms = col.interior_factors(ops)
     A = ott.kron_sum_ttm(Es, Ms)
     b = ott.separable_to_tt(col.gauss_rhs_factors(ops, prob.gauss.amp, prob.gauss.centre, prob.gauss.width))
-    rng = np.random.default_rng(SOLVE_OPTS["seed"])
-    r0 = SOLVE_OPTS["init_rank"]
+    rng = np.random.default_rng(opts["seed"])
+    r0 = opts["init_rank"]
     ms = [n - 2 for n in prob.N]
     rs = [1] + [min(r0, 30 ** min(l, prob.d - l)) for l in range(1, prob.d)] + [1]
     x0 = [rng.standard_normal((rs[l], ms[l], rs[l + 1])) for l in range(prob.d)]
     with threadpool_limits(limits=threads):
         used = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
         t0 = time.perf_counter()
-        _, info = oamen.solve(A, b, x0=x0, tol=SOLVE_OPTS["tol"], target=SOLVE_OPTS["target"], max_sweeps=40,
-                              kick=SOLVE_OPTS["kick"], rank_cap=RANK_CAP, local_solver="kron",
-                              kron_factors=(Es, Ms), stop_on_residual=True)
+        _, info = oamen.solve(A, b, x0=x0, tol=opts["tol"], target=opts["target"],
+                              max_sweeps=opts.get("max_sweeps", 40), kick=opts["kick"], rank_cap=cap,
+                              local_solver="kron", kron_factors=(Es, Ms), stop_on_residual=True)
         t = time.perf_counter() - t0
     return t, info, int(used)
 
@@ -189,6 +195,37 @@ def bench_batched(args, rank: int):
         torch.cuda.synchronize()
         seq = time.perf_counter() - t1
     conv = sum(r.converged for r in res)
+    # outside the timed region: the first 64 instances again on one stream
+    # with every kernel class event-timed, for the dominant class's roofline
+    # (with 16 streams in flight an event pair would also time the waits
+    # behind other streams' kernels)
+    t2s2.timing_classes(None)
+    t2s2.timing_enable(True)
+    t2s2.solve_batched(probs[:64], fs[:64], outs=outs[:64], workers=1, **BATCH_OPTS)
+    torch.cuda.synchronize()
+    full = t2s2.timing_read()
+    t2s2.timing_enable(False)
+    dominant = max(full, key=lambda k: full[k]["ms"])
+    roof = roofline_entry(dominant, full[dominant])
+    roof["sample"] = "the first 64 instances on one stream, every kernel class event-timed"
+    cpu = None
+    if not args.no_cpu_baseline and rank == 0:
+        # the oracle on a bounded sample: the first instances in order until
+        # ~30 s of host time, the mean scaled to the whole batch
+        times, used, last = [], 1, None
+        for q in insts[:8]:
+            t, info, used = _oracle_solve(q, None, opts=BATCH_OPTS, cap=cap)
+            times.append(t)
+            last = info
+            print(f"cpu baseline: oracle instance {len(times) - 1}: {t:.1f} s, {info['sweeps']} sweeps",
+                  file=sys.stderr, flush=True)
+            if sum(times) >= 30.0:
+                break
+        n = len(times)
+        cpu = {"value": sum(times) / n * len(insts), "unit": "s", "cores": used, "kind": "oracle",
+               "sample": f"the first {n} of {len(insts)} instances solved by the oracle (mean "
+                         f"{sum(times) / n:.1f} s each, same options and rank cap), scaled to {len(insts)}",
+               "sample_times_s": times, "cpu_model": _cpu_model(), "logical_cpus": os.cpu_count()}
     out = {
         "metric": "batched TT solves: seconds for 256 uneven instances to rel. resid 1e-8",
         "value": sec, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -202,7 +239,9 @@ def bench_batched(args, rank: int):
         "max_rank_p50": float(np.median([max(r.ranks) for r in res])),
         "sequential_s": seq,
         "speedup_vs_sequential": (seq / sec) if seq else None,
-        "roofline": None, "cpu_baseline": None,
+        "kernels": {k: {"ms_64_instances": v["ms"], "launches": v["launches"]} for k, v in full.items()
+                    if v["launches"]},
+        "roofline": roof, "cpu_baseline": cpu,
     }
     if rank == 0:
         print(json.dumps(out), flush=True)

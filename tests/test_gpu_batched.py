@@ -92,3 +92,32 @@ def test_batched_rejects_shared_problem_and_empty_batch():
     with pytest.raises(t2s2.T2S2Error):
         t2s2.solve_batched([p, p], [f, f], workers=2)
     assert t2s2.solve_batched([], []) == []
+
+
+def test_batched_workload_bitwise_equals_sequential_with_16_in_flight():
+    """64 instances of the batched workload, 16 concurrent streams: each result
+    is bitwise the sequential solve's.  Concurrent solves put other
+    workgroups on the same SIMDs, so a kernel whose waves race on shared
+    state (a wave released late from a barrier) shows up here as an
+    instance whose sweeps or ranks differ."""
+    insts = workloads.batched_instances(64)
+    cap = insts[0].rank_cap
+    opts = dict(tol=insts[0].tol, target=insts[0].target_residual, max_sweeps=30, kick=8, init_rank=8,
+                check_every=0, seed=0, overlap=False)
+    _say("batched workload, 64 instances: sequential then 16 in flight")
+    pf = [_gpu(q, cap) for q in insts]
+    seq = []
+    for p, f in pf:
+        r = p.solve(f, out=TT.empty(p.m, cap), **opts)
+        seq.append((r.residual, r.sweeps, list(r.ranks), [c.copy() for c in r.x.to_numpy()]))
+    pf2 = [_gpu(q, cap) for q in insts]
+    res = t2s2.solve_batched([p for p, _ in pf2], [f for _, f in pf2],
+                             outs=[TT.empty(p.m, cap) for p, _ in pf2], workers=16, **opts)
+    differ = []
+    for i, (s, b) in enumerate(zip(seq, res)):
+        same = (s[0] == b.residual and s[1] == b.sweeps and s[2] == list(b.ranks)
+                and all(np.array_equal(x, y) for x, y in zip(s[3], b.x.to_numpy())))
+        if not same:
+            differ.append((i, s[0], b.residual, s[1], b.sweeps))
+    _say("instances that differ:", differ)
+    assert not differ
