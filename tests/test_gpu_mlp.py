@@ -206,3 +206,6 @@ def test_learned_warm_start_end_to_end_reduced():
     _say(f"held-out: warm-start residual {np.round(rho0, 3).tolist()}, used {used}, sweeps cold {cold_sw} "
          f"warm {warm_sw}")
     assert sum(used) >= nte // 2
+    # at this reduced shape a start saves at most a sweep (cold solves take
+    # 4-7); the learned starts must not cost sweeps over the held-out set
+    assert sum(warm_sw) <= sum(cold_sw)
