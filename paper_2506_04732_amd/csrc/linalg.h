@@ -14,7 +14,13 @@
 
 namespace t2s2 {
 
-// Named device buffers, grown on demand, released on destruction.
+// Named device buffers, grown on demand, released on destruction.  The
+// block a buffer outgrows is retired, not freed at once: hipFree waits for
+// all work on the device, which in the middle of a solve would stall the
+// host behind the side streams' eigendecompositions (and, in a batched
+// solve, behind every other instance's queue).  release_retired() frees the
+// retired blocks; a retired block stays valid until then, so work already
+// queued on it completes as before.
 class Scratch {
  public:
   ~Scratch();
@@ -24,6 +30,9 @@ class Scratch {
     return static_cast<T*>(raw(name, count * sizeof(T) + 64));
   }
   size_t bytes() const;
+  // frees the retired blocks (each hipFree first waits for the device)
+  void release_retired();
+  bool has_retired() const { return !retired_.empty(); }
 
  private:
   struct Buf {
@@ -31,6 +40,7 @@ class Scratch {
     size_t bytes = 0;
   };
   std::map<std::string, Buf> bufs_;
+  std::vector<void*> retired_;
 };
 
 struct Ctx {

@@ -76,14 +76,20 @@ bool read_fail(const Ctx& c) {
 }
 
 Scratch::~Scratch() {
+  release_retired();
   for (auto& kv : bufs_)
     if (kv.second.p) (void)hipFree(kv.second.p);
+}
+
+void Scratch::release_retired() {
+  for (void* p : retired_) (void)hipFree(p);
+  retired_.clear();
 }
 
 void* Scratch::raw(const std::string& name, size_t bytes) {
   Buf& b = bufs_[name];
   if (b.bytes >= bytes && b.p) return b.p;
-  if (b.p) T2S2_HIP(hipFree(b.p));
+  if (b.p) retired_.push_back(b.p);
   b.p = nullptr;
   b.bytes = 0;
   // grow geometrically to limit reallocations

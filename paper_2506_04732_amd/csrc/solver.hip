@@ -1589,11 +1589,39 @@ int mol_step(Problem& p, const Ctx& c, const DTT& u, const DTT* b, const SolveOp
   return solve(p, c, f, &u, o, x, rep);
 }
 
+// Frees the blocks that scratch buffers outgrew (Scratch::release_retired)
+// when that cannot stall the host behind queued work: before a solve queues
+// anything, and after it if no side stream still runs its eigendecompositions
+// (otherwise at the next solve, or when the problem is destroyed).
+static void release_scratch(Problem& p, bool only_if_sides_idle) {
+  bool any = p.sc.has_retired();
+  for (int k = 0; k < Problem::kSides; ++k) any = any || p.sc_side[k].has_retired();
+  if (!any) return;
+  if (only_if_sides_idle)
+    for (int k = 0; k < Problem::kSides; ++k) {
+      if (!p.side[k]) continue;
+      const hipError_t q = hipStreamQuery(p.side[k]);
+      if (q == hipErrorNotReady) {
+        (void)hipGetLastError();  // not an error: the side stream is busy
+        return;
+      }
+      T2S2_HIP(q);
+    }
+  p.sc.release_retired();
+  for (int k = 0; k < Problem::kSides; ++k) p.sc_side[k].release_retired();
+}
+
 int solve(Problem& p, const Ctx& c0, const DTT& f, const DTT* x0, const SolveOptions& o, DTT& x, SolveReport& rep) {
   Ctx c = c0;
+  release_scratch(p, false);
   c.fail = c.sc->get<int>("ctx.fail", 1);
-  Amen a(p, c, o);
-  return a.run(f, x0, x, rep);
+  int st;
+  {
+    Amen a(p, c, o);
+    st = a.run(f, x0, x, rep);
+  }
+  release_scratch(p, true);
+  return st;
 }
 
 }  // namespace t2s2
