@@ -134,3 +134,30 @@ def test_warm_start_from_solution_converges_in_one_sweep():
     x0 = TT.from_numpy(r1.x.to_numpy())
     r2 = p.solve(f, x0=x0, tol=1e-12, target=1e-11, max_sweeps=20)
     assert r2.converged and r2.sweeps <= 2
+
+
+def test_first_solve_on_fresh_problem_equals_later_solves():
+    """Scratch buffers grow during the first solve on a problem; the blocks
+    they outgrow are kept until the solve ends (side streams idle) or the
+    next solve starts.  Three solves on one problem and one on a fresh
+    problem (created after the first is destroyed, so it reuses freed
+    memory) return bitwise the same TT, with overlap on and off."""
+    prob = workloads.gauss_problem(5, 16, 3e-3, 3, seed=7, tol=1e-10, rank_cap=96)
+    for overlap in (True, False):
+        _say(prob.name, "overlap" if overlap else "single stream")
+        opts = dict(tol=1e-10, target=1e-9, max_sweeps=30, kick=8, overlap=overlap)
+        keys = []
+        p = _gpu_problem(prob)
+        f = _gpu_source(p, prob)
+        for _ in range(3):
+            r = p.solve(f, **opts)
+            keys.append((r.residual, r.sweeps, list(r.ranks), [c.copy() for c in r.x.to_numpy()]))
+        del p, f, r
+        p = _gpu_problem(prob)
+        f = _gpu_source(p, prob)
+        r = p.solve(f, **opts)
+        keys.append((r.residual, r.sweeps, list(r.ranks), [c.copy() for c in r.x.to_numpy()]))
+        _say(f"residual {keys[0][0]:.3e}, sweeps {keys[0][1]}, ranks {keys[0][2]}, converged {r.converged}")
+        for k in keys[1:]:
+            assert k[:3] == keys[0][:3]
+            assert all(np.array_equal(a, b) for a, b in zip(k[3], keys[0][3]))
