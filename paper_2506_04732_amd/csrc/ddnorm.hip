@@ -19,6 +19,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "linalg.h"
 
@@ -60,21 +61,26 @@ __device__ inline dd dd_mul_d(double a, dd b) {
   return quick_two_sum(p, e);
 }
 
-__device__ inline dd load_dd(const dd* p, long i) { return p[i]; }
-__device__ inline dd load_dd(const double* p, long i) { return {p[i], 0.0}; }
-
 constexpr int TB = 64, TK = 16, NTH = 256;
 
+// a (FP64) times b (double-double), whichever operand of the GEMM is FP64
+__device__ inline dd dd_prod(double a, dd b) { return dd_mul_d(a, b); }
+__device__ inline dd dd_prod(dd a, double b) { return dd_mul_d(b, a); }
+
 // C (M x N, double-double, row-major ld N) = op(A) (M x K) B (K x N), one of
-// A, B FP64 and the other double-double.  op(A) = A (ld lda) or, with transA,
-// A stored K x M (ld lda).  kchunk > 0: split-K partial products, slab z of
-// C at C + z * M * N covers K range [z kchunk, (z + 1) kchunk).
+// A, B FP64 and the other double-double (the tiles are staged in their own
+// type, so the FP64 operand's product is exact by construction).  op(A) = A
+// (ld lda) or, with transA, A stored K x M (ld lda).  kchunk > 0: split-K
+// partial products, slab z of C at C + z * M * N covers K range
+// [z kchunk, (z + 1) kchunk).
 template <class TA, class TBt>
 __global__ void __launch_bounds__(NTH) dd_gemm_kernel(int transA, int M, int N, int K, const TA* __restrict__ A,
                                                       long lda, const TBt* __restrict__ B, long ldb,
                                                       dd* __restrict__ C, int kchunk) {
-  __shared__ dd As[TK][TB + 1];
-  __shared__ dd Bs[TK][TB + 1];
+  static_assert(std::is_same<TA, double>::value != std::is_same<TBt, double>::value,
+                "one operand FP64, the other double-double");
+  __shared__ TA As[TK][TB + 1];
+  __shared__ TBt Bs[TK][TB + 1];
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
   const int m0 = blockIdx.y * TB, n0 = blockIdx.x * TB;
   int kbeg = 0, kend = K;
@@ -95,8 +101,8 @@ __global__ void __launch_bounds__(NTH) dd_gemm_kernel(int transA, int M, int N, 
       int i, k;
       if (!transA) { i = e / TK; k = e % TK; } else { k = e / TB; i = e % TB; }
       const int gi = m0 + i, gk = k0 + k;
-      dd v = {0.0, 0.0};
-      if (gi < M && gk < kend) v = transA ? load_dd(A, (long)gk * lda + gi) : load_dd(A, (long)gi * lda + gk);
+      TA v{};
+      if (gi < M && gk < kend) v = transA ? A[(long)gk * lda + gi] : A[(long)gi * lda + gk];
       As[k][i] = v;
     }
 #pragma unroll
@@ -104,14 +110,15 @@ __global__ void __launch_bounds__(NTH) dd_gemm_kernel(int transA, int M, int N, 
       const int e = tid + NTH * s;
       const int k = e / TB, j = e % TB;
       const int gj = n0 + j, gk = k0 + k;
-      dd v = {0.0, 0.0};
-      if (gj < N && gk < kend) v = load_dd(B, (long)gk * ldb + gj);
+      TBt v{};
+      if (gj < N && gk < kend) v = B[(long)gk * ldb + gj];
       Bs[k][j] = v;
     }
     __syncthreads();
 #pragma unroll 4
     for (int k = 0; k < TK; ++k) {
-      dd a[4], b[4];
+      TA a[4];
+      TBt b[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) a[i] = As[k][ty + 16 * i];
 #pragma unroll
@@ -119,11 +126,7 @@ __global__ void __launch_bounds__(NTH) dd_gemm_kernel(int transA, int M, int N, 
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          // one factor is always an FP64 value (lo == 0): exact product
-          const dd p = (a[i].lo == 0.0) ? dd_mul_d(a[i].hi, b[j]) : dd_mul_d(b[j].hi, a[i]);
-          acc[i][j] = dd_add(acc[i][j], p);
-        }
+        for (int j = 0; j < 4; ++j) acc[i][j] = dd_add(acc[i][j], dd_prod(a[i], b[j]));
     }
     __syncthreads();
   }
