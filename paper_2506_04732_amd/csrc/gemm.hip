@@ -181,24 +181,19 @@ gemm_kernel(int opA, int opB, int M, int N, int K, T alpha,
   }
 }
 
-// FP64 on the matrix cores: the same 64 x 64 tile and register-prefetched K
-// staging as gemm_kernel (with a deeper K tile), each of the 4 wavefronts computing a 32 x 32 quarter as 2 x 2
+// FP64 on the matrix cores: the same 64 x 64 tile and K staging as
+// gemm_kernel, each of the 4 wavefronts computing a 32 x 32 quarter as 2 x 2
 // blocks of V_MFMA_F64_16X16X4_F64 (lane l holds A[l % 16][k0 + l / 16] and
 // B[k0 + l / 16][l % 16]; output element (l / 16 + 4 i, l % 16) in slot i).
 typedef double dbl4 __attribute__((ext_vector_type(4)));
-// K tile of the matrix-core kernel: twice the vector-ALU kernel's, so a
-// small-K product (most of the solver's) takes half the K-loop iterations,
-// each of which waits for its tile's global loads; the products are the
-// same MFMA sequence in increasing k, so the results do not change.
-constexpr int BKM = 32;
 
 __global__ void __launch_bounds__(NT)
 gemm_mfma_f64_kernel(int opA, int opB, int M, int N, int K, double alpha,
                      const double* __restrict__ A, long lda, long sA,
                      const double* __restrict__ B, long ldb, long sB,
                      double beta, double* __restrict__ C, long ldc, long sC, int kchunk) {
-  __shared__ double As[BKM][BM + 1];
-  __shared__ double Bs[BKM][BN + 1];
+  __shared__ double As[BK][BM + 1];
+  __shared__ double Bs[BK][BN + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
@@ -217,7 +212,7 @@ gemm_mfma_f64_kernel(int opA, int opB, int M, int N, int K, double alpha,
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
-  constexpr int SA = (BM * BKM) / NT, SB = (BN * BKM) / NT;
+  constexpr int SA = (BM * BK) / NT, SB = (BN * BK) / NT;
   const bool ta = (opA == 1), tb = (opB == 1);
   double ra[SA], rb[SB];
   auto fetch = [&](int k0) {
@@ -225,7 +220,7 @@ gemm_mfma_f64_kernel(int opA, int opB, int M, int N, int K, double alpha,
     for (int s = 0; s < SA; ++s) {
       const int e = tid + NT * s;
       int i, k;
-      if (!ta) { i = e / BKM; k = e % BKM; } else { k = e / BM; i = e % BM; }
+      if (!ta) { i = e / BK; k = e % BK; } else { k = e / BM; i = e % BM; }
       const int gi = m0 + i, gk = k0 + k;
       ra[s] = (gi < M && gk < kend) ? (!ta ? A[(long)gi * lda + gk] : A[(long)gk * lda + gi]) : 0.0;
     }
@@ -233,28 +228,28 @@ gemm_mfma_f64_kernel(int opA, int opB, int M, int N, int K, double alpha,
     for (int s = 0; s < SB; ++s) {
       const int e = tid + NT * s;
       int j, k;
-      if (!tb) { k = e / BN; j = e % BN; } else { j = e / BKM; k = e % BKM; }
+      if (!tb) { k = e / BN; j = e % BN; } else { j = e / BK; k = e % BK; }
       const int gj = n0 + j, gk = k0 + k;
       rb[s] = (gj < N && gk < kend) ? (!tb ? B[(long)gk * ldb + gj] : B[(long)gj * ldb + gk]) : 0.0;
     }
   };
   if (kbeg < kend) fetch(kbeg);
   const int li = lane & 15, lk = lane >> 4;
-  for (int k0 = kbeg; k0 < kend; k0 += BKM) {
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
 #pragma unroll
     for (int s = 0; s < SA; ++s) {
       const int e = tid + NT * s;
-      if (!ta) As[e % BKM][e / BKM] = ra[s]; else As[e / BM][e % BM] = ra[s];
+      if (!ta) As[e % BK][e / BK] = ra[s]; else As[e / BM][e % BM] = ra[s];
     }
 #pragma unroll
     for (int s = 0; s < SB; ++s) {
       const int e = tid + NT * s;
-      if (!tb) Bs[e / BN][e % BN] = rb[s]; else Bs[e % BKM][e / BKM] = rb[s];
+      if (!tb) Bs[e / BN][e % BN] = rb[s]; else Bs[e % BK][e / BK] = rb[s];
     }
     __syncthreads();
-    if (k0 + BKM < kend) fetch(k0 + BKM);
+    if (k0 + BK < kend) fetch(k0 + BK);
 #pragma unroll
-    for (int kk = 0; kk < BKM; kk += 4) {
+    for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + lk;
       const double a0 = As[kr][wr + li], a1 = As[kr][wr + 16 + li];
       const double b0 = Bs[kr][wc + li], b1 = Bs[kr][wc + 16 + li];
