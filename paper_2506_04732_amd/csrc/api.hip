@@ -534,6 +534,9 @@ int t2s2_solve_batched(int count, t2s2_problem* const* probs, const t2s2_tt* con
       if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
           hipStreamWaitEvent(s, ready, 0) != hipSuccess)
         fail = "worker stream set-up failed";
+      // outgrown scratch blocks are freed after the batch, not between the
+      // instances (a hipFree would wait for every other worker's queue)
+      t2s2::defer_scratch_release(true);
       for (int k = next++; k < count; k = next++) {
         const int i = order[k];
         if (!fail.empty()) {
@@ -554,6 +557,7 @@ int t2s2_solve_batched(int count, t2s2_problem* const* probs, const t2s2_tt* con
     for (int w = 0; w < nw; ++w) pool.emplace_back(work);
     for (auto& t : pool) t.join();
     (void)hipEventDestroy(ready);
+    for (int i = 0; i < count; ++i) t2s2::free_retired_scratch(*ps[i]->P);
     // a hard error outranks "not converged"; report the first of the worst
     int worst = T2S2_OK;
     std::string first;

@@ -143,4 +143,12 @@ void lift_rhs(Problem& p, const Ctx& c, const DTT& f, const DTT& g, DTT& b, int 
 // receives the solution; its cores need rank_cap * m * rank_cap doubles.
 int solve(Problem& p, const Ctx& c, const DTT& f, const DTT* x0, const SolveOptions& o, DTT& x, SolveReport& rep);
 
+// Scratch blocks outgrown during a solve are normally freed when the solve
+// ends (or starts) with no side work queued; each hipFree waits for all work
+// on the device.  While concurrent solves run (a batch), the calling thread
+// defers those frees (on = true) so that no solve waits for the others'
+// queues; free_retired_scratch then frees a problem's deferred blocks.
+void defer_scratch_release(bool on);
+void free_retired_scratch(Problem& p);
+
 }  // namespace t2s2

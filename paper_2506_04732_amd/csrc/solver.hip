@@ -1593,7 +1593,17 @@ int mol_step(Problem& p, const Ctx& c, const DTT& u, const DTT* b, const SolveOp
 // when that cannot stall the host behind queued work: before a solve queues
 // anything, and after it if no side stream still runs its eigendecompositions
 // (otherwise at the next solve, or when the problem is destroyed).
+thread_local bool t_defer_release = false;
+
+void defer_scratch_release(bool on) { t_defer_release = on; }
+
+void free_retired_scratch(Problem& p) {
+  p.sc.release_retired();
+  for (int k = 0; k < Problem::kSides; ++k) p.sc_side[k].release_retired();
+}
+
 static void release_scratch(Problem& p, bool only_if_sides_idle) {
+  if (t_defer_release) return;
   bool any = p.sc.has_retired();
   for (int k = 0; k < Problem::kSides; ++k) any = any || p.sc_side[k].has_retired();
   if (!any) return;
@@ -1607,8 +1617,7 @@ static void release_scratch(Problem& p, bool only_if_sides_idle) {
       }
       T2S2_HIP(q);
     }
-  p.sc.release_retired();
-  for (int k = 0; k < Problem::kSides; ++k) p.sc_side[k].release_retired();
+  free_retired_scratch(p);
 }
 
 int solve(Problem& p, const Ctx& c0, const DTT& f, const DTT* x0, const SolveOptions& o, DTT& x, SolveReport& rep) {
