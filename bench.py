@@ -534,7 +534,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs one solve on one GPU; --gpus {args.gpus} is not supported (the solve is a single-GPU "
-              f"workload and this build has no multi-GPU path)", file=sys.stderr)
+              f"workload and the library has no multi-GPU path)", file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
     if args.workload == "batched256":
