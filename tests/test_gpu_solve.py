@@ -17,6 +17,7 @@ from oracle import collocation as col  # noqa: E402
 from oracle import metrics  # noqa: E402
 from oracle import spectral as sp  # noqa: E402
 from oracle import tt as ott  # noqa: E402
+from residual_floor import agreement_bound  # noqa: E402
 
 
 def _say(*a):
@@ -161,3 +162,24 @@ def test_first_solve_on_fresh_problem_equals_later_solves():
         for k in keys[1:]:
             assert k[:3] == keys[0][:3]
             assert all(np.array_equal(a, b) for a, b in zip(k[3], keys[0][3]))
+
+
+def test_7d_n24_warm_start_shape_meets_target_by_oracle_residual():
+    """The learned warm start's shape (7D, N = 24, eps in [1e-4, 1e-2], a
+    12-parameter Gaussian source) solved cold: the oracle's FP64 residual of
+    the returned TT agrees with the library's within what two FP64
+    constructions of the operator can agree on, and meets the 1e-8 target."""
+    q = workloads.warm_instance(10 ** 6 + 7)
+    _say(q.name, f"eps {q.eps:.2e}")
+    p = _gpu_problem(q)
+    f = _gpu_source(p, q)
+    r = p.solve(f, tol=q.tol, target=q.target_residual, max_sweeps=30, kick=8, init_rank=8)
+    ops = col.build_ops(q.d, q.N, q.eps, q.beta, q.scheme)
+    Es, Ms = col.interior_factors(ops)
+    b = ott.separable_to_tt(col.gauss_rhs_factors(ops, q.gauss.amp, q.gauss.centre, q.gauss.width))
+    xs = r.x.to_numpy()
+    rho = ott.residual_norm(ott.kron_sum_ttm(Es, Ms), xs, b)
+    bound = agreement_bound(ops, q.eps, q.beta, Es, Ms, xs, b, rho)
+    _say(f"sweeps {r.sweeps}, ranks {r.ranks}, library {r.residual:.6e}, oracle {rho:.6e}, bound {bound:.1e}")
+    assert abs(rho - r.residual) <= bound
+    assert r.converged and rho <= q.target_residual + bound
